@@ -1,0 +1,45 @@
+"""CPU FP64 oracle for the linearized VHS collision operator.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import anything from this package.
+The GPU library never calls it, links it or falls back to it, and this
+package imports nothing from the GPU library.
+
+Reference: Yin, Cai, Wang, "A fast Fourier spectral method for the
+linearized Boltzmann collision operator" (arXiv 2503.09580).
+
+Modules
+-------
+quadrature   Gauss-Jacobi-Radau rule in the relative speed g (Sec. 2.3,
+             eq. (13); Sec. 4.1) and the hemisphere product rule used by
+             the binary method.
+grid         Collocation grid, index sets and dense DFT matrices (Sec. 2.3).
+fast_direct  O1: the fast linearized method (Sec. 3.2, eqs. (20), (23),
+             (24); Algorithm 1) evaluated with dense DFT matrices and the
+             naive (direct-sum) cyclic convolution for psi_j.
+alg1         Algorithm 1 step by step with a library FFT as the transform
+             primitive (used as the CPU throughput baseline).
+binary       O2: the binary-operator spectral method (Sec. 2.3, eq. (14))
+             with an explicit hemisphere quadrature, evaluated for
+             L_bin[h] = Q(M,h) + Q(h,M).
+projection   Orthogonal projection onto the complement of the collision
+             invariants in the M^{-1}-weighted inner product.
+
+Readings of the paper that the oracle takes where the text is silent or
+inconsistent (each also implemented identically on the GPU side):
+  R2  g-quadrature: Gauss-Jacobi-Radau in x = 2g/R - 1 with weight
+      (1+x)^(4-2*omega), which absorbs g^2 B(g); fixed node g = 0;
+      J = n/2 + 1 nodes (exact to degree n).  Alternative rule 1: weight
+      (1+x)^2 with B(g_j) multiplied in.
+  R3  gain constant: Phi_j(k) = 4 pi^2 W_j s_j(k) together with
+      G = rho (pi theta)^(-3/2) exp(-|v|^2/theta).  Algorithm 1 prints
+      32 pi^2, which with its own M^g normalisation gives a gain term
+      8x too large (pinned by the Maxwell-molecule closed form
+      L+[M] = 2 rho M in the tests).
+  R4  phi_j = iDFT[sigma_j] where sigma_j doubles s_j at each Nyquist
+      index (eq. (24) sums m over -N..N, so +N and -N coincide).
+  R5  the product in eq. (24) is a plain cyclic convolution (no c_k
+      halving of the Nyquist entries).
+  R9  cutoff: r = h/M kept where M/rho >= eps, r = 0 otherwise; the
+      loss term uses the uncut h.
+"""

@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs for the linearized collision operator.
+
+This module only builds input distributions and per-cell Maxwellian
+parameters; it contains none of the operator's arithmetic.  It is the one
+module shared by the GPU tests/benchmark and the CPU oracle tests.  NumPy
+only, FP64.
+
+Grid: n points per axis, v_i = -L + i (2L/n), i = 0..n-1, row-major
+[x][y][z] with z fastest.  Parameters per cell: (rho, u1, u2, u3, theta).
+
+The paper measures on closed-form distributions only (Sec. 4: f^(1), f^(2));
+the configurations below are synthetic stand-ins of the same kind:
+  C1  n=16, L=8,  omega=0.5,  1 cell, M=(1,0,1), h = M p(v)
+  C2  n=32, L=8,  omega=0.74, 64 cells, M=(1,0,1), h = f_b - M with f_b a
+      drifting anisotropic (bi-)Maxwellian; also Burnett functions (omega=1)
+  C3  n=32, L=8,  omega=0.74, 4096 cells along a 1-D grid with sinusoidal
+      rho, u, theta (amplitude 0.2), h_i = M_i p_i((v-u_i)/sqrt(theta_i))
+  C5  n=64, L=10, omega=0.74, 512 cells, rho=1, u=0, theta log-uniform in
+      [0.5, 2], h_i = M_i p_i(v/sqrt(theta_i))
+p is a polynomial of total degree <= 4 (35 monomials) with coefficients
+drawn N(0, 0.1^2).
+"""
+import math
+
+import numpy as np
+
+CONFIGS = {
+    "C1": dict(n=16, L=8.0, omega=0.5, batch=1, seed=101),
+    "C2": dict(n=32, L=8.0, omega=0.74, batch=64, seed=202),
+    "C3": dict(n=32, L=8.0, omega=0.74, batch=4096, seed=303),
+    "C5": dict(n=64, L=10.0, omega=0.74, batch=512, seed=505),
+}
+
+MONOMIALS = [(a, b, c) for a in range(5) for b in range(5) for c in range(5) if a + b + c <= 4]
+
+
+def axis(n, L):
+    return -L + np.arange(n) * (2.0 * L / n)
+
+
+def maxwellian(n, L, rho, u, theta):
+    """rho (2 pi theta)^-3/2 exp(-|v-u|^2/(2 theta)) on the grid (input
+    construction only)."""
+    v = axis(n, L)
+    ex = np.exp(-(v - u[0]) ** 2 / (2.0 * theta))
+    ey = np.exp(-(v - u[1]) ** 2 / (2.0 * theta))
+    ez = np.exp(-(v - u[2]) ** 2 / (2.0 * theta))
+    return rho * (2.0 * math.pi * theta) ** -1.5 * ex[:, None, None] * ey[None, :, None] * ez[None, None, :]
+
+
+def poly_eval(n, L, coeffs, shift=(0.0, 0.0, 0.0), scale=1.0):
+    """sum_abc c_abc w1^a w2^b w3^c with w = (v - shift) / scale."""
+    v = axis(n, L)
+    w = [(v - shift[d]) / scale for d in range(3)]
+    pw = [np.stack([wd ** e for e in range(5)]) for wd in w]
+    out = np.zeros((n, n, n))
+    for c, (a, b, e) in zip(coeffs, MONOMIALS):
+        out += c * pw[0][a][:, None, None] * pw[1][b][None, :, None] * pw[2][e][None, None, :]
+    return out
+
+
+def poly_coeffs(rng, std=0.1):
+    return rng.normal(0.0, std, size=len(MONOMIALS))
+
+
+def bimaxwellian(n, L, tau, u):
+    """Unit-density anisotropic Maxwellian with T_par = tau T_perp along e1,
+    trace temperature 1, drift u."""
+    tperp = 3.0 / (2.0 + tau)
+    tpar = tau * tperp
+    v = axis(n, L)
+    ex = np.exp(-(v - u[0]) ** 2 / (2.0 * tpar))
+    ey = np.exp(-(v - u[1]) ** 2 / (2.0 * tperp))
+    ez = np.exp(-(v - u[2]) ** 2 / (2.0 * tperp))
+    pre = (2.0 * math.pi) ** -1.5 / math.sqrt(tpar * tperp * tperp)
+    return pre * ex[:, None, None] * ey[None, :, None] * ez[None, None, :]
+
+
+def _ball(rng, radius):
+    while True:
+        u = rng.uniform(-radius, radius, size=3)
+        if u @ u <= radius * radius:
+            return u
+
+
+def c1(seed=101):
+    cfg = CONFIGS["C1"]
+    n, L = cfg["n"], cfg["L"]
+    rng = np.random.default_rng(seed)
+    M = maxwellian(n, L, 1.0, (0, 0, 0), 1.0)
+    h = M * poly_eval(n, L, poly_coeffs(rng))
+    params = np.array([[1.0, 0.0, 0.0, 0.0, 1.0]])
+    return h[None], params
+
+
+def c2(batch=64, seed=202, n=32, L=8.0):
+    rng = np.random.default_rng(seed)
+    M = maxwellian(n, L, 1.0, (0, 0, 0), 1.0)
+    h = np.empty((batch, n, n, n))
+    for b in range(batch):
+        tau = rng.uniform(0.8, 1.25)
+        u = _ball(rng, 0.3)
+        h[b] = bimaxwellian(n, L, tau, u) - M
+    params = np.array([[1.0, 0.0, 0.0, 0.0, 1.0]])
+    return h, params
+
+
+def c3_params(batch=4096, seed=303):
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=5)        # rho, u1, u2, u3, theta
+    x = (np.arange(batch) + 0.5) / batch
+    p = np.empty((batch, 5))
+    p[:, 0] = 1.0 + 0.2 * np.sin(2 * math.pi * x + ph[0])
+    for d in range(3):
+        p[:, 1 + d] = 0.2 * np.sin(2 * math.pi * x + ph[1 + d])
+    p[:, 4] = 1.0 + 0.2 * np.sin(2 * math.pi * x + ph[4])
+    return p, rng
+
+
+def c3(batch=4096, seed=303, n=32, L=8.0, cells=None):
+    """Returns (h[len(cells)], params[len(cells)]); `cells` selects a subset
+    of the full batch (default: all) without changing any cell's data."""
+    p, rng = c3_params(batch, seed)
+    coeffs = np.stack([poly_coeffs(rng) for _ in range(batch)])
+    cells = np.arange(batch) if cells is None else np.asarray(cells, dtype=np.int64)
+    h = np.empty((len(cells), n, n, n))
+    for i, c in enumerate(cells):
+        rho, u, th = p[c, 0], p[c, 1:4], p[c, 4]
+        h[i] = maxwellian(n, L, rho, u, th) * poly_eval(n, L, coeffs[c], u, math.sqrt(th))
+    return h, p[cells].copy()
+
+
+def c5(batch=512, seed=505, n=64, L=10.0, cells=None):
+    rng = np.random.default_rng(seed)
+    th = np.exp(rng.uniform(math.log(0.5), math.log(2.0), size=batch))
+    coeffs = np.stack([poly_coeffs(rng) for _ in range(batch)])
+    p = np.zeros((batch, 5))
+    p[:, 0] = 1.0
+    p[:, 4] = th
+    cells = np.arange(batch) if cells is None else np.asarray(cells, dtype=np.int64)
+    h = np.empty((len(cells), n, n, n))
+    for i, c in enumerate(cells):
+        h[i] = maxwellian(n, L, 1.0, (0, 0, 0), th[c]) * poly_eval(n, L, coeffs[c], (0, 0, 0), math.sqrt(th[c]))
+    return h, p[cells].copy()
+
+
+def invariant_inputs(n, L, rho=1.0, u=(0.0, 0.0, 0.0), theta=1.0):
+    """[5, n, n, n]: M, v1 M, v2 M, v3 M, |v|^2 M."""
+    v = axis(n, L)
+    VX, VY, VZ = np.meshgrid(v, v, v, indexing="ij")
+    M = maxwellian(n, L, rho, u, theta)
+    return np.stack([M, VX * M, VY * M, VZ * M, (VX ** 2 + VY ** 2 + VZ ** 2) * M])
+
+
+BURNETT_NL = [(0, 0), (0, 1), (1, 0), (0, 2), (1, 1), (2, 0), (0, 3), (1, 2), (0, 4)]
+
+
+def burnett(n, L, nn, l):
+    """h_nl = M(v) L_n^(l+1/2)(|v|^2/2) |v|^l P_l(v3/|v|) for the unit
+    Maxwellian (the m = 0 Burnett functions)."""
+    from scipy.special import eval_genlaguerre, eval_legendre
+    v = axis(n, L)
+    VX, VY, VZ = np.meshgrid(v, v, v, indexing="ij")
+    r2 = VX ** 2 + VY ** 2 + VZ ** 2
+    r = np.sqrt(r2)
+    c = np.where(r > 0, VZ / np.where(r > 0, r, 1.0), 0.0)
+    rad = eval_genlaguerre(nn, l + 0.5, r2 / 2.0) * r ** l
+    ang = eval_legendre(l, c) if l > 0 else np.ones_like(c)
+    return maxwellian(n, L, 1.0, (0, 0, 0), 1.0) * rad * ang
