@@ -1,0 +1,141 @@
+/*
+ * lincoll: the linearized Boltzmann collision operator for VHS gases by the
+ * fast Fourier spectral method of Yin, Cai and Wang (arXiv 2503.09580),
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Operator (Sec. 2.1, eq. (5)):  L[h] = Q(M,h) + Q(h,M)  about a Maxwellian
+ *   M(v) = rho (2 pi theta)^(-3/2) exp(-|v-u|^2 / (2 theta)),
+ * VHS kernel B(g) = C g^(2(1-omega)) (eq. (4)), truncated at g <= R.
+ * Discretisation (Sec. 2.3, Sec. 3.2 eqs. (20), (23), (24), Algorithm 1):
+ * n points per velocity axis on the periodic box [-L, L)^3,
+ *   v_i = -L + i * 2L/n,  i = 0..n-1,
+ * g-quadrature by a Jacobi-Gauss-Radau rule with J = n/2 + 1 nodes, and the
+ * cutoff r = h/M only where M/rho >= eps (eq. (25)).  Each application costs
+ * O(J n^3 log n) with no sum over sphere points.
+ *
+ * Conventions shared by every entry point
+ *   - Arrays h, out, x are device memory, row-major [batch][n][n][n]
+ *     (last index fastest, index i <-> velocity -L + i*2L/n).  Element type
+ *     is double for LINCOLL_F64 and float for LINCOLL_F32 / LINCOLL_BF16X3.
+ *   - Maxwellian parameters are device memory, double [batch][5] holding
+ *     (rho, u1, u2, u3, theta) per cell, rho > 0, theta > 0.
+ *   - The caller owns h, out, x and the parameter array; the plan owns all
+ *     tables, per-cell caches and scratch, and frees them in lincoll_destroy.
+ *   - Every call is asynchronous on the plan's stream (lincoll_set_stream;
+ *     the null stream until set).  Completion follows stream order.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ *   - Functions return LINCOLL_OK (0) or a negative status; nothing throws
+ *     across this interface.  Argument checks happen on the host before any
+ *     device work is enqueued.
+ */
+#ifndef LINCOLL_H
+#define LINCOLL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LINCOLL_OK 0
+#define LINCOLL_EINVAL -1    /* bad argument: n, L, omega, dtype, batch, null or aliased pointer */
+#define LINCOLL_ENOMEM -2    /* device allocation failed */
+#define LINCOLL_EHIP -3      /* a HIP runtime call failed (lincoll_get_info LINCOLL_INFO_HIP_ERROR) */
+#define LINCOLL_ENOTREADY -4 /* batch does not match the Maxwellians set (neither 1 nor batch) */
+#define LINCOLL_ENOTIMPL -5  /* operation not provided by this build */
+
+typedef struct lincoll_plan_s* lincoll_plan_t;
+
+typedef enum {
+  LINCOLL_F64 = 0,   /* every step in double */
+  LINCOLL_F32 = 1,   /* transforms and mode products in float; setup, mask and projection in double */
+  LINCOLL_BF16X3 = 2 /* as F32, with the per-axis DFT stages of the gain loop as split-bf16 MFMA products */
+} lincoll_dtype_t;
+
+typedef enum {
+  LINCOLL_PATH_AUTO = 0,    /* fused kernel where it exists, otherwise the staged kernels */
+  LINCOLL_PATH_STAGED = 1,  /* batched per-stage kernels (every n and dtype) */
+  LINCOLL_PATH_FUSED = 2    /* one persistent workgroup per cell (F32/BF16X3 at n = 16, 32) */
+} lincoll_path_t;
+
+typedef struct {
+  int n;            /* points per velocity axis (the paper's 2N): 8, 16, 32 (F64) or 8..64 (F32) */
+  double L;         /* half-width of the periodic velocity box, > 0 */
+  double omega;     /* VHS viscosity index, 1/2 <= omega <= 1 (eq. (4)) */
+  double C;         /* kernel constant of B(g) = C g^(2(1-omega)); default 1/(4 pi) (eq. (26)) */
+  double R;         /* kernel cutoff; <= 0 selects 4L/(3+sqrt 2), the largest de-aliased value (Sec. 2.3) */
+  int J;            /* g-quadrature nodes; <= 0 selects n/2 + 1 (exact to degree n, Sec. 4.1) */
+  double eps;       /* cutoff of eq. (25); default 1e-9; 0 disables it */
+  int quad_rule;    /* 0: Radau weight (1+x)^(4-2 omega) absorbs g^2 B(g); 1: weight (1+x)^2 times B(g_j) */
+  int project;      /* 1: lincoll_apply returns P L P (exact conservation), see lincoll_project */
+  int max_batch;    /* upper bound on batch accepted by apply (0: unbounded) */
+  int dtype;        /* lincoll_dtype_t */
+  int path;         /* lincoll_path_t */
+} lincoll_params_t;
+
+/* Fills *p with the defaults above for (n, L, omega, dtype). */
+void lincoll_params_default(lincoll_params_t* p, int n, double L_domain, double vhs_omega, int dtype);
+
+/* Creates a plan: host FP64 precomputation of Algorithm 1 (quadrature, the
+ * kernel-mode tables s_j, Phi_j, Omega and phi_j = iDFT[s_j]), upload, and the
+ * default Maxwellian (rho, u, theta) = (1, 0, 1) for one cell.  Synchronous. */
+int lincoll_plan(int n, double L_domain, double vhs_omega, int dtype, lincoll_plan_t* out);
+int lincoll_plan_ex(const lincoll_params_t* p, lincoll_plan_t* out);
+
+/* Sets the HIP stream (a hipStream_t passed as void*) for all later calls. */
+int lincoll_set_stream(lincoll_plan_t plan, void* hip_stream);
+
+/* Per-cell Maxwellians (Algorithm 1, first loop; Sec. 5.2 uses one local
+ * Maxwellian per spatial cell).  params: device double [batch][5].  Computes
+ * in FP64 on the device: the cutoff mask, the kernel modes
+ * K_j = DFT[G phi_j] with G = rho (pi theta)^(-3/2) exp(-|v|^2/theta) (eq. (24)),
+ * nu = iDFT[Omega DFT[M]] (eq. (20)) and the invariant Gram matrix.  batch = 1
+ * is broadcast to every cell of a later apply.  Asynchronous. */
+int lincoll_set_maxwellians(lincoll_plan_t plan, const double* params, int batch);
+
+/* out[b] = L[h[b]] about Maxwellian b (or the broadcast one) for b < batch
+ * (eq. (20) + eq. (23), Algorithm 1).  h and out must not overlap.
+ * batch must equal the Maxwellian batch or the Maxwellian batch must be 1. */
+int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
+
+/* y[b] = P x[b]: removes the collision-invariant part in the inner product
+ * <a,b> = sum a b / M, i.e. y = x - M sum_a phi_a (A^-1 m[x])_a with
+ * phi_a in {1, v1, v2, v3, |v|^2}, A_ab = sum M phi_a phi_b, m_a = sum x phi_a.
+ * Then sum y phi_a = 0 and P(phi_a M) = 0.  Reductions in FP64 for every
+ * dtype.  x == y is allowed. */
+int lincoll_project(lincoll_plan_t plan, const void* x, void* y, int batch);
+
+/* Binary operator Q(f,f) of eq. (14) with a hemisphere rule; not provided
+ * by this build: returns LINCOLL_ENOTIMPL. */
+int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
+
+#define LINCOLL_INFO_N 0
+#define LINCOLL_INFO_J 1
+#define LINCOLL_INFO_R 2
+#define LINCOLL_INFO_DTYPE 3
+#define LINCOLL_INFO_PATH 4          /* path the next apply uses (lincoll_path_t) */
+#define LINCOLL_INFO_MAXW_BATCH 5    /* batch of the Maxwellians currently set */
+#define LINCOLL_INFO_DEVICE_BYTES 6  /* device memory held by the plan */
+#define LINCOLL_INFO_HIP_ERROR 7     /* last hipError_t seen (0 if none) */
+#define LINCOLL_INFO_EPS 8
+/* Reads one plan property into *val. */
+int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
+
+/* Releases everything the plan owns (waits for its stream first). */
+void lincoll_destroy(lincoll_plan_t plan);
+
+/* Static string for a status code. */
+const char* lincoll_strerror(int status);
+
+#define LINCOLL_TABLE_G 0      /* g_j, [J] */
+#define LINCOLL_TABLE_W 1      /* W_j = w_j^g B(g_j), [J] */
+#define LINCOLL_TABLE_PHI 2    /* Phi_j(q) = 4 pi^2 W_j sinc(pi g_j sqrt(q)/(2L)), [J][3(n/2)^2+1], q = |k|^2 */
+#define LINCOLL_TABLE_OMEGA 3  /* Omega(q) = 16 pi^2 sum_j W_j sinc(pi g_j sqrt(q)/L), [3(n/2)^2+1] */
+#define LINCOLL_TABLE_PHIJ 4   /* phi_j(|d1|,|d2|,|d3|) = iDFT[sigma_j], octant [J][n/2+1]^3 */
+/* Host-only (no device is touched): writes `count` doubles of one
+ * precomputed table for the parameters *p into out.  Returns the table's
+ * element count, or a negative status (count too small, bad parameters). */
+long long lincoll_plan_tables(const lincoll_params_t* p, int table, double* out, long long count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LINCOLL_H */

@@ -1,0 +1,436 @@
+// C ABI of liblincoll (declared in include/lincoll.h): argument checks,
+// plan ownership, table upload and launch orchestration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lincoll.h"
+#include "host_tables.h"
+#include "internal.h"
+
+using namespace lincoll;
+
+namespace lincoll {
+bool fused_supported(int n, int dtype);
+hipError_t fused_apply(const ApplyCtx& c);
+}  // namespace lincoll
+
+struct lincoll_plan_s {
+  lincoll_params_t p{};
+  HostTables t;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int last_hip = 0;
+  size_t bytes = 0;
+  // plan tables
+  void* d_Phi = nullptr;      // [J][Q] apply dtype, / n^3
+  void* d_Om = nullptr;       // [Q]    apply dtype, / n^3
+  double* d_Om64 = nullptr;   // [Q]    FP64, / n^3
+  double* d_phi = nullptr;    // [J][P^3]
+  double* d_Cdct = nullptr;   // [P][P]
+  // per-cell cache
+  int Bc = 0, cap_cells = 0;
+  double* d_params = nullptr;
+  double* d_fac64 = nullptr;
+  double* d_pref64 = nullptr;
+  double* d_gfac64 = nullptr;
+  double* d_Ainv = nullptr;
+  void* d_facT = nullptr;
+  void* d_prefT = nullptr;
+  uint32_t* d_mask = nullptr;
+  void* d_Kh = nullptr;
+  void* d_nu = nullptr;
+  // setup scratch
+  int setup_chunk = 0;
+  double* d_tmpA = nullptr;
+  double* d_tmpB = nullptr;
+  double* d_planes64 = nullptr;
+  // apply work
+  int cap_work = 0, cap_pin = 0;
+  void* d_R = nullptr;
+  void* d_H = nullptr;
+  void* d_W = nullptr;
+  void* d_Lp = nullptr;
+  void* d_pin = nullptr;      // projected input when p.project
+};
+
+namespace {
+
+size_t esize(int dtype) { return dtype == LINCOLL_F64 ? sizeof(double) : sizeof(float); }
+
+int hip_fail(lincoll_plan_t pl, hipError_t e) {
+  if (pl) pl->last_hip = (int)e;
+  return e == hipErrorOutOfMemory ? LINCOLL_ENOMEM : LINCOLL_EHIP;
+}
+
+template <typename P>
+hipError_t dalloc(lincoll_plan_t pl, P** ptr, size_t bytes) {
+  if (*ptr) {
+    (void)hipFree(*ptr);
+    *ptr = nullptr;
+  }
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, bytes);
+  if (e == hipSuccess) {
+    *ptr = static_cast<P*>(v);
+    pl->bytes += bytes;
+  }
+  return e;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int validate(const lincoll_params_t* p) {
+  if (!p) return LINCOLL_EINVAL;
+  if (p->dtype != LINCOLL_F64 && p->dtype != LINCOLL_F32 && p->dtype != LINCOLL_BF16X3) return LINCOLL_EINVAL;
+  if (!(p->n == 8 || p->n == 16 || p->n == 32)) return LINCOLL_EINVAL;
+  if (!(p->L > 0.0) || !std::isfinite(p->L)) return LINCOLL_EINVAL;
+  if (!(p->omega >= 0.5 && p->omega <= 1.0)) return LINCOLL_EINVAL;
+  if (!(p->C > 0.0) || !std::isfinite(p->C)) return LINCOLL_EINVAL;
+  if (!std::isfinite(p->R)) return LINCOLL_EINVAL;
+  if (p->J < 0 || p->J > 256) return LINCOLL_EINVAL;
+  if (!(p->eps >= 0.0) || !(p->eps < 1.0)) return LINCOLL_EINVAL;
+  if (p->quad_rule != 0 && p->quad_rule != 1) return LINCOLL_EINVAL;
+  if (p->project != 0 && p->project != 1) return LINCOLL_EINVAL;
+  if (p->max_batch < 0) return LINCOLL_EINVAL;
+  if (p->path < 0 || p->path > 2) return LINCOLL_EINVAL;
+  if (p->path == LINCOLL_PATH_FUSED && !fused_supported(p->n, p->dtype)) return LINCOLL_EINVAL;
+  if (p->dtype == LINCOLL_BF16X3 && !fused_supported(p->n, p->dtype)) return LINCOLL_EINVAL;
+  return LINCOLL_OK;
+}
+
+lincoll_params_t resolved(const lincoll_params_t* in) {
+  lincoll_params_t p = *in;
+  if (p.R <= 0.0) p.R = 4.0 * p.L / (3.0 + std::sqrt(2.0));
+  if (p.J <= 0) p.J = p.n / 2 + 1;
+  return p;
+}
+
+bool use_fused(const lincoll_plan_s* pl) {
+  if (pl->p.path == LINCOLL_PATH_STAGED) return false;
+  if (pl->p.path == LINCOLL_PATH_FUSED) return true;
+  return fused_supported(pl->p.n, pl->p.dtype);
+}
+
+int ensure_cells(lincoll_plan_t pl, int B) {
+  if (B <= pl->cap_cells) return LINCOLL_OK;
+  const int n = pl->p.n, P = n / 2 + 1, J = pl->t.J, MW = (n + 31) / 32;
+  const size_t n3 = (size_t)n * n * n, P3 = (size_t)P * P * P, es = esize(pl->p.dtype);
+  hipError_t e;
+  if ((e = dalloc(pl, &pl->d_params, (size_t)B * 5 * sizeof(double))) ||
+      (e = dalloc(pl, &pl->d_fac64, (size_t)B * 6 * n * sizeof(double))) ||
+      (e = dalloc(pl, &pl->d_pref64, (size_t)B * 2 * sizeof(double))) ||
+      (e = dalloc(pl, &pl->d_gfac64, (size_t)B * P * sizeof(double))) ||
+      (e = dalloc(pl, &pl->d_Ainv, (size_t)B * 25 * sizeof(double))) ||
+      (e = dalloc(pl, &pl->d_facT, (size_t)B * 6 * n * es)) || (e = dalloc(pl, &pl->d_prefT, (size_t)B * 2 * es)) ||
+      (e = dalloc(pl, &pl->d_mask, (size_t)B * n * n * MW * sizeof(uint32_t))) ||
+      (e = dalloc(pl, &pl->d_Kh, (size_t)B * J * P3 * es)) || (e = dalloc(pl, &pl->d_nu, (size_t)B * n3 * es)))
+    return hip_fail(pl, e);
+  pl->cap_cells = B;
+  // setup scratch: chunks of cells bounded to ~256 MiB per buffer
+  const size_t per_cell = (size_t)J * P3 * sizeof(double);
+  int chunk = (int)std::max<size_t>(1, (size_t)(256u << 20) / per_cell);
+  if (chunk > B) chunk = B;
+  if (chunk > pl->setup_chunk) {
+    if ((e = dalloc(pl, &pl->d_tmpA, (size_t)chunk * per_cell)) || (e = dalloc(pl, &pl->d_tmpB, (size_t)chunk * per_cell)) ||
+        (e = dalloc(pl, &pl->d_planes64, (size_t)chunk * P * n * n * 2 * sizeof(double))))
+      return hip_fail(pl, e);
+    pl->setup_chunk = chunk;
+  }
+  return LINCOLL_OK;
+}
+
+int ensure_work(lincoll_plan_t pl, int B) {
+  const int n = pl->p.n, P = n / 2 + 1;
+  const size_t es = esize(pl->p.dtype);
+  hipError_t e;
+  if (pl->p.project && B > pl->cap_pin) {
+    if ((e = dalloc(pl, &pl->d_pin, (size_t)B * n * n * n * es))) return hip_fail(pl, e);
+    pl->cap_pin = B;
+  }
+  if (use_fused(pl)) return LINCOLL_OK;
+  if (B <= pl->cap_work && pl->d_R) return LINCOLL_OK;
+  const size_t vol = (size_t)B * P * n * n * 2 * es;
+  if ((e = dalloc(pl, &pl->d_R, vol)) || (e = dalloc(pl, &pl->d_H, vol)) || (e = dalloc(pl, &pl->d_W, vol)) ||
+      (e = dalloc(pl, &pl->d_Lp, vol)))
+    return hip_fail(pl, e);
+  pl->cap_work = B;
+  return LINCOLL_OK;
+}
+
+int do_set_maxwellians(lincoll_plan_t pl, const double* params, int batch) {
+  int st = ensure_cells(pl, batch);
+  if (st) return st;
+  hipError_t e = hipMemcpyAsync(pl->d_params, params, (size_t)batch * 5 * sizeof(double), hipMemcpyDeviceToDevice,
+                                pl->stream);
+  if (e) return hip_fail(pl, e);
+  SetupCtx c;
+  c.n = pl->p.n;
+  c.J = pl->t.J;
+  c.Q = pl->t.Q;
+  c.Bc = batch;
+  c.dtype = pl->p.dtype;
+  c.L = pl->p.L;
+  c.eps = pl->p.eps;
+  c.stream = pl->stream;
+  c.params = pl->d_params;
+  c.phi = pl->d_phi;
+  c.Cdct = pl->d_Cdct;
+  c.Om64 = pl->d_Om64;
+  c.fac64 = pl->d_fac64;
+  c.pref64 = pl->d_pref64;
+  c.gfac64 = pl->d_gfac64;
+  c.Ainv = pl->d_Ainv;
+  c.facT = pl->p.dtype == LINCOLL_F64 ? (void*)pl->d_fac64 : pl->d_facT;
+  c.prefT = pl->p.dtype == LINCOLL_F64 ? (void*)pl->d_pref64 : pl->d_prefT;
+  c.mask = pl->d_mask;
+  c.Kh = pl->d_Kh;
+  c.nu = pl->d_nu;
+  c.tmpA = pl->d_tmpA;
+  c.tmpB = pl->d_tmpB;
+  c.planes64 = pl->d_planes64;
+  c.chunk = pl->setup_chunk;
+  e = setup_cells(c);
+  if (e) return hip_fail(pl, e);
+  pl->Bc = batch;
+  return LINCOLL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lincoll_params_default(lincoll_params_t* p, int n, double L_domain, double vhs_omega, int dtype) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n = n;
+  p->L = L_domain;
+  p->omega = vhs_omega;
+  p->C = 1.0 / (4.0 * M_PI);
+  p->R = 0.0;
+  p->J = 0;
+  p->eps = 1e-9;
+  p->quad_rule = 0;
+  p->project = 0;
+  p->max_batch = 0;
+  p->dtype = dtype;
+  p->path = LINCOLL_PATH_AUTO;
+}
+
+const char* lincoll_strerror(int s) {
+  switch (s) {
+    case LINCOLL_OK: return "success";
+    case LINCOLL_EINVAL: return "invalid argument";
+    case LINCOLL_ENOMEM: return "device out of memory";
+    case LINCOLL_EHIP: return "HIP runtime error";
+    case LINCOLL_ENOTREADY: return "Maxwellians not set for this batch";
+    case LINCOLL_ENOTIMPL: return "not implemented";
+  }
+  return "unknown status";
+}
+
+long long lincoll_plan_tables(const lincoll_params_t* pin, int table, double* out, long long count) {
+  if (!pin) return LINCOLL_EINVAL;
+  lincoll_params_t q = *pin;
+  if (q.path == LINCOLL_PATH_FUSED || q.dtype == LINCOLL_BF16X3) q.path = LINCOLL_PATH_STAGED, q.dtype = LINCOLL_F32;
+  if (validate(&q)) return LINCOLL_EINVAL;
+  const lincoll_params_t p = resolved(pin);
+  HostTables t;
+  TableParams tp{p.n, p.L, p.omega, p.C, p.R, p.J, p.quad_rule};
+  if (!build_tables(tp, t)) return LINCOLL_EINVAL;
+  const std::vector<double>* v = nullptr;
+  switch (table) {
+    case LINCOLL_TABLE_G: v = &t.g; break;
+    case LINCOLL_TABLE_W: v = &t.W; break;
+    case LINCOLL_TABLE_PHI: v = &t.Phi; break;
+    case LINCOLL_TABLE_OMEGA: v = &t.Omega; break;
+    case LINCOLL_TABLE_PHIJ: v = &t.phi; break;
+    default: return LINCOLL_EINVAL;
+  }
+  const long long need = (long long)v->size();
+  if (out) {
+    if (count < need) return LINCOLL_EINVAL;
+    std::memcpy(out, v->data(), (size_t)need * sizeof(double));
+  }
+  return need;
+}
+
+int lincoll_plan_ex(const lincoll_params_t* pin, lincoll_plan_t* out) {
+  if (!out) return LINCOLL_EINVAL;
+  *out = nullptr;
+  int st = validate(pin);
+  if (st) return st;
+  lincoll_plan_t pl = new (std::nothrow) lincoll_plan_s();
+  if (!pl) return LINCOLL_ENOMEM;
+  pl->p = resolved(pin);
+  TableParams tp{pl->p.n, pl->p.L, pl->p.omega, pl->p.C, pl->p.R, pl->p.J, pl->p.quad_rule};
+  if (!build_tables(tp, pl->t)) {
+    delete pl;
+    return LINCOLL_EINVAL;
+  }
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e) {
+    pl->last_hip = (int)e;
+    delete pl;
+    return LINCOLL_EHIP;
+  }
+  const int n = pl->p.n, P = n / 2 + 1, J = pl->t.J, Q = pl->t.Q;
+  const double s3 = 1.0 / ((double)n * n * n);
+  std::vector<double> phis(pl->t.Phi), oms(pl->t.Omega);
+  for (auto& v : phis) v *= s3;
+  for (auto& v : oms) v *= s3;
+  const size_t es = esize(pl->p.dtype);
+  auto upload = [&](void* dst, const std::vector<double>& src, bool asf) -> hipError_t {
+    if (!asf) return hipMemcpy(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice);
+    std::vector<float> f(src.begin(), src.end());
+    return hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+  };
+  const bool asf = pl->p.dtype != LINCOLL_F64;
+  if ((e = dalloc(pl, &pl->d_Phi, (size_t)J * Q * es)) || (e = dalloc(pl, &pl->d_Om, (size_t)Q * es)) ||
+      (e = dalloc(pl, &pl->d_Om64, (size_t)Q * sizeof(double))) ||
+      (e = dalloc(pl, &pl->d_phi, (size_t)J * P * P * P * sizeof(double))) ||
+      (e = dalloc(pl, &pl->d_Cdct, (size_t)P * P * sizeof(double))) || (e = upload(pl->d_Phi, phis, asf)) ||
+      (e = upload(pl->d_Om, oms, asf)) || (e = upload(pl->d_Om64, oms, false)) ||
+      (e = upload(pl->d_phi, pl->t.phi, false)) || (e = upload(pl->d_Cdct, pl->t.Cdct, false))) {
+    int rc = hip_fail(pl, e);
+    lincoll_destroy(pl);
+    return rc;
+  }
+  // default Maxwellian (1, 0, 1)
+  double* dpar = nullptr;
+  const double def[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  if ((e = hipMalloc(&dpar, sizeof(def))) || (e = hipMemcpy(dpar, def, sizeof(def), hipMemcpyHostToDevice))) {
+    dfree(dpar);
+    int rc = hip_fail(pl, e);
+    lincoll_destroy(pl);
+    return rc;
+  }
+  st = do_set_maxwellians(pl, dpar, 1);
+  if (!st && (e = hipStreamSynchronize(pl->stream))) st = hip_fail(pl, e);
+  dfree(dpar);
+  if (st) {
+    lincoll_destroy(pl);
+    return st;
+  }
+  *out = pl;
+  return LINCOLL_OK;
+}
+
+int lincoll_plan(int n, double L_domain, double vhs_omega, int dtype, lincoll_plan_t* out) {
+  lincoll_params_t p;
+  lincoll_params_default(&p, n, L_domain, vhs_omega, dtype);
+  return lincoll_plan_ex(&p, out);
+}
+
+int lincoll_set_stream(lincoll_plan_t pl, void* s) {
+  if (!pl) return LINCOLL_EINVAL;
+  pl->stream = static_cast<hipStream_t>(s);
+  return LINCOLL_OK;
+}
+
+int lincoll_set_maxwellians(lincoll_plan_t pl, const double* params, int batch) {
+  if (!pl || !params || batch < 1) return LINCOLL_EINVAL;
+  if (pl->p.max_batch > 0 && batch > pl->p.max_batch) return LINCOLL_EINVAL;
+  return do_set_maxwellians(pl, params, batch);
+}
+
+int lincoll_project(lincoll_plan_t pl, const void* x, void* y, int batch) {
+  if (!pl || !x || !y || batch < 1) return LINCOLL_EINVAL;
+  if (pl->Bc != 1 && pl->Bc != batch) return LINCOLL_ENOTREADY;
+  ProjectCtx c;
+  c.n = pl->p.n;
+  c.batch = batch;
+  c.Bc = pl->Bc;
+  c.dtype = pl->p.dtype == LINCOLL_F64 ? 0 : 1;
+  c.L = pl->p.L;
+  c.stream = pl->stream;
+  c.x = x;
+  c.y = y;
+  c.fac64 = pl->d_fac64;
+  c.pref64 = pl->d_pref64;
+  c.Ainv = pl->d_Ainv;
+  hipError_t e = project_cells(c);
+  return e ? hip_fail(pl, e) : LINCOLL_OK;
+}
+
+int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
+  if (!pl || !h || !out || batch < 1) return LINCOLL_EINVAL;
+  if (pl->p.max_batch > 0 && batch > pl->p.max_batch) return LINCOLL_EINVAL;
+  const size_t bytes = (size_t)batch * pl->p.n * pl->p.n * pl->p.n * esize(pl->p.dtype);
+  const char* a = static_cast<const char*>(h);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return LINCOLL_EINVAL;   // overlap
+  if (pl->Bc != 1 && pl->Bc != batch) return LINCOLL_ENOTREADY;
+  int st = ensure_work(pl, batch);
+  if (st) return st;
+  const void* hin = h;
+  if (pl->p.project) {
+    st = lincoll_project(pl, h, pl->d_pin, batch);
+    if (st) return st;
+    hin = pl->d_pin;
+  }
+  ApplyCtx c;
+  c.n = pl->p.n;
+  c.J = pl->t.J;
+  c.Q = pl->t.Q;
+  c.batch = batch;
+  c.Bc = pl->Bc;
+  c.dtype = pl->p.dtype;
+  c.stream = pl->stream;
+  c.h = hin;
+  c.out = out;
+  c.Phi = pl->d_Phi;
+  c.Om = pl->d_Om;
+  c.fac = pl->p.dtype == LINCOLL_F64 ? (const void*)pl->d_fac64 : pl->d_facT;
+  c.pref = pl->p.dtype == LINCOLL_F64 ? (const void*)pl->d_pref64 : pl->d_prefT;
+  c.mask = pl->d_mask;
+  c.Kh = pl->d_Kh;
+  c.nu = pl->d_nu;
+  c.R = pl->d_R;
+  c.H = pl->d_H;
+  c.W = pl->d_W;
+  c.Lp = pl->d_Lp;
+  hipError_t e = use_fused(pl) ? fused_apply(c) : staged_apply(c);
+  if (e) return hip_fail(pl, e);
+  if (pl->p.project) return lincoll_project(pl, out, out, batch);
+  return LINCOLL_OK;
+}
+
+int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
+  if (!pl || !f || !out || batch < 1) return LINCOLL_EINVAL;
+  return LINCOLL_ENOTIMPL;
+}
+
+int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
+  if (!pl || !val) return LINCOLL_EINVAL;
+  switch (key) {
+    case LINCOLL_INFO_N: *val = pl->p.n; break;
+    case LINCOLL_INFO_J: *val = pl->t.J; break;
+    case LINCOLL_INFO_R: *val = pl->p.R; break;
+    case LINCOLL_INFO_DTYPE: *val = pl->p.dtype; break;
+    case LINCOLL_INFO_PATH: *val = use_fused(pl) ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED; break;
+    case LINCOLL_INFO_MAXW_BATCH: *val = pl->Bc; break;
+    case LINCOLL_INFO_DEVICE_BYTES: *val = (double)pl->bytes; break;
+    case LINCOLL_INFO_HIP_ERROR: *val = pl->last_hip; break;
+    case LINCOLL_INFO_EPS: *val = pl->p.eps; break;
+    default: return LINCOLL_EINVAL;
+  }
+  return LINCOLL_OK;
+}
+
+void lincoll_destroy(lincoll_plan_t pl) {
+  if (!pl) return;
+  (void)hipStreamSynchronize(pl->stream);
+  void* ptrs[] = {pl->d_Phi,  pl->d_Om,    pl->d_Om64,  pl->d_phi,  pl->d_Cdct, pl->d_params, pl->d_fac64,
+                  pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
+                  pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Lp, pl->d_pin};
+  for (void* p : ptrs) dfree(p);
+  delete pl;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// In-register FFT building blocks for gfx950 (one thread owns a whole
+// length-N complex sequence; N a power of two <= 64).  Every index is a
+// compile-time constant after expansion, so the sequence stays in VGPRs and
+// the bit-reversal is a register renaming.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "twiddles.h"
+
+namespace lincoll {
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+constexpr int bitrev(int i, int n) {
+  int r = 0;
+  for (int b = 1; b < n; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// (re + i im) *= exp(-+ 2 pi i E / N)   (minus: forward, plus: inverse)
+template <int N, int E, bool INV, typename T>
+__device__ __forceinline__ void twiddle(T& re, T& im) {
+  constexpr int e = ((E % N) + N) % N;
+  if constexpr (e == 0) {
+    return;
+  } else if constexpr (2 * e == N) {
+    re = -re;
+    im = -im;
+  } else if constexpr (4 * e == N) {
+    const T r = re;
+    if constexpr (!INV) { re = im; im = -r; } else { re = -im; im = r; }
+  } else if constexpr (4 * e == 3 * N) {
+    const T r = re;
+    if constexpr (!INV) { re = -im; im = r; } else { re = im; im = -r; }
+  } else {
+    constexpr int k = e * (64 / N);
+    const T c = static_cast<T>(TWC[k]);
+    const T s = INV ? static_cast<T>(TWS[k]) : -static_cast<T>(TWS[k]);
+    const T r = re * c - im * s;
+    im = re * s + im * c;
+    re = r;
+  }
+}
+
+// Unnormalised DFT of length N in place, natural order in and out:
+//   X[k] = sum_j x[j] exp(-+ 2 pi i j k / N).
+// Radix-2 decimation in frequency; trivial twiddles are free.
+template <int N, bool INV, typename T>
+__device__ __forceinline__ void fft(T (&re)[N], T (&im)[N]) {
+  static_assert(N >= 2 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
+  static_for<0, ilog2(N)>([&](auto s) {
+    constexpr int span = N >> s;
+    constexpr int half = span / 2;
+    static_for<0, N / span>([&](auto g) {
+      static_for<0, half>([&](auto k) {
+        constexpr int i0 = g * span + k;
+        constexpr int i1 = i0 + half;
+        const T ar = re[i0], ai = im[i0], br = re[i1], bi = im[i1];
+        re[i0] = ar + br;
+        im[i0] = ai + bi;
+        T dr = ar - br, di = ai - bi;
+        twiddle<span, k, INV>(dr, di);
+        re[i1] = dr;
+        im[i1] = di;
+      });
+    });
+  });
+  T tr[N], ti[N];
+  static_for<0, N>([&](auto i) {
+    constexpr int r = bitrev(i, N);
+    tr[r] = re[i];
+    ti[r] = im[i];
+  });
+  static_for<0, N>([&](auto i) {
+    re[i] = tr[i];
+    im[i] = ti[i];
+  });
+}
+
+// Two real length-N sequences a, b packed as z = a + i b, transformed
+// forward: returns the half spectra A[k], B[k], k = 0..N/2.
+template <int N, typename T>
+__device__ __forceinline__ void split_real_pair(const T (&zr)[N], const T (&zi)[N], T (&Ar)[N / 2 + 1],
+                                                T (&Ai)[N / 2 + 1], T (&Br)[N / 2 + 1], T (&Bi)[N / 2 + 1]) {
+  static_for<0, N / 2 + 1>([&](auto k) {
+    constexpr int m = (N - k) % N;
+    const T pr = zr[k], pi = zi[k], qr = zr[m], qi = -zi[m];   // Z(k), conj Z(N-k)
+    Ar[k] = T(0.5) * (pr + qr);
+    Ai[k] = T(0.5) * (pi + qi);
+    // (Z - conj Z') / (2i)
+    Br[k] = T(0.5) * (pi - qi);
+    Bi[k] = -T(0.5) * (pr - qr);
+  });
+}
+
+// Inverse of the above packing: from Hermitian half spectra A, B build
+// Z = A + i B on all N bins (imaginary parts of the bins 0 and N/2 are
+// dropped, as a real inverse transform does).
+template <int N, typename T>
+__device__ __forceinline__ void join_real_pair(const T (&Ar)[N / 2 + 1], const T (&Ai)[N / 2 + 1],
+                                               const T (&Br)[N / 2 + 1], const T (&Bi)[N / 2 + 1], T (&zr)[N],
+                                               T (&zi)[N]) {
+  zr[0] = Ar[0];
+  zi[0] = Br[0];
+  zr[N / 2] = Ar[N / 2];
+  zi[N / 2] = Br[N / 2];
+  static_for<1, N / 2>([&](auto k) {
+    zr[k] = Ar[k] - Bi[k];
+    zi[k] = Ai[k] + Br[k];
+    zr[N - k] = Ar[k] + Bi[k];
+    zi[N - k] = Br[k] - Ai[k];
+  });
+}
+
+}  // namespace lincoll

@@ -1,0 +1,73 @@
+// Internal interfaces between the ABI layer and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lincoll {
+
+// Everything one staged or fused apply needs (raw device pointers; element
+// type is double for dtype 0 and float otherwise; complex = interleaved).
+struct ApplyCtx {
+  int n = 0, J = 0, Q = 0;
+  int batch = 0, Bc = 0;       // cells in this call; cells in the Maxwellian cache (1 = broadcast)
+  int dtype = 0;
+  hipStream_t stream = nullptr;
+  const void* h = nullptr;
+  void* out = nullptr;
+  const void* Phi = nullptr;   // [J][Q]  Phi_j(|k|^2) / n^3
+  const void* Om = nullptr;    // [Q]     Omega(|k|^2) / n^3
+  const void* fac = nullptr;   // [Bc][6][n]: exp(-(v-u_d)^2/(2 theta)), d = 1..3; then exp(-(v-u_d)^2/theta)
+  const void* pref = nullptr;  // [Bc][2]: rho (2 pi theta)^-3/2, rho (pi theta)^-3/2
+  const uint32_t* mask = nullptr;  // [Bc][n*n][(n+31)/32] cutoff bits along z
+  const void* Kh = nullptr;    // [Bc][J][P][P][P]  K_j / n^3 on the octant, P = n/2+1
+  const void* nu = nullptr;    // [Bc][n^3]
+  void* R = nullptr;           // work, complex [batch][P][n][n] each
+  void* H = nullptr;
+  void* W = nullptr;
+  void* Lp = nullptr;
+};
+
+// Per-cell FP64 setup context.
+struct SetupCtx {
+  int n = 0, J = 0, Q = 0;
+  int Bc = 0;
+  int dtype = 0;
+  double L = 0.0, eps = 0.0;
+  hipStream_t stream = nullptr;
+  const double* params = nullptr;  // [Bc][5]
+  const double* phi = nullptr;     // [J][P^3]
+  const double* Cdct = nullptr;    // [P][P]
+  const double* Om64 = nullptr;    // [Q] Omega / n^3, FP64
+  double* fac64 = nullptr;         // [Bc][6][n]
+  double* pref64 = nullptr;        // [Bc][2]
+  double* gfac64 = nullptr;        // [Bc][P]
+  double* Ainv = nullptr;          // [Bc][25]
+  void* facT = nullptr;            // copies in the apply dtype
+  void* prefT = nullptr;
+  uint32_t* mask = nullptr;
+  void* Kh = nullptr;              // [Bc][J][P^3] apply dtype
+  void* nu = nullptr;              // [Bc][n^3] apply dtype
+  double* tmpA = nullptr;          // scratch, [chunk][J][P^3] FP64 each
+  double* tmpB = nullptr;
+  double* planes64 = nullptr;      // scratch, complex double [chunk][P][n][n]
+  int chunk = 0;                   // cells per scratch pass
+};
+
+struct ProjectCtx {
+  int n = 0, batch = 0, Bc = 0, dtype = 0;
+  double L = 0.0;
+  hipStream_t stream = nullptr;
+  const void* x = nullptr;
+  void* y = nullptr;
+  const double* fac64 = nullptr;
+  const double* pref64 = nullptr;
+  const double* Ainv = nullptr;
+};
+
+hipError_t staged_apply(const ApplyCtx& c);
+hipError_t setup_cells(const SetupCtx& c);
+hipError_t project_cells(const ProjectCtx& c);
+bool staged_supported(int n, int dtype);
+
+}  // namespace lincoll

@@ -1,0 +1,171 @@
+"""Thin ctypes binding of liblincoll (C ABI in include/lincoll.h).
+
+Argument marshalling only: every step of the operator runs in the HIP
+library.  Device arrays are torch tensors (contiguous, on the plan's GPU);
+the binding passes their data pointers and torch's current HIP stream.
+If the library is missing the import of this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblincoll.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENOTIMPL = 0, -1, -2, -3, -4, -5
+DTYPES = {"f64": 0, "f32": 1, "bf16x3": 2}
+PATHS = {"auto": 0, "staged": 1, "fused": 2}
+TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
+INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
+        "hip_error": 7, "eps": 8}
+SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
+           "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
+           "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables"]
+
+
+class LincollError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {_lib.lincoll_strerror(status).decode()} ({status})")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_double), ("omega", ctypes.c_double),
+                ("C", ctypes.c_double), ("R", ctypes.c_double), ("J", ctypes.c_int),
+                ("eps", ctypes.c_double), ("quad_rule", ctypes.c_int), ("project", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("dtype", ctypes.c_int), ("path", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"liblincoll.so not built at {LIB_PATH}; run python -m paper_2503_09580_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "lincoll_params_default": (None, [P(Params), i, d, d, i]),
+        "lincoll_plan": (i, [i, d, d, i, P(vp)]),
+        "lincoll_plan_ex": (i, [P(Params), P(vp)]),
+        "lincoll_set_stream": (i, [vp, vp]),
+        "lincoll_set_maxwellians": (i, [vp, vp, i]),
+        "lincoll_apply": (i, [vp, vp, vp, i]),
+        "lincoll_project": (i, [vp, vp, vp, i]),
+        "quadcoll_apply": (i, [vp, vp, vp, i]),
+        "lincoll_get_info": (i, [vp, i, P(d)]),
+        "lincoll_destroy": (None, [vp]),
+        "lincoll_strerror": (ctypes.c_char_p, [i]),
+        "lincoll_plan_tables": (ctypes.c_longlong, [P(Params), i, P(d), ctypes.c_longlong]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def library():
+    return _lib
+
+
+def make_params(n, L, omega, dtype="f64", **kw):
+    p = Params()
+    _lib.lincoll_params_default(ctypes.byref(p), int(n), float(L), float(omega), DTYPES[dtype])
+    for k, v in kw.items():
+        if k == "path":
+            v = PATHS[v] if isinstance(v, str) else v
+        setattr(p, k, v)
+    return p
+
+
+def plan_tables(n, L, omega, table, **kw):
+    """Host-only plan table (no GPU): g, W, Phi, Omega or phi."""
+    p = make_params(n, L, omega, "f64", **kw)
+    cnt = _lib.lincoll_plan_tables(ctypes.byref(p), TABLES[table], None, 0)
+    if cnt < 0:
+        raise LincollError(int(cnt), "lincoll_plan_tables")
+    out = np.empty(cnt, dtype=np.float64)
+    st = _lib.lincoll_plan_tables(ctypes.byref(p), TABLES[table], out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cnt)
+    if st < 0:
+        raise LincollError(int(st), "lincoll_plan_tables")
+    return out
+
+
+def _check(st, what):
+    if st != OK:
+        raise LincollError(st, what)
+
+
+class Plan:
+    """A lincoll plan on the current GPU.
+
+    Plan(n, L, omega, dtype="f64"|"f32"|"bf16x3", **params) with optional
+    C, R, J, eps, quad_rule, project, max_batch, path ("auto"|"staged"|"fused").
+    """
+
+    def __init__(self, n, L, omega, dtype="f64", **kw):
+        import torch
+        self._torch = torch
+        self.n, self.L, self.omega, self.dtype = n, L, omega, dtype
+        self.tdtype = torch.float64 if dtype == "f64" else torch.float32
+        self._p = make_params(n, L, omega, dtype, **kw)
+        self._h = ctypes.c_void_p()
+        _check(_lib.lincoll_plan_ex(ctypes.byref(self._p), ctypes.byref(self._h)), "lincoll_plan_ex")
+        self._stream = None
+
+    def close(self):
+        if self._h:
+            _lib.lincoll_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = self._torch.cuda.current_stream().cuda_stream
+        if s != self._stream:
+            _check(_lib.lincoll_set_stream(self._h, ctypes.c_void_p(s)), "lincoll_set_stream")
+            self._stream = s
+
+    def _dev(self, t, dtype, shape_tail=None, name="array"):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype:
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+        if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [batch, {shape_tail}]")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_maxwellians(self, params):
+        """params: float64 CUDA tensor [batch, 5] = (rho, u1, u2, u3, theta)."""
+        self._sync_stream()
+        self._params_ref = params
+        _check(_lib.lincoll_set_maxwellians(self._h, self._dev(params, self._torch.float64, (5,), "params"),
+                                            params.shape[0]), "lincoll_set_maxwellians")
+
+    def apply(self, h, out=None):
+        n = self.n
+        if out is None:
+            out = self._torch.empty_like(h)
+        self._sync_stream()
+        _check(_lib.lincoll_apply(self._h, self._dev(h, self.tdtype, (n, n, n), "h"),
+                                  self._dev(out, self.tdtype, (n, n, n), "out"), h.shape[0]), "lincoll_apply")
+        return out
+
+    def project(self, x, y=None):
+        n = self.n
+        if y is None:
+            y = self._torch.empty_like(x)
+        self._sync_stream()
+        _check(_lib.lincoll_project(self._h, self._dev(x, self.tdtype, (n, n, n), "x"),
+                                    self._dev(y, self.tdtype, (n, n, n), "y"), x.shape[0]), "lincoll_project")
+        return y
+
+    def info(self, key):
+        v = ctypes.c_double()
+        _check(_lib.lincoll_get_info(self._h, INFO[key], ctypes.byref(v)), "lincoll_get_info")
+        return v.value
