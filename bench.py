@@ -1,0 +1,175 @@
+"""Benchmark: batched applications of the linearized VHS collision operator
+L[h] = Q(M,h) + Q(h,M) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64|bf16x3]
+                    [--path auto|staged|fused] [--config C3|C2|C1] [--no-cpu]
+
+A step is one call of lincoll_apply over the whole batch of the workload
+(configuration C3 by default: n = 32 points per velocity axis, box [-8,8)^3,
+VHS omega = 0.74, 4096 cells along a 1-D grid, each with its own local
+Maxwellian), with the inputs and the per-cell Maxwellian setup resident in
+HBM before timing starts.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks.  Packed FP32 instructions are kept out of these
+# kernels, so plain FP32 and FP64 vector FMAs both issue at
+# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.
+PEAK_VALU_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def alg_flops_per_cell(n, J):
+    """Algorithmic work of one cell-apply: (2J + 4) real 3-D transforms at
+    2.5 N log2 N (N = n^3), 4J n^3 for the mode products and ~60 n^3 for the
+    Maxwellians, the cutoff division and the loss combination."""
+    N3 = n ** 3
+    return (2 * J + 4) * 2.5 * N3 * math.log2(N3) + 4 * J * N3 + 60 * N3
+
+
+def alg_bytes_per_cell(n, elem):
+    """Compulsory HBM traffic of one cell-apply: h in, L out, 5 parameters."""
+    return 2 * n ** 3 * elem + 40
+
+
+def workload(cfg):
+    from paper_2503_09580_amd import workloads as wl
+    if cfg == "C3":
+        h, p = wl.c3()
+    elif cfg == "C2":
+        h, p = wl.c2()
+    elif cfg == "C1":
+        h, p = wl.c1()
+    else:
+        raise SystemExit(f"unknown config {cfg}")
+    c = wl.CONFIGS[cfg]
+    return h, p, c
+
+
+def cpu_baseline(cfg, h, params, c, budget_s=12.0):
+    """The oracle (Algorithm 1 with numpy's FFT, FP64) on a bounded sample of
+    the same cells, timed on this host."""
+    from oracle import alg1, fast_direct
+    plan = fast_direct.make_plan(c["n"], c["L"], c["omega"])
+    alg1.apply_batch(plan, h[:1], params[:1])          # warm
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < budget_s and done < h.shape[0]:
+        b = done
+        alg1.apply_batch(plan, h[b:b + 1], params[b:b + 1] if params.shape[0] > 1 else params)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "applies/s", "cores": alg1.threads_used(), "kind": "oracle",
+            "sample": f"first {done} cells of {cfg}, one at a time, FP64, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--path", default="auto")
+    ap.add_argument("--config", default="C3")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; per-cell work has no cross-GPU traffic, "
+                                   "so N GPUs would each run this workload on their own share of cells",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2503_09580_amd import lincoll
+
+    dev = torch.device("cuda:0")
+    h, params, c = workload(a.config)
+    n, L, om, B = c["n"], c["L"], c["omega"], h.shape[0]
+    td = torch.float64 if a.dtype == "f64" else torch.float32
+    elem = 8 if a.dtype == "f64" else 4
+    ht = torch.from_numpy(h).to(dev, td)
+    pt = torch.from_numpy(params).to(dev, torch.float64)
+    out = torch.empty_like(ht)
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        plan = lincoll.Plan(n, L, om, a.dtype, path=a.path)
+        plan.set_maxwellians(pt)
+        J = int(plan.info("J"))
+        path = "fused" if plan.info("path") == 2 else "staged"
+        for _ in range(a.warmup):
+            plan.apply(ht, out)
+        stream.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(a.steps):
+            plan.apply(ht, out)
+        ev1.record(stream)
+        ev1.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / a.steps
+    value = B * a.steps / (gpu_ms / 1e3)
+
+    rec = {
+        "metric": f"L[h] applies/sec at N={n} ({a.dtype.upper()})",
+        "value": value,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "wall_s_timed": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32 storage, f64 arithmetic", "bf16x3": "bf16x3"}.get(a.dtype, a.dtype),
+        "data": "synthetic",
+        "config": {"workload": f"{a.config}: {B} cells, n={n}, box [-{L:g},{L:g})^3, VHS omega={om}, "
+                               f"J={J}, eps=1e-9, per-cell Maxwellians" if a.config == "C3" else
+                               f"{a.config}: {B} cells, n={n}, box [-{L:g},{L:g})^3, VHS omega={om}, J={J}",
+                   "cells": B, "n": n, "path": path},
+    }
+    # roofline of the apply (all launches of one step on one stream)
+    fl = alg_flops_per_cell(n, J) * B
+    by = alg_bytes_per_cell(n, elem) * B
+    achieved = fl / (ms_per_step / 1e3) / 1e12
+    rec["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                       "kernel": "lincoll_apply (whole step)",
+                       "hbm_GBs_compulsory": by / (ms_per_step / 1e3) / 1e9}
+    if not a.no_check:
+        # accuracy of this result against the FP64 path on the same GPU and
+        # the same (rounded) inputs
+        with torch.cuda.stream(stream):
+            ref_plan = lincoll.Plan(n, L, om, "f64", path="staged")
+            ref_plan.set_maxwellians(pt)
+            h64 = ht.double()
+            ref = ref_plan.apply(h64)
+            stream.synchronize()
+        d = (out.double() - ref).reshape(B, -1).norm(dim=1) / ref.reshape(B, -1).norm(dim=1)
+        rec["rel_err_vs_fp64"] = {"max": float(d.max()), "median": float(d.median())}
+        del ref_plan, ref, h64
+    if not a.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(a.config, h, params, c)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -13,11 +13,6 @@
 
 using namespace lincoll;
 
-namespace lincoll {
-bool fused_supported(int n, int dtype);
-hipError_t fused_apply(const ApplyCtx& c);
-}  // namespace lincoll
-
 struct lincoll_plan_s {
   lincoll_params_t p{};
   HostTables t;
@@ -50,6 +45,7 @@ struct lincoll_plan_s {
   double* d_planes64 = nullptr;
   // apply work
   int cap_work = 0, cap_pin = 0;
+  size_t fused_bytes = 0;
   void* d_R = nullptr;
   void* d_H = nullptr;
   void* d_W = nullptr;
@@ -153,8 +149,16 @@ int ensure_work(lincoll_plan_t pl, int B) {
     if ((e = dalloc(pl, &pl->d_pin, (size_t)B * n * n * n * es))) return hip_fail(pl, e);
     pl->cap_pin = B;
   }
-  if (use_fused(pl)) return LINCOLL_OK;
-  if (B <= pl->cap_work && pl->d_R) return LINCOLL_OK;
+  if (use_fused(pl)) {
+    const size_t need = fused_scratch_bytes(n, fused_slots(n, B));
+    if (need > pl->fused_bytes) {
+      if ((e = dalloc(pl, &pl->d_R, need))) return hip_fail(pl, e);
+      pl->fused_bytes = need;
+      pl->cap_work = 0;
+    }
+    return LINCOLL_OK;
+  }
+  if (B <= pl->cap_work && pl->d_R && pl->d_H) return LINCOLL_OK;
   const size_t vol = (size_t)B * P * n * n * 2 * es;
   if ((e = dalloc(pl, &pl->d_R, vol)) || (e = dalloc(pl, &pl->d_H, vol)) || (e = dalloc(pl, &pl->d_W, vol)) ||
       (e = dalloc(pl, &pl->d_Lp, vol)))
@@ -388,6 +392,8 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
   c.Om = pl->d_Om;
   c.fac = pl->p.dtype == LINCOLL_F64 ? (const void*)pl->d_fac64 : pl->d_facT;
   c.pref = pl->p.dtype == LINCOLL_F64 ? (const void*)pl->d_pref64 : pl->d_prefT;
+  c.fac64 = pl->d_fac64;
+  c.pref64 = pl->d_pref64;
   c.mask = pl->d_mask;
   c.Kh = pl->d_Kh;
   c.nu = pl->d_nu;

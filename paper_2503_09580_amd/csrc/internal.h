@@ -19,6 +19,8 @@ struct ApplyCtx {
   const void* Om = nullptr;    // [Q]     Omega(|k|^2) / n^3
   const void* fac = nullptr;   // [Bc][6][n]: exp(-(v-u_d)^2/(2 theta)), d = 1..3; then exp(-(v-u_d)^2/theta)
   const void* pref = nullptr;  // [Bc][2]: rho (2 pi theta)^-3/2, rho (pi theta)^-3/2
+  const double* fac64 = nullptr;   // the same two in FP64
+  const double* pref64 = nullptr;
   const uint32_t* mask = nullptr;  // [Bc][n*n][(n+31)/32] cutoff bits along z
   const void* Kh = nullptr;    // [Bc][J][P][P][P]  K_j / n^3 on the octant, P = n/2+1
   const void* nu = nullptr;    // [Bc][n^3]
@@ -69,5 +71,9 @@ hipError_t staged_apply(const ApplyCtx& c);
 hipError_t setup_cells(const SetupCtx& c);
 hipError_t project_cells(const ProjectCtx& c);
 bool staged_supported(int n, int dtype);
+bool fused_supported(int n, int dtype);
+hipError_t fused_apply(const ApplyCtx& c);
+size_t fused_scratch_bytes(int n, int nslots);
+int fused_slots(int n, int batch);
 
 }  // namespace lincoll

@@ -18,146 +18,184 @@ template <typename T> struct V2;
 template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
 
+// Arrays in device memory hold the storage type TS (float or double); every
+// transform and product runs in registers of the compute type TC.  The FP32
+// path uses TS = float, TC = double: on gfx950 without packed FP32 math a
+// double FMA issues at the same rate as a float FMA, so the extra precision
+// costs only conversions and registers, while the round-off that the
+// division r = h/M amplifies (Sec. 3.3) drops to the FP32 storage rounding.
+
 template <int NN>
 __device__ __forceinline__ int fold(int K) { return K <= NN / 2 ? K : NN - K; }
 
 // ---------------------------------------------------------------- z stage
-// Prologue (Algorithm 1, first loop and the FFTs of r and f): per column
-// (cell, x, y) the two real sequences r = chi h / M and h along z, packed as
-// one complex transform, split into the half spectra R and H.
-// MODE 1: the same for the single sequence M (setup of nu), into H.
-template <typename T, int NN, int MODE>
-__global__ void __launch_bounds__(128) k_z_fwd(const T* __restrict__ h, typename V2<T>::t* __restrict__ R,
-                                                typename V2<T>::t* __restrict__ H, const T* __restrict__ fac,
-                                                const T* __restrict__ pref, const uint32_t* __restrict__ mask,
+// Prologue (Algorithm 1, first loop and the FFTs of r and f): per pair of
+// columns (x, y) and (x, y + n/2) the real sequences r = chi h / M and h along
+// z; the two r columns share one complex transform and the two h columns
+// another (r and h are never packed together: r is large where M is small,
+// and its round-off would swamp the much smaller h).
+// MODE 1: M itself for the setup of nu (into H).
+template <typename TS, typename T, int NN, int MODE>
+__global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, typename V2<TS>::t* __restrict__ R,
+                                                typename V2<TS>::t* __restrict__ H, const TS* __restrict__ fac,
+                                                const TS* __restrict__ pref, const uint32_t* __restrict__ mask,
                                                 int Bc, int batch) {
-  using C = typename V2<T>::t;
-  constexpr int P = NN / 2 + 1, NP = NN * NN, MW = (NN + 31) / 32;
+  using C = typename V2<TS>::t;
+  constexpr int P = NN / 2 + 1, NP = NN * NN, HALF = NP / 2, MW = (NN + 31) / 32;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)batch * NP) return;
-  const int cell = (int)(gid / NP), col = (int)(gid % NP);
-  const int x = col / NN, y = col % NN;
+  if (gid >= (long)batch * HALF) return;
+  const int cell = (int)(gid / HALF), c = (int)(gid % HALF);
+  const int x = c / (NN / 2), y1 = c % (NN / 2), y2 = y1 + NN / 2;
+  const int col1 = x * NN + y1, col2 = col1 + NN / 2;
   const int cc = Bc > 1 ? cell : 0;
-  const T* f = fac + (size_t)cc * 6 * NN;
-  const T mxy = pref[2 * cc] * f[x] * f[NN + y];
-  T zr[NN], zi[NN];
+  const TS* f = fac + (size_t)cc * 6 * NN;
+  const T mx = T(pref[2 * cc]) * T(f[x]);
+  const T m1 = mx * T(f[NN + y1]), m2 = mx * T(f[NN + y2]);
+  T ar[NN], ai[NN];
+  T Ar[P], Ai[P], Br[P], Bi[P];
+  const size_t b1 = (size_t)cell * P * NP + col1, b2 = b1 + NN / 2;
   if constexpr (MODE == 0) {
-    const T* hc = h + ((size_t)cell * NP + col) * NN;
-    const uint32_t* mk = mask + ((size_t)cc * NP + col) * MW;
-    uint32_t bits[MW];
-    static_for<0, MW>([&](auto w) { bits[w] = mk[w]; });
+    const TS* h1 = h + ((size_t)cell * NP + col1) * NN;
+    const TS* h2 = h1 + (size_t)(NN / 2) * NN;
+    const uint32_t* mk1 = mask + ((size_t)cc * NP + col1) * MW;
+    const uint32_t* mk2 = mk1 + (NN / 2) * MW;
+    uint32_t k1[MW], k2[MW];
+    static_for<0, MW>([&](auto w) { k1[w] = mk1[w]; k2[w] = mk2[w]; });
+    T hr[NN], hi[NN];
     static_for<0, NN>([&](auto z) {
-      const T hv = hc[z];
-      const T M = mxy * f[2 * NN + z];
-      const bool keep = (bits[z / 32] >> (z % 32)) & 1u;
-      zr[z] = keep ? hv / M : T(0);
-      zi[z] = hv;
+      const T ez = T(f[2 * NN + z]);
+      const T v1 = T(h1[z]), v2 = T(h2[z]);
+      hr[z] = v1;
+      hi[z] = v2;
+      ar[z] = ((k1[z / 32] >> (z % 32)) & 1u) ? v1 / (m1 * ez) : T(0);
+      ai[z] = ((k2[z / 32] >> (z % 32)) & 1u) ? v2 / (m2 * ez) : T(0);
+    });
+    fft<NN, false>(ar, ai);
+    split_real_pair<NN>(ar, ai, Ar, Ai, Br, Bi);
+    static_for<0, P>([&](auto k) {
+      R[b1 + (size_t)k * NP] = C{TS(Ar[k]), TS(Ai[k])};
+      R[b2 + (size_t)k * NP] = C{TS(Br[k]), TS(Bi[k])};
+    });
+    fft<NN, false>(hr, hi);
+    split_real_pair<NN>(hr, hi, Ar, Ai, Br, Bi);
+    static_for<0, P>([&](auto k) {
+      H[b1 + (size_t)k * NP] = C{TS(Ar[k]), TS(Ai[k])};
+      H[b2 + (size_t)k * NP] = C{TS(Br[k]), TS(Bi[k])};
     });
   } else {
     static_for<0, NN>([&](auto z) {
-      zr[z] = mxy * f[2 * NN + z];
-      zi[z] = T(0);
+      const T ez = T(f[2 * NN + z]);
+      ar[z] = m1 * ez;
+      ai[z] = m2 * ez;
+    });
+    fft<NN, false>(ar, ai);
+    split_real_pair<NN>(ar, ai, Ar, Ai, Br, Bi);
+    static_for<0, P>([&](auto k) {
+      H[b1 + (size_t)k * NP] = C{TS(Ar[k]), TS(Ai[k])};
+      H[b2 + (size_t)k * NP] = C{TS(Br[k]), TS(Bi[k])};
     });
   }
-  fft<NN, false>(zr, zi);
-  T Ar[P], Ai[P], Br[P], Bi[P];
-  split_real_pair<NN>(zr, zi, Ar, Ai, Br, Bi);
-  const size_t base = (size_t)cell * P * NP + col;
-  static_for<0, P>([&](auto k) {
-    if constexpr (MODE == 0) {
-      R[base + (size_t)k * NP] = C{Ar[k], Ai[k]};
-      H[base + (size_t)k * NP] = C{Br[k], Bi[k]};
-    } else {
-      H[base + (size_t)k * NP] = C{Ar[k], Ai[k]};
-    }
-  });
 }
 
 // Gain loop, physical-space step (Algorithm 1: psi <- M^h psi between the
 // inverse and forward transforms): per pair of columns (x, y) and
 // (x, y + n/2), inverse real transform along z, multiply by M^h, forward
 // real transform, in place on W.
-template <typename T, int NN>
-__global__ void __launch_bounds__(128) k_z_mid(typename V2<T>::t* __restrict__ W, const T* __restrict__ fac,
-                                                const T* __restrict__ pref, int Bc, int batch) {
-  using C = typename V2<T>::t;
+template <typename TS, typename T, int NN>
+__global__ void __launch_bounds__(128) k_z_mid(typename V2<TS>::t* __restrict__ W, const TS* __restrict__ fac,
+                                                const TS* __restrict__ pref, int Bc, int batch) {
+  using C = typename V2<TS>::t;
   constexpr int P = NN / 2 + 1, NP = NN * NN, HALF = NP / 2;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long)batch * HALF) return;
   const int cell = (int)(gid / HALF), c = (int)(gid % HALF);
   const int x = c / (NN / 2), y1 = c % (NN / 2), y2 = y1 + NN / 2;
   const int cc = Bc > 1 ? cell : 0;
-  const T* f = fac + (size_t)cc * 6 * NN + 3 * NN;     // M^h factors
-  const T ph = pref[2 * cc + 1] * f[x];
-  const T m1 = ph * f[NN + y1], m2 = ph * f[NN + y2];
+  const TS* f = fac + (size_t)cc * 6 * NN + 3 * NN;    // M^h factors
+  const T ph = T(pref[2 * cc + 1]) * T(f[x]);
+  const T m1 = ph * T(f[NN + y1]), m2 = ph * T(f[NN + y2]);
   const size_t b1 = (size_t)cell * P * NP + (size_t)x * NN + y1;
   const size_t b2 = b1 + NN / 2;
   T Ar[P], Ai[P], Br[P], Bi[P];
   static_for<0, P>([&](auto k) {
     const C a = W[b1 + (size_t)k * NP];
     const C b = W[b2 + (size_t)k * NP];
-    Ar[k] = a.x; Ai[k] = a.y; Br[k] = b.x; Bi[k] = b.y;
+    Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
   });
   T zr[NN], zi[NN];
   join_real_pair<NN>(Ar, Ai, Br, Bi, zr, zi);
   fft<NN, true>(zr, zi);
   static_for<0, NN>([&](auto z) {
-    const T ez = f[2 * NN + z];
+    const T ez = T(f[2 * NN + z]);
     zr[z] *= m1 * ez;
     zi[z] *= m2 * ez;
   });
   fft<NN, false>(zr, zi);
   split_real_pair<NN>(zr, zi, Ar, Ai, Br, Bi);
   static_for<0, P>([&](auto k) {
-    W[b1 + (size_t)k * NP] = C{Ar[k], Ai[k]};
-    W[b2 + (size_t)k * NP] = C{Br[k], Bi[k]};
+    W[b1 + (size_t)k * NP] = C{TS(Ar[k]), TS(Ai[k])};
+    W[b2 + (size_t)k * NP] = C{TS(Br[k]), TS(Bi[k])};
   });
 }
 
-// Epilogue (Algorithm 1, last three lines): per column, inverse real
-// transforms of L+^ and (Omega H^) along z packed as one complex transform,
-// then L = L+ - M U - nu h.  MODE 1 (setup): nu <- inverse of H only.
-template <typename T, int NN, int MODE>
-__global__ void __launch_bounds__(128) k_z_inv(const typename V2<T>::t* __restrict__ Lp,
-                                                const typename V2<T>::t* __restrict__ H, const T* __restrict__ h,
-                                                const T* __restrict__ nu, T* __restrict__ out,
-                                                const T* __restrict__ fac, const T* __restrict__ pref, int Bc,
+// Epilogue (Algorithm 1, last three lines): per pair of columns, inverse
+// real transforms along z of L+^ (two columns packed) and of (Omega H^) (two
+// columns packed), then L = L+ - M U - nu h.
+// MODE 1 (setup): nu <- inverse of H only.
+template <typename TS, typename T, int NN, int MODE>
+__global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restrict__ Lp,
+                                                const typename V2<TS>::t* __restrict__ H, const TS* __restrict__ h,
+                                                const TS* __restrict__ nu, TS* __restrict__ out,
+                                                const TS* __restrict__ fac, const TS* __restrict__ pref, int Bc,
                                                 int batch) {
-  using C = typename V2<T>::t;
-  constexpr int P = NN / 2 + 1, NP = NN * NN;
+  using C = typename V2<TS>::t;
+  constexpr int P = NN / 2 + 1, NP = NN * NN, HALF = NP / 2;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)batch * NP) return;
-  const int cell = (int)(gid / NP), col = (int)(gid % NP);
-  const int x = col / NN, y = col % NN;
+  if (gid >= (long)batch * HALF) return;
+  const int cell = (int)(gid / HALF), c = (int)(gid % HALF);
+  const int x = c / (NN / 2), y1 = c % (NN / 2), y2 = y1 + NN / 2;
+  const int col1 = x * NN + y1, col2 = col1 + NN / 2;
   const int cc = Bc > 1 ? cell : 0;
-  const size_t base = (size_t)cell * P * NP + col;
+  const size_t b1 = (size_t)cell * P * NP + col1, b2 = b1 + NN / 2;
   T Ar[P], Ai[P], Br[P], Bi[P];
+  T ur[NN], ui[NN];
   static_for<0, P>([&](auto k) {
-    const C b = H[base + (size_t)k * NP];
-    Br[k] = b.x; Bi[k] = b.y;
-    if constexpr (MODE == 0) {
-      const C a = Lp[base + (size_t)k * NP];
-      Ar[k] = a.x; Ai[k] = a.y;
-    } else {
-      Ar[k] = T(0); Ai[k] = T(0);
-    }
+    const C a = H[b1 + (size_t)k * NP];
+    const C b = H[b2 + (size_t)k * NP];
+    Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
   });
-  T zr[NN], zi[NN];
-  join_real_pair<NN>(Ar, Ai, Br, Bi, zr, zi);
-  fft<NN, true>(zr, zi);
-  T* oc = out + ((size_t)cell * NP + col) * NN;
+  join_real_pair<NN>(Ar, Ai, Br, Bi, ur, ui);
+  fft<NN, true>(ur, ui);                       // U on column 1 (re), column 2 (im)
+  TS* o1 = out + ((size_t)cell * NP + col1) * NN;
+  TS* o2 = o1 + (size_t)(NN / 2) * NN;
   if constexpr (MODE == 0) {
-    const T* f = fac + (size_t)cc * 6 * NN;
-    const T mxy = pref[2 * cc] * f[x] * f[NN + y];
-    const T* hc = h + ((size_t)cell * NP + col) * NN;
-    const T* nc = nu + ((size_t)cc * NP + col) * NN;
+    T lr[NN], li[NN];
+    static_for<0, P>([&](auto k) {
+      const C a = Lp[b1 + (size_t)k * NP];
+      const C b = Lp[b2 + (size_t)k * NP];
+      Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
+    });
+    join_real_pair<NN>(Ar, Ai, Br, Bi, lr, li);
+    fft<NN, true>(lr, li);                     // L+ on column 1 (re), column 2 (im)
+    const TS* f = fac + (size_t)cc * 6 * NN;
+    const T mx = T(pref[2 * cc]) * T(f[x]);
+    const T m1 = mx * T(f[NN + y1]), m2 = mx * T(f[NN + y2]);
+    const TS* h1 = h + ((size_t)cell * NP + col1) * NN;
+    const TS* h2 = h1 + (size_t)(NN / 2) * NN;
+    const TS* n1 = nu + ((size_t)cc * NP + col1) * NN;
+    const TS* n2 = n1 + (size_t)(NN / 2) * NN;
     static_for<0, NN>([&](auto z) {
-      const T M = mxy * f[2 * NN + z];
-      oc[z] = zr[z] - M * zi[z] - nc[z] * hc[z];
+      const T ez = T(f[2 * NN + z]);
+      o1[z] = TS(lr[z] - (m1 * ez) * ur[z] - T(n1[z]) * T(h1[z]));
+      o2[z] = TS(li[z] - (m2 * ez) * ui[z] - T(n2[z]) * T(h2[z]));
     });
   } else {
-    static_for<0, NN>([&](auto z) { oc[z] = zi[z]; });
+    static_for<0, NN>([&](auto z) {
+      o1[z] = TS(ur[z]);
+      o2[z] = TS(ui[z]);
+    });
   }
+  (void)col2;
 }
 
 // ------------------------------------------------------------- xy stage
@@ -165,32 +203,33 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<T>::t* __restri
 // PRE 1: multiply by K_j(|kx|,|ky|,kz) before an inverse transform.
 // POST 1: multiply by a radial table t(|k|^2) after a forward transform.
 // POST 2: as 1 and accumulate into out (store when first).
-template <typename T, int NN, bool INV, int PRE, int POST>
-__global__ void __launch_bounds__(64) k_plane(const typename V2<T>::t* in, typename V2<T>::t* out,
-                                               const T* __restrict__ Kh, const T* __restrict__ table, int J,
+template <typename TS, typename T, int NN, bool INV, int PRE, int POST>
+__global__ void __launch_bounds__(64) k_plane(const typename V2<TS>::t* in, typename V2<TS>::t* out,
+                                               const TS* __restrict__ Kh, const TS* __restrict__ table, int J,
                                                int j, int Bc, int nplanes, int first) {
-  using C = typename V2<T>::t;
+  using C = typename V2<TS>::t;
+  using CT = typename V2<T>::t;     // the transpose in LDS keeps compute precision
   constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
-  __shared__ C lds[PPB * NN * LD];
+  __shared__ CT lds[PPB * NN * LD];
   const int lp = threadIdx.x / NN, a = threadIdx.x % NN;
   const long pid = (long)blockIdx.x * PPB + lp;
   const bool active = pid < nplanes;
   const int cell = (int)(pid / P), kz = (int)(pid % P);
   const int cc = Bc > 1 ? cell : 0;
-  C* sm = lds + lp * NN * LD;
+  CT* sm = lds + lp * NN * LD;
   T vr[NN], vi[NN];
   // column a of the plane: element [k1][a], k1 = 0..NN-1
   if (active) {
     const C* src = in + (size_t)pid * NP + a;
     static_for<0, NN>([&](auto k1) {
       const C v = src[(size_t)k1 * NN];
-      vr[k1] = v.x;
-      vi[k1] = v.y;
+      vr[k1] = T(v.x);
+      vi[k1] = T(v.y);
     });
     if constexpr (PRE == 1) {
-      const T* K = Kh + ((size_t)cc * J + j) * P * P * P + (size_t)kz * P * P + fold<NN>(a);
+      const TS* K = Kh + ((size_t)cc * J + j) * P * P * P + (size_t)kz * P * P + fold<NN>(a);
       static_for<0, NN>([&](auto k1) {
-        const T kv = K[fold<NN>(k1) * P];
+        const T kv = T(K[fold<NN>(k1) * P]);
         vr[k1] *= kv;
         vi[k1] *= kv;
       });
@@ -199,31 +238,31 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<T>::t* in, typen
     static_for<0, NN>([&](auto k1) { vr[k1] = T(0); vi[k1] = T(0); });
   }
   fft<NN, INV>(vr, vi);                    // along the first in-plane axis
-  static_for<0, NN>([&](auto k1) { sm[k1 * LD + a] = C{vr[k1], vi[k1]}; });
+  static_for<0, NN>([&](auto k1) { sm[k1 * LD + a] = CT{vr[k1], vi[k1]}; });
   __syncthreads();
   static_for<0, NN>([&](auto k2) {
-    const C v = sm[a * LD + k2];
+    const CT v = sm[a * LD + k2];
     vr[k2] = v.x;
     vi[k2] = v.y;
   });
   fft<NN, INV>(vr, vi);                    // along the second in-plane axis
   __syncthreads();
-  static_for<0, NN>([&](auto k2) { sm[a * LD + k2] = C{vr[k2], vi[k2]}; });
+  static_for<0, NN>([&](auto k2) { sm[a * LD + k2] = CT{vr[k2], vi[k2]}; });
   __syncthreads();
   static_for<0, NN>([&](auto k1) {
-    const C v = sm[k1 * LD + a];
+    const CT v = sm[k1 * LD + a];
     vr[k1] = v.x;
     vi[k1] = v.y;
   });
   if (!active) return;
   C* dst = out + (size_t)pid * NP + a;
   if constexpr (POST >= 1) {
-    const T* tj = table + (size_t)j * (3 * (NN / 2) * (NN / 2) + 1);
+    const TS* tj = table + (size_t)j * (3 * (NN / 2) * (NN / 2) + 1);
     const int fa = fold<NN>(a);
     const int qb = fa * fa + kz * kz;
     static_for<0, NN>([&](auto k1) {
       const int f1 = fold<NN>(k1);
-      const T t = tj[qb + f1 * f1];
+      const T t = T(tj[qb + f1 * f1]);
       vr[k1] *= t;
       vi[k1] *= t;
     });
@@ -232,66 +271,62 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<T>::t* in, typen
     if (!first) {
       static_for<0, NN>([&](auto k1) {
         const C o = dst[(size_t)k1 * NN];
-        vr[k1] += o.x;
-        vi[k1] += o.y;
+        vr[k1] += T(o.x);
+        vi[k1] += T(o.y);
       });
     }
   }
-  static_for<0, NN>([&](auto k1) { dst[(size_t)k1 * NN] = C{vr[k1], vi[k1]}; });
+  static_for<0, NN>([&](auto k1) { dst[(size_t)k1 * NN] = C{TS(vr[k1]), TS(vi[k1])}; });
 }
 
 // ----------------------------------------------------------- launchers
-template <typename T, int NN>
+template <typename TS, typename T, int NN>
 static hipError_t apply_n(const ApplyCtx& c) {
-  using Cx = typename V2<T>::t;
+  using Cx = typename V2<TS>::t;
   constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = 64 / NN;
   const int B = c.batch;
-  const T* fac = static_cast<const T*>(c.fac);
-  const T* pref = static_cast<const T*>(c.pref);
-  const T* Kh = static_cast<const T*>(c.Kh);
-  const T* Phi = static_cast<const T*>(c.Phi);
-  const T* Om = static_cast<const T*>(c.Om);
+  const TS* fac = static_cast<const TS*>(c.fac);
+  const TS* pref = static_cast<const TS*>(c.pref);
+  const TS* Kh = static_cast<const TS*>(c.Kh);
+  const TS* Phi = static_cast<const TS*>(c.Phi);
+  const TS* Om = static_cast<const TS*>(c.Om);
   Cx* R = static_cast<Cx*>(c.R);
   Cx* H = static_cast<Cx*>(c.H);
   Cx* W = static_cast<Cx*>(c.W);
   Cx* Lp = static_cast<Cx*>(c.Lp);
   const long ncol = (long)B * NP;
   const int nplanes = B * P;
-  const dim3 gz((unsigned)((ncol + 127) / 128)), gz2((unsigned)((ncol / 2 + 127) / 128));
+  const dim3 gz2((unsigned)((ncol / 2 + 127) / 128));
   const dim3 gp((unsigned)((nplanes + PPB - 1) / PPB));
-  k_z_fwd<T, NN, 0><<<gz, 128, 0, c.stream>>>(static_cast<const T*>(c.h), R, H, fac, pref, c.mask, c.Bc, B);
-  k_plane<T, NN, false, 0, 0><<<gp, 64, 0, c.stream>>>(R, R, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
-  k_plane<T, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
+  k_z_fwd<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(static_cast<const TS*>(c.h), R, H, fac, pref, c.mask, c.Bc, B);
+  k_plane<TS, T, NN, false, 0, 0><<<gp, 64, 0, c.stream>>>(R, R, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
+  k_plane<TS, T, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
   for (int j = 0; j < c.J; ++j) {
-    k_plane<T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc, nplanes, 1);
-    k_z_mid<T, NN><<<gz2, 128, 0, c.stream>>>(W, fac, pref, c.Bc, B);
-    k_plane<T, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(W, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes, j == 0);
+    k_plane<TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc, nplanes, 1);
+    k_z_mid<TS, T, NN><<<gz2, 128, 0, c.stream>>>(W, fac, pref, c.Bc, B);
+    k_plane<TS, T, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(W, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes, j == 0);
   }
-  k_plane<T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
-  k_plane<T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
-  k_z_inv<T, NN, 0><<<gz, 128, 0, c.stream>>>(Lp, H, static_cast<const T*>(c.h), static_cast<const T*>(c.nu),
-                                             static_cast<T*>(c.out), fac, pref, c.Bc, B);
+  k_plane<TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
+  k_plane<TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
+  k_z_inv<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(Lp, H, static_cast<const TS*>(c.h), static_cast<const TS*>(c.nu),
+                                                 static_cast<TS*>(c.out), fac, pref, c.Bc, B);
   return hipGetLastError();
 }
 
-bool staged_supported(int n, int dtype) {
-  if (dtype == 0) return n == 8 || n == 16 || n == 32;
-  return n == 8 || n == 16 || n == 32 || n == 64;
-}
+bool staged_supported(int n, int) { return n == 8 || n == 16 || n == 32; }
 
 hipError_t staged_apply(const ApplyCtx& c) {
   if (c.dtype == 0) {
     switch (c.n) {
-      case 8: return apply_n<double, 8>(c);
-      case 16: return apply_n<double, 16>(c);
-      case 32: return apply_n<double, 32>(c);
+      case 8: return apply_n<double, double, 8>(c);
+      case 16: return apply_n<double, double, 16>(c);
+      case 32: return apply_n<double, double, 32>(c);
     }
   } else {
     switch (c.n) {
-      case 8: return apply_n<float, 8>(c);
-      case 16: return apply_n<float, 16>(c);
-      case 32: return apply_n<float, 32>(c);
-      case 64: return apply_n<float, 64>(c);
+      case 8: return apply_n<float, double, 8>(c);
+      case 16: return apply_n<float, double, 16>(c);
+      case 32: return apply_n<float, double, 32>(c);
     }
   }
   return hipErrorInvalidValue;
@@ -304,11 +339,11 @@ hipError_t nu_chunk(const double* fac64, const double* pref64, const double* Om6
   constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = 64 / NN;
   const long ncol = (long)ncell * NP;
   const int nplanes = ncell * P;
-  const dim3 gz((unsigned)((ncol + 127) / 128)), gp((unsigned)((nplanes + PPB - 1) / PPB));
-  k_z_fwd<double, NN, 1><<<gz, 128, 0, s>>>(nullptr, nullptr, planes, fac64, pref64, nullptr, ncell, ncell);
-  k_plane<double, NN, false, 0, 1><<<gp, 64, 0, s>>>(planes, planes, nullptr, Om64, 0, 0, ncell, nplanes, 1);
-  k_plane<double, NN, true, 0, 0><<<gp, 64, 0, s>>>(planes, planes, nullptr, nullptr, 0, 0, ncell, nplanes, 1);
-  k_z_inv<double, NN, 1><<<gz, 128, 0, s>>>(nullptr, planes, nullptr, nullptr, nu64, nullptr, nullptr, ncell, ncell);
+  const dim3 gz2((unsigned)((ncol / 2 + 127) / 128)), gp((unsigned)((nplanes + PPB - 1) / PPB));
+  k_z_fwd<double, double, NN, 1><<<gz2, 128, 0, s>>>(nullptr, nullptr, planes, fac64, pref64, nullptr, ncell, ncell);
+  k_plane<double, double, NN, false, 0, 1><<<gp, 64, 0, s>>>(planes, planes, nullptr, Om64, 0, 0, ncell, nplanes, 1);
+  k_plane<double, double, NN, true, 0, 0><<<gp, 64, 0, s>>>(planes, planes, nullptr, nullptr, 0, 0, ncell, nplanes, 1);
+  k_z_inv<double, double, NN, 1><<<gz2, 128, 0, s>>>(nullptr, planes, nullptr, nullptr, nu64, nullptr, nullptr, ncell, ncell);
   return hipGetLastError();
 }
 
