@@ -49,6 +49,7 @@ struct lincoll_plan_s {
   void* d_R = nullptr;
   void* d_H = nullptr;
   void* d_W = nullptr;
+  void* d_Wq = nullptr;
   void* d_Lp = nullptr;
   void* d_pin = nullptr;      // projected input when p.project
 };
@@ -159,9 +160,9 @@ int ensure_work(lincoll_plan_t pl, int B) {
     return LINCOLL_OK;
   }
   if (B <= pl->cap_work && pl->d_R && pl->d_H) return LINCOLL_OK;
-  const size_t vol = (size_t)B * P * n * n * 2 * es;
-  if ((e = dalloc(pl, &pl->d_R, vol)) || (e = dalloc(pl, &pl->d_H, vol)) || (e = dalloc(pl, &pl->d_W, vol)) ||
-      (e = dalloc(pl, &pl->d_Lp, vol)))
+  const size_t vol = (size_t)B * P * n * n * 2 * es, vol64 = (size_t)B * P * n * n * 2 * sizeof(double);
+  if ((e = dalloc(pl, &pl->d_R, vol64)) || (e = dalloc(pl, &pl->d_H, vol)) || (e = dalloc(pl, &pl->d_W, vol64)) ||
+      (e = dalloc(pl, &pl->d_Wq, vol)) || (e = dalloc(pl, &pl->d_Lp, vol)))
     return hip_fail(pl, e);
   pl->cap_work = B;
   return LINCOLL_OK;
@@ -400,6 +401,7 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
   c.R = pl->d_R;
   c.H = pl->d_H;
   c.W = pl->d_W;
+  c.Wq = pl->d_Wq;
   c.Lp = pl->d_Lp;
   hipError_t e = use_fused(pl) ? fused_apply(c) : staged_apply(c);
   if (e) return hip_fail(pl, e);
@@ -434,7 +436,7 @@ void lincoll_destroy(lincoll_plan_t pl) {
   (void)hipStreamSynchronize(pl->stream);
   void* ptrs[] = {pl->d_Phi,  pl->d_Om,    pl->d_Om64,  pl->d_phi,  pl->d_Cdct, pl->d_params, pl->d_fac64,
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
-                  pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Lp, pl->d_pin};
+                  pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin};
   for (void* p : ptrs) dfree(p);
   delete pl;
 }

@@ -24,9 +24,10 @@ struct ApplyCtx {
   const uint32_t* mask = nullptr;  // [Bc][n*n][(n+31)/32] cutoff bits along z
   const void* Kh = nullptr;    // [Bc][J][P][P][P]  K_j / n^3 on the octant, P = n/2+1
   const void* nu = nullptr;    // [Bc][n^3]
-  void* R = nullptr;           // work, complex [batch][P][n][n] each
+  void* R = nullptr;           // work, complex [batch][P][n][n] each; R and W in double
   void* H = nullptr;
   void* W = nullptr;
+  void* Wq = nullptr;
   void* Lp = nullptr;
 };
 

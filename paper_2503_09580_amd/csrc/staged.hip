@@ -36,7 +36,7 @@ __device__ __forceinline__ int fold(int K) { return K <= NN / 2 ? K : NN - K; }
 // and its round-off would swamp the much smaller h).
 // MODE 1: M itself for the setup of nu (into H).
 template <typename TS, typename T, int NN, int MODE>
-__global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, typename V2<TS>::t* __restrict__ R,
+__global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, double2* __restrict__ R,
                                                 typename V2<TS>::t* __restrict__ H, const TS* __restrict__ fac,
                                                 const TS* __restrict__ pref, const uint32_t* __restrict__ mask,
                                                 int Bc, int batch) {
@@ -73,8 +73,8 @@ __global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, typenam
     fft<NN, false>(ar, ai);
     split_real_pair<NN>(ar, ai, Ar, Ai, Br, Bi);
     static_for<0, P>([&](auto k) {
-      R[b1 + (size_t)k * NP] = C{TS(Ar[k]), TS(Ai[k])};
-      R[b2 + (size_t)k * NP] = C{TS(Br[k]), TS(Bi[k])};
+      R[b1 + (size_t)k * NP] = double2{double(Ar[k]), double(Ai[k])};
+      R[b2 + (size_t)k * NP] = double2{double(Br[k]), double(Bi[k])};
     });
     fft<NN, false>(hr, hi);
     split_real_pair<NN>(hr, hi, Ar, Ai, Br, Bi);
@@ -102,8 +102,9 @@ __global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, typenam
 // (x, y + n/2), inverse real transform along z, multiply by M^h, forward
 // real transform, in place on W.
 template <typename TS, typename T, int NN>
-__global__ void __launch_bounds__(128) k_z_mid(typename V2<TS>::t* __restrict__ W, const TS* __restrict__ fac,
-                                                const TS* __restrict__ pref, int Bc, int batch) {
+__global__ void __launch_bounds__(128) k_z_mid(const double2* __restrict__ W, typename V2<TS>::t* __restrict__ Wq,
+                                                const TS* __restrict__ fac, const TS* __restrict__ pref, int Bc,
+                                                int batch) {
   using C = typename V2<TS>::t;
   constexpr int P = NN / 2 + 1, NP = NN * NN, HALF = NP / 2;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,8 +119,8 @@ __global__ void __launch_bounds__(128) k_z_mid(typename V2<TS>::t* __restrict__ 
   const size_t b2 = b1 + NN / 2;
   T Ar[P], Ai[P], Br[P], Bi[P];
   static_for<0, P>([&](auto k) {
-    const C a = W[b1 + (size_t)k * NP];
-    const C b = W[b2 + (size_t)k * NP];
+    const double2 a = W[b1 + (size_t)k * NP];
+    const double2 b = W[b2 + (size_t)k * NP];
     Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
   });
   T zr[NN], zi[NN];
@@ -133,8 +134,8 @@ __global__ void __launch_bounds__(128) k_z_mid(typename V2<TS>::t* __restrict__ 
   fft<NN, false>(zr, zi);
   split_real_pair<NN>(zr, zi, Ar, Ai, Br, Bi);
   static_for<0, P>([&](auto k) {
-    W[b1 + (size_t)k * NP] = C{TS(Ar[k]), TS(Ai[k])};
-    W[b2 + (size_t)k * NP] = C{TS(Br[k]), TS(Bi[k])};
+    Wq[b1 + (size_t)k * NP] = C{TS(Ar[k]), TS(Ai[k])};
+    Wq[b2 + (size_t)k * NP] = C{TS(Br[k]), TS(Bi[k])};
   });
 }
 
@@ -203,11 +204,12 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restr
 // PRE 1: multiply by K_j(|kx|,|ky|,kz) before an inverse transform.
 // POST 1: multiply by a radial table t(|k|^2) after a forward transform.
 // POST 2: as 1 and accumulate into out (store when first).
-template <typename TS, typename T, int NN, bool INV, int PRE, int POST>
-__global__ void __launch_bounds__(64) k_plane(const typename V2<TS>::t* in, typename V2<TS>::t* out,
+template <typename TI, typename TO, typename TS, typename T, int NN, bool INV, int PRE, int POST>
+__global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, typename V2<TO>::t* out,
                                                const TS* __restrict__ Kh, const TS* __restrict__ table, int J,
                                                int j, int Bc, int nplanes, int first) {
-  using C = typename V2<TS>::t;
+  using CI = typename V2<TI>::t;
+  using C = typename V2<TO>::t;
   using CT = typename V2<T>::t;     // the transpose in LDS keeps compute precision
   constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
   __shared__ CT lds[PPB * NN * LD];
@@ -220,9 +222,9 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TS>::t* in, type
   T vr[NN], vi[NN];
   // column a of the plane: element [k1][a], k1 = 0..NN-1
   if (active) {
-    const C* src = in + (size_t)pid * NP + a;
+    const CI* src = in + (size_t)pid * NP + a;
     static_for<0, NN>([&](auto k1) {
-      const C v = src[(size_t)k1 * NN];
+      const CI v = src[(size_t)k1 * NN];
       vr[k1] = T(v.x);
       vi[k1] = T(v.y);
     });
@@ -276,7 +278,7 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TS>::t* in, type
       });
     }
   }
-  static_for<0, NN>([&](auto k1) { dst[(size_t)k1 * NN] = C{TS(vr[k1]), TS(vi[k1])}; });
+  static_for<0, NN>([&](auto k1) { dst[(size_t)k1 * NN] = C{TO(vr[k1]), TO(vi[k1])}; });
 }
 
 // ----------------------------------------------------------- launchers
@@ -290,24 +292,31 @@ static hipError_t apply_n(const ApplyCtx& c) {
   const TS* Kh = static_cast<const TS*>(c.Kh);
   const TS* Phi = static_cast<const TS*>(c.Phi);
   const TS* Om = static_cast<const TS*>(c.Om);
-  Cx* R = static_cast<Cx*>(c.R);
+  // r-derived spectra (R, and W before the product with M^h) are kept in
+  // double for every dtype; H, W after the product and L+ use TS.
+  double2* R = static_cast<double2*>(c.R);
+  double2* W = static_cast<double2*>(c.W);
   Cx* H = static_cast<Cx*>(c.H);
-  Cx* W = static_cast<Cx*>(c.W);
+  Cx* Wq = static_cast<Cx*>(c.Wq);
   Cx* Lp = static_cast<Cx*>(c.Lp);
   const long ncol = (long)B * NP;
   const int nplanes = B * P;
   const dim3 gz2((unsigned)((ncol / 2 + 127) / 128));
   const dim3 gp((unsigned)((nplanes + PPB - 1) / PPB));
   k_z_fwd<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(static_cast<const TS*>(c.h), R, H, fac, pref, c.mask, c.Bc, B);
-  k_plane<TS, T, NN, false, 0, 0><<<gp, 64, 0, c.stream>>>(R, R, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
-  k_plane<TS, T, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
+  k_plane<double, double, TS, T, NN, false, 0, 0><<<gp, 64, 0, c.stream>>>(R, R, nullptr, nullptr, c.J, 0, c.Bc,
+                                                                           nplanes, 1);
+  k_plane<TS, TS, TS, T, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
   for (int j = 0; j < c.J; ++j) {
-    k_plane<TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc, nplanes, 1);
-    k_z_mid<TS, T, NN><<<gz2, 128, 0, c.stream>>>(W, fac, pref, c.Bc, B);
-    k_plane<TS, T, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(W, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes, j == 0);
+    k_plane<double, double, TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc,
+                                                                            nplanes, 1);
+    k_z_mid<TS, T, NN><<<gz2, 128, 0, c.stream>>>(W, Wq, fac, pref, c.Bc, B);
+    k_plane<TS, TS, TS, T, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(Wq, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes,
+                                                                     j == 0);
   }
-  k_plane<TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
-  k_plane<TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
+  k_plane<TS, TS, TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc, nplanes,
+                                                                  1);
+  k_plane<TS, TS, TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
   k_z_inv<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(Lp, H, static_cast<const TS*>(c.h), static_cast<const TS*>(c.nu),
                                                  static_cast<TS*>(c.out), fac, pref, c.Bc, B);
   return hipGetLastError();
@@ -341,8 +350,10 @@ hipError_t nu_chunk(const double* fac64, const double* pref64, const double* Om6
   const int nplanes = ncell * P;
   const dim3 gz2((unsigned)((ncol / 2 + 127) / 128)), gp((unsigned)((nplanes + PPB - 1) / PPB));
   k_z_fwd<double, double, NN, 1><<<gz2, 128, 0, s>>>(nullptr, nullptr, planes, fac64, pref64, nullptr, ncell, ncell);
-  k_plane<double, double, NN, false, 0, 1><<<gp, 64, 0, s>>>(planes, planes, nullptr, Om64, 0, 0, ncell, nplanes, 1);
-  k_plane<double, double, NN, true, 0, 0><<<gp, 64, 0, s>>>(planes, planes, nullptr, nullptr, 0, 0, ncell, nplanes, 1);
+  k_plane<double, double, double, double, NN, false, 0, 1><<<gp, 64, 0, s>>>(planes, planes, nullptr, Om64, 0, 0,
+                                                                             ncell, nplanes, 1);
+  k_plane<double, double, double, double, NN, true, 0, 0><<<gp, 64, 0, s>>>(planes, planes, nullptr, nullptr, 0, 0,
+                                                                            ncell, nplanes, 1);
   k_z_inv<double, double, NN, 1><<<gz2, 128, 0, s>>>(nullptr, planes, nullptr, nullptr, nu64, nullptr, nullptr, ncell, ncell);
   return hipGetLastError();
 }
