@@ -1,6 +1,6 @@
-// Fused persistent kernel: one workgroup per cell (looping over cells), the
-// whole of Algorithm 1 on chip except the FP64 spectrum of r, which streams
-// from a per-workgroup scratch slot (L2 / Infinity-cache resident).
+// Fused persistent kernel: one workgroup per cell (looping over cells) runs
+// all of Algorithm 1 on chip; only the FP64 spectrum of r streams from a
+// per-workgroup scratch slot, once per quadrature node.
 //
 // Grid-of-pencils layout for n = NN points per axis (N = NN/2, KP = N packed
 // z-planes, NN*N threads).  The real transform along z packs the real bins
@@ -11,14 +11,18 @@
 //   X role: thread t = (kp, b) owns the pencil along x (or kx) at y (ky) = b.
 //   Z role: thread t = (x, yp) = (t / N, t % N) owns the columns (x, yp) and
 //           (x, yp + N) along z.
-// Transposes between roles go through LDS.
+// A wave holds whole planes in the Y and X roles (64 / NN planes), so the
+// Y <-> X transposes are local to a wave's own LDS region and need no
+// workgroup barrier; only X <-> Z exchanges synchronise the workgroup.
 //
-// Precision (FP32 storage at the HBM boundary): every butterfly runs in
-// double.  The spectrum of r = chi h / M and the inverse transforms that
-// produce psi_j keep double storage as well: r is large where M is small and
-// any rounding of its spectral or partially transformed values spreads that
-// size over the whole box (Sec. 3.3).  After the product with M^h the data
-// is concentrated where M is not small and float storage suffices.
+// Precision (FP32 at the HBM boundary): the spectrum of r = chi h / M is
+// stored in double, and every butterfly that acts on r-derived data (the
+// forward transform of r, the inverse transforms giving psi_j) runs in
+// double, with float storage between axis passes.  r is large where M is
+// small (Sec. 3.3): rounding its spectrum to float, or float arithmetic on
+// it, spreads that size over the box, while rounding partially transformed
+// values between passes does not measurably change the result.  After the
+// product with M^h everything runs in float.
 #include "fft.h"
 #include "internal.h"
 
@@ -26,168 +30,115 @@ namespace lincoll {
 
 namespace {
 
-template <typename S> struct V2f;
-template <> struct V2f<float> { using t = float2; };
-template <> struct V2f<double> { using t = double2; };
-
 template <int NN>
 struct Cfg {
   static constexpr int N = NN / 2;
   static constexpr int KP = N;                 // packed planes
   static constexpr int T = NN * N;             // threads
   static constexpr int P = N + 1;
+  static constexpr int P3 = P * P * P;
   static constexpr int Q = 3 * N * N + 1;
   static constexpr int MW = (NN + 31) / 32;
   static constexpr int LD = NN + 1;            // padded LDS row
-  // LDS transpose buffer: one full volume of float2 (KP * NN * LD * 8 B)
-  static constexpr int LDS_BYTES = KP * NN * LD * 8;
-  // rounds needed to move a double volume through it
-  static constexpr int R64 = 2;
+  static constexpr int LDS_BYTES = KP * NN * LD * 8;   // one float2 volume
+  static constexpr int KPRE = (P3 + T - 1) / T;        // K_j values per thread
+  static constexpr int PPRE = (Q + T - 1) / T;         // Phi_j values per thread
 };
 
-__device__ __forceinline__ int foldk(int K, int NN) { return K <= NN / 2 ? K : NN - K; }
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ---- z stage: two real columns <-> their packed half spectra ------------------
-// forward: a, b real (as zr, zi) -> s1[k], s2[k], k < N, with bin 0 holding
-// (A(0), A(N)) and bins 1..N-1 the complex A(k).
+// forward: a, b real (as zr, zi) -> v[k] (column a) and v[N + k] (column b),
+// k < N; bin 0 holds (A(0), A(N)), bins 1..N-1 the complex A(k).
 template <int NN, typename T>
-__device__ __forceinline__ void z_forward(T (&zr)[NN], T (&zi)[NN], T (&s1r)[NN / 2], T (&s1i)[NN / 2],
-                                          T (&s2r)[NN / 2], T (&s2i)[NN / 2]) {
+__device__ __forceinline__ void z_forward(T (&zr)[NN], T (&zi)[NN], T (&vr)[NN], T (&vi)[NN]) {
   constexpr int N = NN / 2;
   fft<NN, false>(zr, zi);
   T Ar[N + 1], Ai[N + 1], Br[N + 1], Bi[N + 1];
   split_real_pair<NN>(zr, zi, Ar, Ai, Br, Bi);
-  s1r[0] = Ar[0];
-  s1i[0] = Ar[N];
-  s2r[0] = Br[0];
-  s2i[0] = Br[N];
+  vr[0] = Ar[0];
+  vi[0] = Ar[N];
+  vr[N] = Br[0];
+  vi[N] = Br[N];
   static_for<1, N>([&](auto k) {
-    s1r[k] = Ar[k];
-    s1i[k] = Ai[k];
-    s2r[k] = Br[k];
-    s2i[k] = Bi[k];
+    vr[k] = Ar[k];
+    vi[k] = Ai[k];
+    vr[N + k] = Br[k];
+    vi[N + k] = Bi[k];
   });
 }
 
 template <int NN, typename T>
-__device__ __forceinline__ void z_inverse(const T (&s1r)[NN / 2], const T (&s1i)[NN / 2], const T (&s2r)[NN / 2],
-                                          const T (&s2i)[NN / 2], T (&zr)[NN], T (&zi)[NN]) {
+__device__ __forceinline__ void z_inverse(const T (&vr)[NN], const T (&vi)[NN], T (&zr)[NN], T (&zi)[NN]) {
   constexpr int N = NN / 2;
   T Ar[N + 1], Ai[N + 1], Br[N + 1], Bi[N + 1];
-  Ar[0] = s1r[0]; Ai[0] = T(0); Ar[N] = s1i[0]; Ai[N] = T(0);
-  Br[0] = s2r[0]; Bi[0] = T(0); Br[N] = s2i[0]; Bi[N] = T(0);
+  Ar[0] = vr[0]; Ai[0] = T(0); Ar[N] = vi[0]; Ai[N] = T(0);
+  Br[0] = vr[N]; Bi[0] = T(0); Br[N] = vi[N]; Bi[N] = T(0);
   static_for<1, N>([&](auto k) {
-    Ar[k] = s1r[k]; Ai[k] = s1i[k];
-    Br[k] = s2r[k]; Bi[k] = s2i[k];
+    Ar[k] = vr[k]; Ai[k] = vi[k];
+    Br[k] = vr[N + k]; Bi[k] = vi[N + k];
   });
   join_real_pair<NN>(Ar, Ai, Br, Bi, zr, zi);
   fft<NN, true>(zr, zi);
 }
 
-// ---- transposes through LDS ---------------------------------------------------
-// Within each plane kp: thread (kp, i) holds v[j] = element (i, j); afterwards
-// it holds v[j] = element (j, i).  S is the LDS storage type; ROUNDS splits
-// the planes into groups when a volume of S does not fit the buffer.
-template <int NN, int ROUNDS, typename S, typename T>
-__device__ __forceinline__ void transpose_plane(T (&vr)[NN], T (&vi)[NN], void* ldsv, int t) {
-  using S2 = typename V2f<S>::t;
-  constexpr int KP = NN / 2, LD = NN + 1, KPR = KP / ROUNDS;
-  S2* lds = static_cast<S2*>(ldsv);
+// ---- transposes through LDS (float2 storage) ----------------------------------
+// Within plane kp: thread (kp, i) holds v[j] = element (i, j); afterwards it
+// holds v[j] = element (j, i).  Plane kp lives in the region of the wave that
+// owns it, so a wave-level fence suffices.
+template <int NN, typename T>
+__device__ __forceinline__ void transpose_plane(T (&vr)[NN], T (&vi)[NN], float2* lds, int t) {
+  constexpr int LD = NN + 1;
   const int kp = t / NN, i = t % NN;
-  static_for<0, ROUNDS>([&](auto r) {
-    const bool mine = (kp / KPR) == r;
-    const int kl = kp % KPR;
-    if (mine) static_for<0, NN>([&](auto j) { lds[(kl * NN + i) * LD + j] = S2{S(vr[j]), S(vi[j])}; });
-    __syncthreads();
-    if (mine)
-      static_for<0, NN>([&](auto j) {
-        const S2 v = lds[(kl * NN + j) * LD + i];
-        vr[j] = T(v.x);
-        vi[j] = T(v.y);
-      });
-    __syncthreads();
+  float2* pl = lds + kp * NN * LD;
+  static_for<0, NN>([&](auto j) { pl[i * LD + j] = float2{float(vr[j]), float(vi[j])}; });
+  wave_lds_sync();
+  static_for<0, NN>([&](auto j) {
+    const float2 v = pl[j * LD + i];
+    vr[j] = T(v.x);
+    vi[j] = T(v.y);
   });
+  wave_lds_sync();
 }
 
-// X role (kp, y) holding v[x]  ->  Z role (x, yp) holding s1[kp] = (kp, x, yp),
-// s2[kp] = (kp, x, yp + N).  The same registers are reused: v and (s1, s2)
-// are two views of NN complex values.
-template <int NN, int ROUNDS, typename S, typename T>
-__device__ __forceinline__ void x_to_z(T (&vr)[NN], T (&vi)[NN], void* ldsv, int t) {
-  using S2 = typename V2f<S>::t;
-  constexpr int N = NN / 2, KP = N, LD = NN + 1, XR = NN / ROUNDS;
-  S2* lds = static_cast<S2*>(ldsv);
-  const int kp = t / NN, y = t % NN;
-  const int x = t / N, yp = t % N;
-  T o1r[N], o1i[N], o2r[N], o2i[N];
-  static_for<0, ROUNDS>([&](auto r) {
-    static_for<0, XR>([&](auto xl) {
-      lds[(kp * XR + xl) * LD + y] = S2{S(vr[r * XR + xl]), S(vi[r * XR + xl])};
-    });
-    __syncthreads();
-    if (x / XR == r) {
-      const int xl = x % XR;
-      static_for<0, KP>([&](auto k) {
-        const S2 a = lds[(k * XR + xl) * LD + yp];
-        const S2 b = lds[(k * XR + xl) * LD + yp + N];
-        o1r[k] = T(a.x); o1i[k] = T(a.y);
-        o2r[k] = T(b.x); o2i[k] = T(b.y);
-      });
-    }
-    __syncthreads();
-  });
-  static_for<0, N>([&](auto k) {
-    vr[k] = o1r[k]; vi[k] = o1i[k];
-    vr[N + k] = o2r[k]; vi[N + k] = o2i[k];
-  });
-}
-
-// Z role -> X role (inverse of x_to_z), one round of float storage.
-template <int NN, typename S, typename T>
-__device__ __forceinline__ void z_to_x(T (&vr)[NN], T (&vi)[NN], void* ldsv, int t) {
-  using S2 = typename V2f<S>::t;
+// X role (kp, y) holding v[x] -> Z role (x, yp) holding v[k] = (k, x, yp),
+// v[N + k] = (k, x, yp + N).  Writes go to the writer's own plane region.
+template <int NN, typename T>
+__device__ __forceinline__ void x_to_z(T (&vr)[NN], T (&vi)[NN], float2* lds, int t) {
   constexpr int N = NN / 2, KP = N, LD = NN + 1;
-  S2* lds = static_cast<S2*>(ldsv);
   const int kp = t / NN, y = t % NN;
   const int x = t / N, yp = t % N;
+  static_for<0, NN>([&](auto xx) { lds[(kp * NN + xx) * LD + y] = float2{float(vr[xx]), float(vi[xx])}; });
+  __syncthreads();
   static_for<0, KP>([&](auto k) {
-    lds[(k * NN + x) * LD + yp] = S2{S(vr[k]), S(vi[k])};
-    lds[(k * NN + x) * LD + yp + N] = S2{S(vr[N + k]), S(vi[N + k])};
+    const float2 a = lds[(k * NN + x) * LD + yp];
+    const float2 b = lds[(k * NN + x) * LD + yp + N];
+    vr[k] = T(a.x); vi[k] = T(a.y);
+    vr[N + k] = T(b.x); vi[N + k] = T(b.y);
+  });
+}
+
+// Z role -> X role.  Reads come from the reader's own plane region.
+template <int NN, typename T>
+__device__ __forceinline__ void z_to_x(T (&vr)[NN], T (&vi)[NN], float2* lds, int t) {
+  constexpr int N = NN / 2, KP = N, LD = NN + 1;
+  const int kp = t / NN, y = t % NN;
+  const int x = t / N, yp = t % N;
+  __syncthreads();
+  static_for<0, KP>([&](auto k) {
+    lds[(k * NN + x) * LD + yp] = float2{float(vr[k]), float(vi[k])};
+    lds[(k * NN + x) * LD + yp + N] = float2{float(vr[N + k]), float(vi[N + k])};
   });
   __syncthreads();
   static_for<0, NN>([&](auto xx) {
-    const S2 a = lds[(kp * NN + xx) * LD + y];
+    const float2 a = lds[(kp * NN + xx) * LD + y];
     vr[xx] = T(a.x);
     vi[xx] = T(a.y);
   });
-  __syncthreads();
-}
-
-// Z role -> X role for double storage, two rounds over the halves of x.
-template <int NN>
-__device__ __forceinline__ void z_to_x64(double (&vr)[NN], double (&vi)[NN], void* ldsv, int t) {
-  constexpr int N = NN / 2, KP = N, LD = NN + 1, XR = NN / 2;
-  double2* lds = static_cast<double2*>(ldsv);
-  const int kp = t / NN, y = t % NN;
-  const int x = t / N, yp = t % N;
-  double orr[NN], oi[NN];
-  static_for<0, 2>([&](auto r) {
-    if (x / XR == r) {
-      const int xl = x % XR;
-      static_for<0, KP>([&](auto k) {
-        lds[(k * XR + xl) * LD + yp] = double2{vr[k], vi[k]};
-        lds[(k * XR + xl) * LD + yp + N] = double2{vr[N + k], vi[N + k]};
-      });
-    }
-    __syncthreads();
-    static_for<0, XR>([&](auto xl) {
-      const double2 a = lds[(kp * XR + xl) * LD + y];
-      orr[r * XR + xl] = a.x;
-      oi[r * XR + xl] = a.y;
-    });
-    __syncthreads();
-  });
-  static_for<0, NN>([&](auto i) { vr[i] = orr[i]; vi[i] = oi[i]; });
 }
 
 // Y role, pencil along ky: multiply by a real spectral factor m(kx, ky, kz)
@@ -209,16 +160,16 @@ __device__ __forceinline__ void mode_multiply(T (&vr)[NN], T (&vi)[NN], int t, G
       const T br = __shfl(vr[j], partner, 64), bi = __shfl(vi[j], partner, 64);
       {
         const auto m = getm(j);
-        const T s = packed ? T(0.5) * (m.x + m.y) : m.x;
-        const T d = packed ? T(0.5) * (m.x - m.y) : T(0);
+        const T s = packed ? T(0.5) * (T(m.x) + T(m.y)) : T(m.x);
+        const T d = packed ? T(0.5) * (T(m.x) - T(m.y)) : T(0);
         const T nr = s * vr[j] + d * ar, ni = s * vi[j] - d * ai;
         vr[j] = nr;
         vi[j] = ni;
       }
       if constexpr (jm != j) {
         const auto m = getm(std::integral_constant<int, jm>{});
-        const T s = packed ? T(0.5) * (m.x + m.y) : m.x;
-        const T d = packed ? T(0.5) * (m.x - m.y) : T(0);
+        const T s = packed ? T(0.5) * (T(m.x) + T(m.y)) : T(m.x);
+        const T d = packed ? T(0.5) * (T(m.x) - T(m.y)) : T(0);
         const T nr = s * vr[jm] + d * br, ni = s * vi[jm] - d * bi;
         vr[jm] = nr;
         vi[jm] = ni;
@@ -226,7 +177,7 @@ __device__ __forceinline__ void mode_multiply(T (&vr)[NN], T (&vi)[NN], int t, G
     });
   } else {
     static_for<0, NN>([&](auto j) {
-      const T m = getm(j).x;
+      const T m = T(getm(j).x);
       vr[j] *= m;
       vi[j] *= m;
     });
@@ -242,24 +193,33 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     const float* __restrict__ nu, const float* __restrict__ Phi, const float* __restrict__ Om,
     double2* __restrict__ scratch, int J) {
   using C = Cfg<NN>;
-  constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, P3 = P * P * P;
-  __shared__ __align__(16) unsigned char lds_raw[C::LDS_BYTES];
-  __shared__ double fs[6 * NN + 2];
+  constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, P3 = C::P3;
+  __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
+  __shared__ double fs[9 * NN + 3];
   __shared__ float tab[Q];
   __shared__ float Ks[P3];
-  void* lds = lds_raw;
-  const int t = threadIdx.x;
-  const int kp = t / NN, ia = t % NN;          // Y / X roles
-  const int zx = t / N, zyp = t % N;           // Z role
-  const int fx = ia <= N ? ia : NN - ia;
+  const int t0 = threadIdx.x;
   double2* Rs = scratch + (size_t)blockIdx.x * KP * NP;
 
   for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
     const int cc = Bc > 1 ? cell : 0;
+    // Per-thread addresses derive from t; keeping t opaque to the optimiser
+    // here stops it from hoisting dozens of them out of the loop (and
+    // spilling them); they are recomputed with a few integer operations.
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const int kp = t / NN, ia = t % NN;          // Y / X roles
+    const int zx = t / N, zyp = t % N;           // Z role
+    const int fx = ia <= N ? ia : NN - ia;
     __syncthreads();
     for (int i = t; i < 6 * NN; i += C::T) fs[i] = fac64[(size_t)cc * 6 * NN + i];
     if (t < 2) fs[6 * NN + t] = pref64[2 * cc + t];
     for (int q = t; q < Q; q += C::T) tab[q] = Om[q];
+    __syncthreads();
+    // reciprocal factors of M for r = chi h / M (infinite where a factor
+    // underflows; such points are outside the cutoff and never selected)
+    for (int i = t; i < 3 * NN; i += C::T) fs[6 * NN + 2 + i] = 1.0 / fs[i];
+    if (t == 0) fs[9 * NN + 2] = 1.0 / fs[6 * NN];
     __syncthreads();
     const double* ex = fs;
     const double* eh = fs + 3 * NN;
@@ -275,13 +235,11 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       {
         float zr[NN], zi[NN];
         static_for<0, NN>([&](auto z) { zr[z] = h1[z]; zi[z] = h2[z]; });
-        float a1r[N], a1i[N], a2r[N], a2i[N];
-        z_forward<NN, float>(zr, zi, a1r, a1i, a2r, a2i);
-        static_for<0, N>([&](auto k) { fr[k] = a1r[k]; fi[k] = a1i[k]; fr[N + k] = a2r[k]; fi[N + k] = a2i[k]; });
+        z_forward<NN, float>(zr, zi, fr, fi);
       }
-      z_to_x<NN, float, float>(fr, fi, lds, t);
+      z_to_x<NN, float>(fr, fi, lds, t);
       fft<NN, false>(fr, fi);
-      transpose_plane<NN, 1, float, float>(fr, fi, lds, t);
+      transpose_plane<NN, float>(fr, fi, lds, t);
       fft<NN, false>(fr, fi);
       mode_multiply<NN, float>(fr, fi, t, [&](auto ky) {   // Omega(|k|^2) / n^3
         constexpr int fy = ky <= N ? ky : NN - ky;
@@ -289,12 +247,11 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         return float2{tab[q + kp * kp], tab[q + N * N]};
       });
       fft<NN, true>(fr, fi);
-      transpose_plane<NN, 1, float, float>(fr, fi, lds, t);
+      transpose_plane<NN, float>(fr, fi, lds, t);
       fft<NN, true>(fr, fi);
-      x_to_z<NN, 1, float, float>(fr, fi, lds, t);
-      float s1r[N], s1i[N], s2r[N], s2i[N], zr[NN], zi[NN];
-      static_for<0, N>([&](auto k) { s1r[k] = fr[k]; s1i[k] = fi[k]; s2r[k] = fr[N + k]; s2i[k] = fi[N + k]; });
-      z_inverse<NN, float>(s1r, s1i, s2r, s2i, zr, zi);
+      x_to_z<NN, float>(fr, fi, lds, t);
+      float zr[NN], zi[NN];
+      z_inverse<NN, float>(fr, fi, zr, zi);
       const float* n1 = nu + ((size_t)cc * NP + col1) * NN;
       const float* n2 = n1 + (size_t)N * NN;
       float* o1 = out + ((size_t)cell * NP + col1) * NN;
@@ -305,7 +262,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         o2[z] = float(-(mxy2 * ez) * double(zi[z]) - double(n2[z]) * double(h2[z]));
       });
     }
-    // ---------------- R = DFT[chi h / M] in double ------------------------------
+    // ---------------- R = DFT[chi h / M]: double arithmetic, double result --------
     {
       double vr[NN], vi[NN];
       {
@@ -313,55 +270,75 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         const uint32_t* mk2 = mk1 + (size_t)N * MW;
         uint32_t b1[MW], b2[MW];
         static_for<0, MW>([&](auto w) { b1[w] = mk1[w]; b2[w] = mk2[w]; });
+        const double* rx = fs + 6 * NN + 2;
+        const double rxy = fs[9 * NN + 2] * rx[zx];
+        const double r1 = rxy * rx[NN + zyp], r2 = rxy * rx[NN + zyp + N];
         double zr[NN], zi[NN];
         static_for<0, NN>([&](auto z) {
-          const double ez = ex[2 * NN + z];
-          zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? double(h1[z]) / (mxy1 * ez) : 0.0;
-          zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? double(h2[z]) / (mxy2 * ez) : 0.0;
+          const double rz = rx[2 * NN + z];
+          const double q1 = double(h1[z]) * (r1 * rz), q2 = double(h2[z]) * (r2 * rz);
+          zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? q1 : 0.0;
+          zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? q2 : 0.0;
         });
-        double a1r[N], a1i[N], a2r[N], a2i[N];
-        z_forward<NN, double>(zr, zi, a1r, a1i, a2r, a2i);
-        static_for<0, N>([&](auto k) { vr[k] = a1r[k]; vi[k] = a1i[k]; vr[N + k] = a2r[k]; vi[N + k] = a2i[k]; });
+        z_forward<NN, double>(zr, zi, vr, vi);
       }
-      z_to_x64<NN>(vr, vi, lds, t);
+      z_to_x<NN, double>(vr, vi, lds, t);
       fft<NN, false>(vr, vi);
-      transpose_plane<NN, C::R64, double, double>(vr, vi, lds, t);
+      transpose_plane<NN, double>(vr, vi, lds, t);
       fft<NN, false>(vr, vi);
-      // store R: [kp][ky][kx], lanes along kx
-      static_for<0, NN>([&](auto ky) { Rs[((size_t)kp * NN + ky) * NN + ia] = double2{vr[ky], vi[ky]}; });
+      // store R: [kp][kx][ky], each thread's pencil contiguous (one base
+      // address, immediate offsets)
+      double2* rp = Rs + (size_t)(kp * NN + ia) * NN;
+      static_for<0, NN>([&](auto ky) { rp[ky] = double2{vr[ky], vi[ky]}; });
     }
 
     // ---------------- gain loop ---------------------------------------------------
     float Lr[NN], Li[NN];
     static_for<0, NN>([&](auto ky) { Lr[ky] = 0.f; Li[ky] = 0.f; });
+    float kpre[C::KPRE], ppre[C::PPRE];
+    {
+      const float* K0 = Kh + (size_t)cc * J * P3;
+      static_for<0, C::KPRE>([&](auto i) {
+        const int q = t + i * C::T;
+        kpre[i] = q < P3 ? K0[q] : 0.f;
+      });
+      static_for<0, C::PPRE>([&](auto i) {
+        const int q = t + i * C::T;
+        ppre[i] = q < Q ? Phi[q] : 0.f;
+      });
+    }
     for (int j = 0; j < J; ++j) {
+      asm volatile("" : "+v"(t));
       __syncthreads();
-      for (int q = t; q < Q; q += C::T) tab[q] = Phi[(size_t)j * Q + q];
-      {
-        const float* Kj = Kh + ((size_t)cc * J + j) * P3;
-        for (int q = t; q < P3; q += C::T) Ks[q] = Kj[q];
-      }
+      static_for<0, C::KPRE>([&](auto i) {
+        const int q = t + i * C::T;
+        if (q < P3) Ks[q] = kpre[i];
+      });
+      static_for<0, C::PPRE>([&](auto i) {
+        const int q = t + i * C::T;
+        if (q < Q) tab[q] = ppre[i];
+      });
       __syncthreads();
       float fr[NN], fi[NN];
       {
         double vr[NN], vi[NN];
+        const double2* rp = Rs + (size_t)(kp * NN + ia) * NN;
         static_for<0, NN>([&](auto ky) {
-          const double2 v = Rs[((size_t)kp * NN + ky) * NN + ia];
+          const double2 v = rp[ky];
           vr[ky] = v.x;
           vi[ky] = v.y;
         });
         mode_multiply<NN, double>(vr, vi, t, [&](auto ky) {     // K_j / n^3
           constexpr int fy = ky <= N ? ky : NN - ky;
-          return double2{double(Ks[(kp * P + fy) * P + fx]), double(Ks[(N * P + fy) * P + fx])};
+          return float2{Ks[(kp * P + fy) * P + fx], Ks[(N * P + fy) * P + fx]};
         });
         fft<NN, true>(vr, vi);
-        transpose_plane<NN, C::R64, double, double>(vr, vi, lds, t);
+        transpose_plane<NN, double>(vr, vi, lds, t);
         fft<NN, true>(vr, vi);
-        x_to_z<NN, C::R64, double, double>(vr, vi, lds, t);
+        x_to_z<NN, double>(vr, vi, lds, t);
         // psi on the two columns, times M^h; float from here on
-        double s1r[N], s1i[N], s2r[N], s2i[N], zr[NN], zi[NN];
-        static_for<0, N>([&](auto k) { s1r[k] = vr[k]; s1i[k] = vi[k]; s2r[k] = vr[N + k]; s2i[k] = vi[N + k]; });
-        z_inverse<NN, double>(s1r, s1i, s2r, s2i, zr, zi);
+        double zr[NN], zi[NN];
+        z_inverse<NN, double>(vr, vi, zr, zi);
         const double hx = prefH * eh[zx];
         const double g1 = hx * eh[NN + zyp], g2 = hx * eh[NN + zyp + N];
         float qr[NN], qi[NN];
@@ -370,13 +347,23 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
           qr[z] = float(zr[z] * (g1 * ez));
           qi[z] = float(zi[z] * (g2 * ez));
         });
-        float t1r[N], t1i[N], t2r[N], t2i[N];
-        z_forward<NN, float>(qr, qi, t1r, t1i, t2r, t2i);
-        static_for<0, N>([&](auto k) { fr[k] = t1r[k]; fi[k] = t1i[k]; fr[N + k] = t2r[k]; fi[N + k] = t2i[k]; });
+        z_forward<NN, float>(qr, qi, fr, fi);
       }
-      z_to_x<NN, float, float>(fr, fi, lds, t);
+      if (j + 1 < J) {   // next node's tables, consumed after the next loop-top barrier
+        const float* K1 = Kh + ((size_t)cc * J + j + 1) * P3;
+        const float* P1 = Phi + (size_t)(j + 1) * Q;
+        static_for<0, C::KPRE>([&](auto i) {
+          const int q = t + i * C::T;
+          kpre[i] = q < P3 ? K1[q] : 0.f;
+        });
+        static_for<0, C::PPRE>([&](auto i) {
+          const int q = t + i * C::T;
+          ppre[i] = q < Q ? P1[q] : 0.f;
+        });
+      }
+      z_to_x<NN, float>(fr, fi, lds, t);
       fft<NN, false>(fr, fi);
-      transpose_plane<NN, 1, float, float>(fr, fi, lds, t);
+      transpose_plane<NN, float>(fr, fi, lds, t);
       fft<NN, false>(fr, fi);
       mode_multiply<NN, float>(fr, fi, t, [&](auto ky) {       // Phi_j / n^3
         constexpr int fy = ky <= N ? ky : NN - ky;
@@ -390,13 +377,12 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     }
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
     fft<NN, true>(Lr, Li);
-    transpose_plane<NN, 1, float, float>(Lr, Li, lds, t);
+    transpose_plane<NN, float>(Lr, Li, lds, t);
     fft<NN, true>(Lr, Li);
-    x_to_z<NN, 1, float, float>(Lr, Li, lds, t);
+    x_to_z<NN, float>(Lr, Li, lds, t);
     {
-      float s1r[N], s1i[N], s2r[N], s2i[N], zr[NN], zi[NN];
-      static_for<0, N>([&](auto k) { s1r[k] = Lr[k]; s1i[k] = Li[k]; s2r[k] = Lr[N + k]; s2i[k] = Li[N + k]; });
-      z_inverse<NN, float>(s1r, s1i, s2r, s2i, zr, zi);
+      float zr[NN], zi[NN];
+      z_inverse<NN, float>(Lr, Li, zr, zi);
       float* o1 = out + ((size_t)cell * NP + col1) * NN;
       float* o2 = o1 + (size_t)N * NN;
       static_for<0, NN>([&](auto z) {
@@ -408,7 +394,6 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
 }
 
 bool fused_supported(int n, int dtype) { return dtype == 1 && (n == 16 || n == 32); }
-
 
 size_t fused_scratch_bytes(int n, int nslots) {
   return (size_t)nslots * (n / 2) * n * n * sizeof(double2);
@@ -429,8 +414,6 @@ hipError_t fused_apply(const ApplyCtx& c) {
   const int slots = fused_slots(c.n, c.batch);
   const float* h = static_cast<const float*>(c.h);
   float* out = static_cast<float*>(c.out);
-  const double* fac64 = c.fac64;
-  const double* pref64 = c.pref64;
   const float* Kh = static_cast<const float*>(c.Kh);
   const float* nu = static_cast<const float*>(c.nu);
   const float* Phi = static_cast<const float*>(c.Phi);
@@ -438,12 +421,12 @@ hipError_t fused_apply(const ApplyCtx& c) {
   double2* scr = static_cast<double2*>(c.R);
   switch (c.n) {
     case 16:
-      k_fused<16><<<slots, Cfg<16>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, fac64, pref64, c.mask, Kh, nu, Phi, Om,
-                                                       scr, c.J);
+      k_fused<16><<<slots, Cfg<16>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
+                                                       Phi, Om, scr, c.J);
       break;
     case 32:
-      k_fused<32><<<slots, Cfg<32>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, fac64, pref64, c.mask, Kh, nu, Phi, Om,
-                                                       scr, c.J);
+      k_fused<32><<<slots, Cfg<32>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
+                                                       Phi, Om, scr, c.J);
       break;
     default:
       return hipErrorInvalidValue;
