@@ -51,6 +51,20 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Copy count floats from global memory into LDS with the direct load-to-LDS
+// path (no registers involved): wave w moves 64-float chunks w, w + nw, ...
+// Completion is tracked by vmcnt; the caller waits for it and synchronises the
+// workgroup before the data is read.
+__device__ __forceinline__ void lds_dma(const float* src, float* dst, int count, int t, int nthreads) {
+  const int wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64, nw = nthreads / 64;
+  for (int c = wave; c * 64 < count; c += nw) {
+    const int q = c * 64 + lane;
+    if (q < count)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + q),
+                                       (__attribute__((address_space(3))) void*)(dst + c * 64), 4, 0, 0);
+  }
+}
+
 // ---- z stage: two real columns <-> their packed half spectra ------------------
 // forward: a, b real (as zr, zi) -> v[k] (column a) and v[N + k] (column b),
 // k < N; bin 0 holds (A(0), A(N)), bins 1..N-1 the complex A(k).
@@ -199,7 +213,12 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
   __shared__ float tab[Q];
   __shared__ float Ks[P3];
   const int t0 = threadIdx.x;
-  double2* Rs = scratch + (size_t)blockIdx.x * KP * NP;
+  // Scratch slot of this workgroup: R (KP*NP complex double) then the L+
+  // accumulator (KP*NP complex float).  Both are interleaved by thread
+  // (element i of thread t at i*T + t) so that each load or store
+  // instruction of a wave covers one contiguous segment.
+  double2* Rs = scratch + (size_t)blockIdx.x * (KP * NP + KP * NP / 2);
+  float4* Ac = reinterpret_cast<float4*>(Rs + KP * NP);
 
   for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
     const int cc = Bc > 1 ? cell : 0;
@@ -215,6 +234,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     for (int i = t; i < 6 * NN; i += C::T) fs[i] = fac64[(size_t)cc * 6 * NN + i];
     if (t < 2) fs[6 * NN + t] = pref64[2 * cc + t];
     for (int q = t; q < Q; q += C::T) tab[q] = Om[q];
+    lds_dma(Kh + (size_t)cc * J * P3, Ks, P3, t, C::T);   // K_0, waited for before the gain loop
     __syncthreads();
     // reciprocal factors of M for r = chi h / M (infinite where a factor
     // underflows; such points are outside the cutoff and never selected)
@@ -286,45 +306,23 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       fft<NN, false>(vr, vi);
       transpose_plane<NN, double>(vr, vi, lds, t);
       fft<NN, false>(vr, vi);
-      // store R: [kp][kx][ky], each thread's pencil contiguous (one base
-      // address, immediate offsets)
-      double2* rp = Rs + (size_t)(kp * NN + ia) * NN;
-      static_for<0, NN>([&](auto ky) { rp[ky] = double2{vr[ky], vi[ky]}; });
+      static_for<0, NN>([&](auto ky) { Rs[ky * C::T + t] = double2{vr[ky], vi[ky]}; });
     }
 
     // ---------------- gain loop ---------------------------------------------------
+    // The running sum of Phi_j Q_j lives in the scratch slot between nodes (it
+    // is loaded back only during the float part of a node, where registers are
+    // free); after the last node it stays in registers.
     float Lr[NN], Li[NN];
-    static_for<0, NN>([&](auto ky) { Lr[ky] = 0.f; Li[ky] = 0.f; });
-    float kpre[C::KPRE], ppre[C::PPRE];
-    {
-      const float* K0 = Kh + (size_t)cc * J * P3;
-      static_for<0, C::KPRE>([&](auto i) {
-        const int q = t + i * C::T;
-        kpre[i] = q < P3 ? K0[q] : 0.f;
-      });
-      static_for<0, C::PPRE>([&](auto i) {
-        const int q = t + i * C::T;
-        ppre[i] = q < Q ? Phi[q] : 0.f;
-      });
-    }
+    __builtin_amdgcn_s_waitcnt(0x0f70);     // vmcnt(0): K_0 has landed
+    __syncthreads();
     for (int j = 0; j < J; ++j) {
       asm volatile("" : "+v"(t));
-      __syncthreads();
-      static_for<0, C::KPRE>([&](auto i) {
-        const int q = t + i * C::T;
-        if (q < P3) Ks[q] = kpre[i];
-      });
-      static_for<0, C::PPRE>([&](auto i) {
-        const int q = t + i * C::T;
-        if (q < Q) tab[q] = ppre[i];
-      });
-      __syncthreads();
       float fr[NN], fi[NN];
       {
         double vr[NN], vi[NN];
-        const double2* rp = Rs + (size_t)(kp * NN + ia) * NN;
         static_for<0, NN>([&](auto ky) {
-          const double2 v = rp[ky];
+          const double2 v = Rs[ky * C::T + t];
           vr[ky] = v.x;
           vi[ky] = v.y;
         });
@@ -336,6 +334,11 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         transpose_plane<NN, double>(vr, vi, lds, t);
         fft<NN, true>(vr, vi);
         x_to_z<NN, double>(vr, vi, lds, t);
+        // Every wave has used K_j and Phi_{j-1} by now: stream K_{j+1} and
+        // Phi_j into LDS while the z stage runs.  Both are complete and
+        // visible after the wait and first barrier of the next X <- Z exchange.
+        if (j + 1 < J) lds_dma(Kh + ((size_t)cc * J + j + 1) * P3, Ks, P3, t, C::T);
+        lds_dma(Phi + (size_t)j * Q, tab, Q, t, C::T);
         // psi on the two columns, times M^h; float from here on
         double zr[NN], zi[NN];
         z_inverse<NN, double>(vr, vi, zr, zi);
@@ -349,19 +352,10 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         });
         z_forward<NN, float>(qr, qi, fr, fi);
       }
-      if (j + 1 < J) {   // next node's tables, consumed after the next loop-top barrier
-        const float* K1 = Kh + ((size_t)cc * J + j + 1) * P3;
-        const float* P1 = Phi + (size_t)(j + 1) * Q;
-        static_for<0, C::KPRE>([&](auto i) {
-          const int q = t + i * C::T;
-          kpre[i] = q < P3 ? K1[q] : 0.f;
-        });
-        static_for<0, C::PPRE>([&](auto i) {
-          const int q = t + i * C::T;
-          ppre[i] = q < Q ? P1[q] : 0.f;
-        });
-      }
+      __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
       z_to_x<NN, float>(fr, fi, lds, t);
+      float4 acc[NN / 2];
+      static_for<0, NN / 2>([&](auto c) { acc[c] = j > 0 ? Ac[c * C::T + t] : float4{0.f, 0.f, 0.f, 0.f}; });
       fft<NN, false>(fr, fi);
       transpose_plane<NN, float>(fr, fi, lds, t);
       fft<NN, false>(fr, fi);
@@ -370,10 +364,16 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         const int q = fx * fx + fy * fy;
         return float2{tab[q + kp * kp], tab[q + N * N]};
       });
-      static_for<0, NN>([&](auto ky) {
-        Lr[ky] += fr[ky];
-        Li[ky] += fi[ky];
+      static_for<0, NN / 2>([&](auto c) {
+        Lr[2 * c] = acc[c].x + fr[2 * c];
+        Li[2 * c] = acc[c].y + fi[2 * c];
+        Lr[2 * c + 1] = acc[c].z + fr[2 * c + 1];
+        Li[2 * c + 1] = acc[c].w + fi[2 * c + 1];
       });
+      if (j + 1 < J)
+        static_for<0, NN / 2>([&](auto c) {
+          Ac[c * C::T + t] = float4{Lr[2 * c], Li[2 * c], Lr[2 * c + 1], Li[2 * c + 1]};
+        });
     }
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
     fft<NN, true>(Lr, Li);
@@ -396,7 +396,8 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
 bool fused_supported(int n, int dtype) { return dtype == 1 && (n == 16 || n == 32); }
 
 size_t fused_scratch_bytes(int n, int nslots) {
-  return (size_t)nslots * (n / 2) * n * n * sizeof(double2);
+  // per slot: R (complex double) and the L+ accumulator (complex float)
+  return (size_t)nslots * (n / 2) * n * n * (sizeof(double2) + sizeof(float2));
 }
 
 int fused_slots(int n, int batch) {
