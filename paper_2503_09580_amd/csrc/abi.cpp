@@ -21,7 +21,7 @@ struct lincoll_plan_s {
   int last_hip = 0;
   size_t bytes = 0;
   // plan tables
-  void* d_Phi = nullptr;      // [J][Q] apply dtype, / n^3
+  void* d_Phi = nullptr;      // [J][phi_stride(n)] apply dtype, / n^3
   void* d_Om = nullptr;       // [Q]    apply dtype, / n^3
   double* d_Om64 = nullptr;   // [Q]    FP64, / n^3
   double* d_phi = nullptr;    // [J][P^3]
@@ -126,7 +126,7 @@ int ensure_cells(lincoll_plan_t pl, int B) {
       (e = dalloc(pl, &pl->d_Ainv, (size_t)B * 25 * sizeof(double))) ||
       (e = dalloc(pl, &pl->d_facT, (size_t)B * 6 * n * es)) || (e = dalloc(pl, &pl->d_prefT, (size_t)B * 2 * es)) ||
       (e = dalloc(pl, &pl->d_mask, (size_t)B * n * n * MW * sizeof(uint32_t))) ||
-      (e = dalloc(pl, &pl->d_Kh, (size_t)B * J * P3 * es)) || (e = dalloc(pl, &pl->d_nu, (size_t)B * n3 * es)))
+      (e = dalloc(pl, &pl->d_Kh, (size_t)B * J * kh_stride(n) * es)) || (e = dalloc(pl, &pl->d_nu, (size_t)B * n3 * es)))
     return hip_fail(pl, e);
   pl->cap_cells = B;
   // setup scratch: chunks of cells bounded to ~256 MiB per buffer
@@ -286,8 +286,10 @@ int lincoll_plan_ex(const lincoll_params_t* pin, lincoll_plan_t* out) {
   }
   const int n = pl->p.n, P = n / 2 + 1, J = pl->t.J, Q = pl->t.Q;
   const double s3 = 1.0 / ((double)n * n * n);
-  std::vector<double> phis(pl->t.Phi), oms(pl->t.Omega);
-  for (auto& v : phis) v *= s3;
+  const int QS = phi_stride(n);
+  std::vector<double> phis((size_t)J * QS, 0.0), oms(pl->t.Omega);
+  for (int j = 0; j < J; ++j)
+    for (int q = 0; q < Q; ++q) phis[(size_t)j * QS + q] = pl->t.Phi[(size_t)j * Q + q] * s3;
   for (auto& v : oms) v *= s3;
   const size_t es = esize(pl->p.dtype);
   auto upload = [&](void* dst, const std::vector<double>& src, bool asf) -> hipError_t {
@@ -296,7 +298,7 @@ int lincoll_plan_ex(const lincoll_params_t* pin, lincoll_plan_t* out) {
     return hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
   };
   const bool asf = pl->p.dtype != LINCOLL_F64;
-  if ((e = dalloc(pl, &pl->d_Phi, (size_t)J * Q * es)) || (e = dalloc(pl, &pl->d_Om, (size_t)Q * es)) ||
+  if ((e = dalloc(pl, &pl->d_Phi, (size_t)J * QS * es)) || (e = dalloc(pl, &pl->d_Om, (size_t)Q * es)) ||
       (e = dalloc(pl, &pl->d_Om64, (size_t)Q * sizeof(double))) ||
       (e = dalloc(pl, &pl->d_phi, (size_t)J * P * P * P * sizeof(double))) ||
       (e = dalloc(pl, &pl->d_Cdct, (size_t)P * P * sizeof(double))) || (e = upload(pl->d_Phi, phis, asf)) ||

@@ -41,8 +41,6 @@ struct Cfg {
   static constexpr int MW = (NN + 31) / 32;
   static constexpr int LD = NN + 1;            // padded LDS row
   static constexpr int LDS_BYTES = KP * NN * LD * 8;   // one float2 volume
-  static constexpr int KPRE = (P3 + T - 1) / T;        // K_j values per thread
-  static constexpr int PPRE = (Q + T - 1) / T;         // Phi_j values per thread
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -234,7 +232,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     for (int i = t; i < 6 * NN; i += C::T) fs[i] = fac64[(size_t)cc * 6 * NN + i];
     if (t < 2) fs[6 * NN + t] = pref64[2 * cc + t];
     for (int q = t; q < Q; q += C::T) tab[q] = Om[q];
-    lds_dma(Kh + (size_t)cc * J * P3, Ks, P3, t, C::T);   // K_0, waited for before the gain loop
+    lds_dma(Kh + (size_t)cc * J * kh_stride(NN), Ks, P3, t, C::T);   // K_0, waited for before the gain loop
     __syncthreads();
     // reciprocal factors of M for r = chi h / M (infinite where a factor
     // underflows; such points are outside the cutoff and never selected)
@@ -337,8 +335,8 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         // Every wave has used K_j and Phi_{j-1} by now: stream K_{j+1} and
         // Phi_j into LDS while the z stage runs.  Both are complete and
         // visible after the wait and first barrier of the next X <- Z exchange.
-        if (j + 1 < J) lds_dma(Kh + ((size_t)cc * J + j + 1) * P3, Ks, P3, t, C::T);
-        lds_dma(Phi + (size_t)j * Q, tab, Q, t, C::T);
+        if (j + 1 < J) lds_dma(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), Ks, P3, t, C::T);
+        lds_dma(Phi + (size_t)j * phi_stride(NN), tab, Q, t, C::T);
         // psi on the two columns, times M^h; float from here on
         double zr[NN], zi[NN];
         z_inverse<NN, double>(vr, vi, zr, zi);

@@ -6,6 +6,13 @@
 
 namespace lincoll {
 
+// Row strides of the device mode tables (K_j octants and Phi_j radial
+// tables), padded to whole blocks of 512 values so that the fused kernel copies
+// a row into LDS with the same fixed number of load instructions per wave.
+constexpr int pad512(int x) { return (x + 511) / 512 * 512; }
+constexpr int kh_stride(int n) { return pad512((n / 2 + 1) * (n / 2 + 1) * (n / 2 + 1)); }
+constexpr int phi_stride(int n) { return pad512(3 * (n / 2) * (n / 2) + 1); }
+
 // Everything one staged or fused apply needs (raw device pointers; element
 // type is double for dtype 0 and float otherwise; complex = interleaved).
 struct ApplyCtx {
@@ -15,14 +22,14 @@ struct ApplyCtx {
   hipStream_t stream = nullptr;
   const void* h = nullptr;
   void* out = nullptr;
-  const void* Phi = nullptr;   // [J][Q]  Phi_j(|k|^2) / n^3
+  const void* Phi = nullptr;   // [J][phi_stride(n)]  Phi_j(|k|^2) / n^3
   const void* Om = nullptr;    // [Q]     Omega(|k|^2) / n^3
   const void* fac = nullptr;   // [Bc][6][n]: exp(-(v-u_d)^2/(2 theta)), d = 1..3; then exp(-(v-u_d)^2/theta)
   const void* pref = nullptr;  // [Bc][2]: rho (2 pi theta)^-3/2, rho (pi theta)^-3/2
   const double* fac64 = nullptr;   // the same two in FP64
   const double* pref64 = nullptr;
   const uint32_t* mask = nullptr;  // [Bc][n*n][(n+31)/32] cutoff bits along z
-  const void* Kh = nullptr;    // [Bc][J][P][P][P]  K_j / n^3 on the octant, P = n/2+1
+  const void* Kh = nullptr;    // [Bc][J][kh_stride(n)]  K_j / n^3 on the octant [P][P][P], P = n/2+1
   const void* nu = nullptr;    // [Bc][n^3]
   void* R = nullptr;           // work, complex [batch][P][n][n] each; R and W in double
   void* H = nullptr;
@@ -49,7 +56,7 @@ struct SetupCtx {
   void* facT = nullptr;            // copies in the apply dtype
   void* prefT = nullptr;
   uint32_t* mask = nullptr;
-  void* Kh = nullptr;              // [Bc][J][P^3] apply dtype
+  void* Kh = nullptr;              // [Bc][J][kh_stride(n)] apply dtype (octant [P][P][P] first)
   void* nu = nullptr;              // [Bc][n^3] apply dtype
   double* tmpA = nullptr;          // scratch, [chunk][J][P^3] FP64 each
   double* tmpB = nullptr;

@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(256) k_kh_pass(const double* __restrict__ in, 
     for (int k = 0; k < P; ++k) acc[k] += Cm[k * P + a] * x;
   }
   if (LAST) {
-    T* out = static_cast<T*>(outv) + (size_t)cj * P3 + (size_t)bc * P;
+    T* out = static_cast<T*>(outv) + (size_t)cj * kh_stride(2 * (P - 1)) + (size_t)bc * P;
 #pragma unroll
     for (int k = 0; k < P; ++k) out[k] = static_cast<T>(acc[k] * scale);
   } else {
@@ -168,7 +168,7 @@ static hipError_t kh_chunk(const SetupCtx& c, int c0, int nc) {
   const double scale = 1.0 / ((double)c.n * c.n * c.n);
   const double* gf = c.gfac64 + (size_t)c0 * P;
   const double* pr = c.pref64 + (size_t)c0 * 2;
-  T* Kh = static_cast<T*>(c.Kh) + (size_t)c0 * c.J * P * P * P;
+  T* Kh = static_cast<T*>(c.Kh) + (size_t)c0 * c.J * kh_stride(c.n);
   k_kh_pass<P, true, false, T><<<grid, 256, 0, c.stream>>>(nullptr, c.tmpA, c.phi, gf, pr, c.Cdct, c.J, nc, 1.0);
   k_kh_pass<P, false, false, T><<<grid, 256, 0, c.stream>>>(c.tmpA, c.tmpB, c.phi, gf, pr, c.Cdct, c.J, nc, 1.0);
   k_kh_pass<P, false, true, T><<<grid, 256, 0, c.stream>>>(c.tmpB, Kh, c.phi, gf, pr, c.Cdct, c.J, nc, scale);

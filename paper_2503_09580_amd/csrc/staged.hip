@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, type
       vi[k1] = T(v.y);
     });
     if constexpr (PRE == 1) {
-      const TS* K = Kh + ((size_t)cc * J + j) * P * P * P + (size_t)kz * P * P + fold<NN>(a);
+      const TS* K = Kh + ((size_t)cc * J + j) * kh_stride(NN) + (size_t)kz * P * P + fold<NN>(a);
       static_for<0, NN>([&](auto k1) {
         const T kv = T(K[fold<NN>(k1) * P]);
         vr[k1] *= kv;
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, type
   if (!active) return;
   C* dst = out + (size_t)pid * NP + a;
   if constexpr (POST >= 1) {
-    const TS* tj = table + (size_t)j * (3 * (NN / 2) * (NN / 2) + 1);
+    const TS* tj = table + (size_t)j * phi_stride(NN);
     const int fa = fold<NN>(a);
     const int qb = fa * fa + kz * kz;
     static_for<0, NN>([&](auto k1) {
