@@ -116,8 +116,40 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_DEVICE_BYTES 6  /* device memory held by the plan */
 #define LINCOLL_INFO_HIP_ERROR 7     /* last hipError_t seen (0 if none) */
 #define LINCOLL_INFO_EPS 8
+#define LINCOLL_INFO_GRAPH 9         /* 1 if applies replay a captured graph (LINCOLL_OPT_GRAPH) */
+#define LINCOLL_INFO_FUSED_PER_CU 10 /* fused-path workgroups per compute unit in effect */
+#define LINCOLL_INFO_TUNED_MS 11     /* ms per apply of the configuration lincoll_autotune chose (0 if never run) */
 /* Reads one plan property into *val. */
 int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
+
+/* Execution options (batching row of the design: launch shape and launch
+ * mechanism of the persistent path).  Every change drops a captured graph.
+ *   LINCOLL_OPT_GRAPH        0 | 1.  With 1, an apply records its launches
+ *                            once into a hipGraph (kernel nodes only, on a
+ *                            stream the plan owns) and replays it with one
+ *                            hipGraphLaunch on the plan's stream for as long
+ *                            as h, out, batch, the Maxwellian batch, the
+ *                            options and the plan's buffers stay the same;
+ *                            otherwise it records again.  Leave it 0 when
+ *                            the caller captures lincoll_apply into a graph
+ *                            of its own.
+ *   LINCOLL_OPT_FUSED_PER_CU workgroups of the fused path per compute unit:
+ *                            0 = default (the maximum), n = 16: 1..4,
+ *                            n = 32: 1.
+ *   LINCOLL_OPT_PATH         a lincoll_path_t the plan's n and dtype support.
+ * Returns LINCOLL_EINVAL for an unknown key or an unsupported value. */
+#define LINCOLL_OPT_GRAPH 0
+#define LINCOLL_OPT_FUSED_PER_CU 1
+#define LINCOLL_OPT_PATH 2
+int lincoll_set_option(lincoll_plan_t plan, int key, int value);
+
+/* Launch-configuration tuner: times `reps` applies of every supported
+ * (path, workgroups per CU, graph on/off) on the caller's h/out/batch
+ * (after one warm-up each), keeps the fastest as the plan's configuration
+ * and records its time (LINCOLL_INFO_TUNED_MS).  Synchronises the plan's
+ * stream; out holds L[h] afterwards.  Same argument rules as lincoll_apply;
+ * reps in [1, 1000]. */
+int lincoll_autotune(lincoll_plan_t plan, const void* h, void* out, int batch, int reps);
 
 /* Releases everything the plan owns (waits for its stream first). */
 void lincoll_destroy(lincoll_plan_t plan);

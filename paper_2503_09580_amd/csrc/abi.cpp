@@ -45,13 +45,27 @@ struct lincoll_plan_s {
   double* d_planes64 = nullptr;
   // apply work
   int cap_work = 0, cap_pin = 0;
-  size_t fused_bytes = 0;
   void* d_R = nullptr;
   void* d_H = nullptr;
   void* d_W = nullptr;
   void* d_Wq = nullptr;
   void* d_Lp = nullptr;
   void* d_pin = nullptr;      // projected input when p.project
+  size_t R_bytes = 0;         // size of d_R (shared by the staged and fused paths)
+  int cus = 256;              // compute units of the plan's device
+  // options (lincoll_set_option)
+  int opt_graph = 0, opt_per_cu = 0;
+  double tuned_ms = 0.0;
+  // replayable graph of the last apply (opt_graph)
+  unsigned long alloc_gen = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphKey {
+    const void* h;
+    void* out;
+    int batch, Bc, fused, per_cu, project;
+    unsigned long gen;
+  } gkey{};
 };
 
 namespace {
@@ -71,6 +85,7 @@ hipError_t dalloc(lincoll_plan_t pl, P** ptr, size_t bytes) {
   }
   void* v = nullptr;
   hipError_t e = hipMalloc(&v, bytes);
+  ++pl->alloc_gen;   // device pointers changed: a captured graph is stale
   if (e == hipSuccess) {
     *ptr = static_cast<P*>(v);
     pl->bytes += bytes;
@@ -151,19 +166,20 @@ int ensure_work(lincoll_plan_t pl, int B) {
     pl->cap_pin = B;
   }
   if (use_fused(pl)) {
-    const size_t need = fused_scratch_bytes(n, fused_slots(n, B));
-    if (need > pl->fused_bytes) {
+    const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus));
+    if (need > pl->R_bytes) {
       if ((e = dalloc(pl, &pl->d_R, need))) return hip_fail(pl, e);
-      pl->fused_bytes = need;
+      pl->R_bytes = need;
       pl->cap_work = 0;
     }
     return LINCOLL_OK;
   }
-  if (B <= pl->cap_work && pl->d_R && pl->d_H) return LINCOLL_OK;
   const size_t vol = (size_t)B * P * n * n * 2 * es, vol64 = (size_t)B * P * n * n * 2 * sizeof(double);
+  if (B <= pl->cap_work && pl->d_H && pl->R_bytes >= vol64) return LINCOLL_OK;
   if ((e = dalloc(pl, &pl->d_R, vol64)) || (e = dalloc(pl, &pl->d_H, vol)) || (e = dalloc(pl, &pl->d_W, vol64)) ||
       (e = dalloc(pl, &pl->d_Wq, vol)) || (e = dalloc(pl, &pl->d_Lp, vol)))
     return hip_fail(pl, e);
+  pl->R_bytes = vol64;
   pl->cap_work = B;
   return LINCOLL_OK;
 }
@@ -279,6 +295,10 @@ int lincoll_plan_ex(const lincoll_params_t* pin, lincoll_plan_t* out) {
     return LINCOLL_EINVAL;
   }
   hipError_t e = hipGetDevice(&pl->device);
+  if (!e) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, pl->device) == hipSuccess && v > 0) pl->cus = v;
+  }
   if (e) {
     pl->last_hip = (int)e;
     delete pl;
@@ -346,39 +366,42 @@ int lincoll_set_maxwellians(lincoll_plan_t pl, const double* params, int batch) 
   return do_set_maxwellians(pl, params, batch);
 }
 
-int lincoll_project(lincoll_plan_t pl, const void* x, void* y, int batch) {
-  if (!pl || !x || !y || batch < 1) return LINCOLL_EINVAL;
-  if (pl->Bc != 1 && pl->Bc != batch) return LINCOLL_ENOTREADY;
+namespace {
+
+hipError_t launch_project(lincoll_plan_t pl, const void* x, void* y, int batch, hipStream_t stream) {
   ProjectCtx c;
   c.n = pl->p.n;
   c.batch = batch;
   c.Bc = pl->Bc;
   c.dtype = pl->p.dtype == LINCOLL_F64 ? 0 : 1;
   c.L = pl->p.L;
-  c.stream = pl->stream;
+  c.stream = stream;
   c.x = x;
   c.y = y;
   c.fac64 = pl->d_fac64;
   c.pref64 = pl->d_pref64;
   c.Ainv = pl->d_Ainv;
-  hipError_t e = project_cells(c);
+  return project_cells(c);
+}
+
+}  // namespace
+
+int lincoll_project(lincoll_plan_t pl, const void* x, void* y, int batch) {
+  if (!pl || !x || !y || batch < 1) return LINCOLL_EINVAL;
+  if (pl->Bc != 1 && pl->Bc != batch) return LINCOLL_ENOTREADY;
+  hipError_t e = launch_project(pl, x, y, batch, pl->stream);
   return e ? hip_fail(pl, e) : LINCOLL_OK;
 }
 
-int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
-  if (!pl || !h || !out || batch < 1) return LINCOLL_EINVAL;
-  if (pl->p.max_batch > 0 && batch > pl->p.max_batch) return LINCOLL_EINVAL;
-  const size_t bytes = (size_t)batch * pl->p.n * pl->p.n * pl->p.n * esize(pl->p.dtype);
-  const char* a = static_cast<const char*>(h);
-  const char* b = static_cast<const char*>(out);
-  if (a < b + bytes && b < a + bytes) return LINCOLL_EINVAL;   // overlap
-  if (pl->Bc != 1 && pl->Bc != batch) return LINCOLL_ENOTREADY;
-  int st = ensure_work(pl, batch);
-  if (st) return st;
+namespace {
+
+// Every launch of one apply, on `stream` (the plan's stream, or the capture
+// stream while a replayable graph is recorded).  Work buffers must exist.
+hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, hipStream_t stream) {
+  hipError_t e;
   const void* hin = h;
   if (pl->p.project) {
-    st = lincoll_project(pl, h, pl->d_pin, batch);
-    if (st) return st;
+    if ((e = launch_project(pl, h, pl->d_pin, batch, stream))) return e;
     hin = pl->d_pin;
   }
   ApplyCtx c;
@@ -387,8 +410,10 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
   c.Q = pl->t.Q;
   c.batch = batch;
   c.Bc = pl->Bc;
+  c.cus = pl->cus;
+  c.per_cu = pl->opt_per_cu;
   c.dtype = pl->p.dtype;
-  c.stream = pl->stream;
+  c.stream = stream;
   c.h = hin;
   c.out = out;
   c.Phi = pl->d_Phi;
@@ -405,9 +430,152 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
   c.W = pl->d_W;
   c.Wq = pl->d_Wq;
   c.Lp = pl->d_Lp;
-  hipError_t e = use_fused(pl) ? fused_apply(c) : staged_apply(c);
-  if (e) return hip_fail(pl, e);
-  if (pl->p.project) return lincoll_project(pl, out, out, batch);
+  if ((e = use_fused(pl) ? fused_apply(c) : staged_apply(c))) return e;
+  if (pl->p.project) return launch_project(pl, out, out, batch, stream);
+  return hipSuccess;
+}
+
+void drop_graph(lincoll_plan_t pl) {
+  if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+  pl->gexec = nullptr;
+}
+
+// Records the launches of one apply into a graph on the plan's own capture
+// stream and instantiates it; later applies with the same key replay it with
+// a single hipGraphLaunch.  The graph holds kernel nodes only.
+hipError_t capture_apply(lincoll_plan_t pl, const void* h, void* out, int batch,
+                         const lincoll_plan_s::GraphKey& key) {
+  drop_graph(pl);
+  hipError_t e;
+  if (!pl->cap_stream && (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking))) return e;
+  if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal))) return e;
+  const hipError_t el = launch_apply(pl, h, out, batch, pl->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(pl->cap_stream, &g);
+  if (el) e = el;
+  if (!e) e = hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e) {
+    pl->gexec = nullptr;
+    return e;
+  }
+  pl->gkey = key;
+  return hipSuccess;
+}
+
+int checked_apply_args(lincoll_plan_t pl, const void* h, void* out, int batch) {
+  if (!pl || !h || !out || batch < 1) return LINCOLL_EINVAL;
+  if (pl->p.max_batch > 0 && batch > pl->p.max_batch) return LINCOLL_EINVAL;
+  const size_t bytes = (size_t)batch * pl->p.n * pl->p.n * pl->p.n * esize(pl->p.dtype);
+  const char* a = static_cast<const char*>(h);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return LINCOLL_EINVAL;   // overlap
+  if (pl->Bc != 1 && pl->Bc != batch) return LINCOLL_ENOTREADY;
+  return LINCOLL_OK;
+}
+
+}  // namespace
+
+int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
+  int st = checked_apply_args(pl, h, out, batch);
+  if (st) return st;
+  if ((st = ensure_work(pl, batch))) return st;
+  hipError_t e;
+  if (!pl->opt_graph) {
+    if ((e = launch_apply(pl, h, out, batch, pl->stream))) return hip_fail(pl, e);
+    return LINCOLL_OK;
+  }
+  const lincoll_plan_s::GraphKey key{h, out, batch, pl->Bc, use_fused(pl) ? 1 : 0, pl->opt_per_cu, pl->p.project,
+                                     pl->alloc_gen};
+  const lincoll_plan_s::GraphKey& k = pl->gkey;
+  const bool same = pl->gexec && k.h == key.h && k.out == key.out && k.batch == key.batch && k.Bc == key.Bc &&
+                    k.fused == key.fused && k.per_cu == key.per_cu && k.project == key.project && k.gen == key.gen;
+  if (!same && (e = capture_apply(pl, h, out, batch, key))) return hip_fail(pl, e);
+  if ((e = hipGraphLaunch(pl->gexec, pl->stream))) return hip_fail(pl, e);
+  return LINCOLL_OK;
+}
+
+int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
+  if (!pl) return LINCOLL_EINVAL;
+  switch (key) {
+    case LINCOLL_OPT_GRAPH:
+      if (value != 0 && value != 1) return LINCOLL_EINVAL;
+      pl->opt_graph = value;
+      break;
+    case LINCOLL_OPT_FUSED_PER_CU:
+      if (value < 0 || value > fused_max_per_cu(pl->p.n)) return LINCOLL_EINVAL;
+      pl->opt_per_cu = value;
+      break;
+    case LINCOLL_OPT_PATH:
+      if (value < LINCOLL_PATH_AUTO || value > LINCOLL_PATH_FUSED) return LINCOLL_EINVAL;
+      if (value == LINCOLL_PATH_FUSED && !fused_supported(pl->p.n, pl->p.dtype)) return LINCOLL_EINVAL;
+      if (value == LINCOLL_PATH_STAGED && !staged_supported(pl->p.n, pl->p.dtype)) return LINCOLL_EINVAL;
+      pl->p.path = value;
+      break;
+    default:
+      return LINCOLL_EINVAL;
+  }
+  drop_graph(pl);
+  return LINCOLL_OK;
+}
+
+int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int reps) {
+  int st = checked_apply_args(pl, h, out, batch);
+  if (st) return st;
+  if (reps < 1 || reps > 1000) return LINCOLL_EINVAL;
+  struct Cand {
+    int path, per_cu, graph;
+  };
+  Cand cands[2 * 2 * 8];
+  int nc = 0;
+  const int n = pl->p.n, dt = pl->p.dtype;
+  for (int g = 0; g < 2; ++g) {
+    if (staged_supported(n, dt)) cands[nc++] = {LINCOLL_PATH_STAGED, 0, g};
+    if (fused_supported(n, dt))
+      for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) cands[nc++] = {LINCOLL_PATH_FUSED, pc, g};
+  }
+  if (nc == 0) return LINCOLL_EINVAL;
+  const int saved_path = pl->p.path, saved_pc = pl->opt_per_cu, saved_graph = pl->opt_graph;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(pl, e);
+  }
+  double best = 1e300;
+  int bi = -1;
+  for (int i = 0; i < nc && !st; ++i) {
+    pl->p.path = cands[i].path;
+    pl->opt_per_cu = cands[i].per_cu;
+    pl->opt_graph = cands[i].graph;
+    drop_graph(pl);
+    if ((st = lincoll_apply(pl, h, out, batch))) break;   // warm-up (allocates, captures)
+    if ((e = hipEventRecord(e0, pl->stream))) { st = hip_fail(pl, e); break; }
+    for (int r = 0; r < reps && !st; ++r) st = lincoll_apply(pl, h, out, batch);
+    if (st) break;
+    float ms = 0.f;
+    if ((e = hipEventRecord(e1, pl->stream)) || (e = hipEventSynchronize(e1)) || (e = hipEventElapsedTime(&ms, e0, e1))) {
+      st = hip_fail(pl, e);
+      break;
+    }
+    if (ms / reps < best) {
+      best = ms / reps;
+      bi = i;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop_graph(pl);
+  if (st || bi < 0) {
+    pl->p.path = saved_path;
+    pl->opt_per_cu = saved_pc;
+    pl->opt_graph = saved_graph;
+    return st ? st : LINCOLL_EINVAL;
+  }
+  pl->p.path = cands[bi].path;
+  pl->opt_per_cu = cands[bi].per_cu;
+  pl->opt_graph = cands[bi].graph;
+  pl->tuned_ms = best;
   return LINCOLL_OK;
 }
 
@@ -428,6 +596,11 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_DEVICE_BYTES: *val = (double)pl->bytes; break;
     case LINCOLL_INFO_HIP_ERROR: *val = pl->last_hip; break;
     case LINCOLL_INFO_EPS: *val = pl->p.eps; break;
+    case LINCOLL_INFO_GRAPH: *val = pl->opt_graph; break;
+    case LINCOLL_INFO_FUSED_PER_CU:
+      *val = pl->opt_per_cu > 0 ? pl->opt_per_cu : fused_max_per_cu(pl->p.n);
+      break;
+    case LINCOLL_INFO_TUNED_MS: *val = pl->tuned_ms; break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;
@@ -436,6 +609,8 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
 void lincoll_destroy(lincoll_plan_t pl) {
   if (!pl) return;
   (void)hipStreamSynchronize(pl->stream);
+  drop_graph(pl);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   void* ptrs[] = {pl->d_Phi,  pl->d_Om,    pl->d_Om64,  pl->d_phi,  pl->d_Cdct, pl->d_params, pl->d_fac64,
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
                   pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin};

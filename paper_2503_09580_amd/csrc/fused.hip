@@ -398,19 +398,19 @@ size_t fused_scratch_bytes(int n, int nslots) {
   return (size_t)nslots * (n / 2) * n * n * (sizeof(double2) + sizeof(float2));
 }
 
-int fused_slots(int n, int batch) {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-  }
-  const int per_cu = n == 16 ? 4 : 1;
-  const int slots = cus * per_cu;
+// Workgroups resident per compute unit: n = 32 needs all of a CU's LDS, the
+// n = 16 workgroup (two waves, 22 KB of LDS, up to 256 registers) fits four
+// times by registers.
+int fused_max_per_cu(int n) { return n == 16 ? 4 : 1; }
+
+int fused_slots(int n, int batch, int per_cu, int cus) {
+  const int pc = per_cu > 0 && per_cu <= fused_max_per_cu(n) ? per_cu : fused_max_per_cu(n);
+  const int slots = (cus > 0 ? cus : 256) * pc;
   return batch < slots ? batch : slots;
 }
 
 hipError_t fused_apply(const ApplyCtx& c) {
-  const int slots = fused_slots(c.n, c.batch);
+  const int slots = fused_slots(c.n, c.batch, c.per_cu, c.cus);
   const float* h = static_cast<const float*>(c.h);
   float* out = static_cast<float*>(c.out);
   const float* Kh = static_cast<const float*>(c.Kh);

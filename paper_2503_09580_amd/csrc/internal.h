@@ -18,6 +18,8 @@ constexpr int phi_stride(int n) { return pad512(3 * (n / 2) * (n / 2) + 1); }
 struct ApplyCtx {
   int n = 0, J = 0, Q = 0;
   int batch = 0, Bc = 0;       // cells in this call; cells in the Maxwellian cache (1 = broadcast)
+  int cus = 256;               // compute units of the device
+  int per_cu = 0;              // fused path: workgroups per compute unit (0 = default)
   int dtype = 0;
   hipStream_t stream = nullptr;
   const void* h = nullptr;
@@ -82,6 +84,7 @@ bool staged_supported(int n, int dtype);
 bool fused_supported(int n, int dtype);
 hipError_t fused_apply(const ApplyCtx& c);
 size_t fused_scratch_bytes(int n, int nslots);
-int fused_slots(int n, int batch);
+int fused_max_per_cu(int n);
+int fused_slots(int n, int batch, int per_cu, int cus);
 
 }  // namespace lincoll

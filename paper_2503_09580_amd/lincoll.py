@@ -18,10 +18,12 @@ DTYPES = {"f64": 0, "f32": 1, "bf16x3": 2}
 PATHS = {"auto": 0, "staged": 1, "fused": 2}
 TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
 INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
-        "hip_error": 7, "eps": 8}
+        "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11}
+OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2}
 SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
            "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
-           "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables"]
+           "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",
+           "lincoll_set_option", "lincoll_autotune"]
 
 
 class LincollError(RuntimeError):
@@ -56,6 +58,8 @@ def _load():
         "lincoll_destroy": (None, [vp]),
         "lincoll_strerror": (ctypes.c_char_p, [i]),
         "lincoll_plan_tables": (ctypes.c_longlong, [P(Params), i, P(d), ctypes.c_longlong]),
+        "lincoll_set_option": (i, [vp, i, i]),
+        "lincoll_autotune": (i, [vp, vp, vp, i, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -164,6 +168,23 @@ class Plan:
         _check(_lib.lincoll_project(self._h, self._dev(x, self.tdtype, (n, n, n), "x"),
                                     self._dev(y, self.tdtype, (n, n, n), "y"), x.shape[0]), "lincoll_project")
         return y
+
+    def set_option(self, key, value):
+        """key: "graph" (0|1), "fused_per_cu" (0 = default), "path" ("auto"|"staged"|"fused")."""
+        v = PATHS[value] if key == "path" else int(value)
+        _check(_lib.lincoll_set_option(self._h, OPTIONS[key], v), "lincoll_set_option")
+
+    def autotune(self, h, out=None, reps=3):
+        """Times every supported launch configuration on (h, out) and keeps the
+        fastest; returns its milliseconds per apply.  out receives L[h]."""
+        n = self.n
+        if out is None:
+            out = self._torch.empty_like(h)
+        self._sync_stream()
+        _check(_lib.lincoll_autotune(self._h, self._dev(h, self.tdtype, (n, n, n), "h"),
+                                     self._dev(out, self.tdtype, (n, n, n), "out"), h.shape[0], int(reps)),
+               "lincoll_autotune")
+        return self.info("tuned_ms")
 
     def info(self, key):
         v = ctypes.c_double()

@@ -1,0 +1,146 @@
+"""Launch mechanics of the persistent path: graph replay, workgroups per CU
+and the launch-configuration tuner, through the C ABI.
+
+A replayed graph must give exactly the eager result (same kernels, same
+order), on every replay, with unrelated eager GPU work and synchronisations
+between the replays, and it must be re-recorded when the buffers, the batch
+or the plan's allocations change.  Tuned configurations must still meet the
+FP32 bar against the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import alg1, fast_direct as fd
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
+from test_gpu_parity import mixed_inputs, rel  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def eager_result(n, L, om, dtype, path, h, params, **opts):
+    td = torch.float64 if dtype == "f64" else torch.float32
+    plan = lc.Plan(n, L, om, dtype, path=path)
+    for k, v in opts.items():
+        plan.set_option(k, v)
+    plan.set_maxwellians(dev(params, torch.float64))
+    out = plan.apply(dev(h, td))
+    torch.cuda.synchronize()
+    return out.cpu()
+
+
+def busy_work():
+    """Unrelated eager GPU work between graph replays."""
+    a = torch.randn(512, 512, device=DEV)
+    b = (a @ a.T).sum()
+    other = lc.Plan(8, 4.0, 1.0, "f64")
+    x = torch.randn(3, 8, 8, 8, dtype=torch.float64, device=DEV)
+    other.apply(x)
+    torch.cuda.synchronize()
+    return float(b)
+
+
+@pytest.mark.parametrize("n,dtype,path,batch", [(16, "f64", "staged", 5), (32, "f32", "fused", 9),
+                                                (32, "f32", "staged", 4), (16, "f32", "fused", 11)])
+def test_graph_replay_is_bitwise_eager(n, dtype, path, batch):
+    L, om = 8.0, 0.74
+    td = torch.float64 if dtype == "f64" else torch.float32
+    h, params = mixed_inputs(n, L, batch, seed=700 + n + batch)
+    ref = eager_result(n, L, om, dtype, path, h, params)
+    plan = lc.Plan(n, L, om, dtype, path=path)
+    plan.set_option("graph", 1)
+    assert plan.info("graph") == 1
+    plan.set_maxwellians(dev(params, torch.float64))
+    ht = dev(h, td)
+    out = torch.empty_like(ht)
+    for rep in range(4):
+        out.fill_(float("nan"))
+        plan.apply(ht, out)          # first call records, later calls replay
+        torch.cuda.synchronize()
+        assert torch.equal(out.cpu(), ref), (rep, "replay differs from the eager apply")
+        busy_work()
+    # a different output buffer is recorded again
+    out2 = torch.empty_like(ht)
+    plan.apply(ht, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out2.cpu(), ref)
+    # new Maxwellians of the same batch: same buffers, the replay reads them
+    params2 = params.copy()
+    params2[:, 4] *= 1.1
+    plan.set_maxwellians(dev(params2, torch.float64))
+    plan.apply(ht, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out2.cpu(), eager_result(n, L, om, dtype, path, h, params2))
+
+
+def test_graph_rerecords_after_reallocation():
+    """A larger batch reallocates the plan's buffers; the replay must not use
+    the old pointers."""
+    n, L, om = 16, 8.0, 0.74
+    plan = lc.Plan(n, L, om, "f32", path="staged")
+    plan.set_option("graph", 1)
+    for batch in (3, 9, 4):
+        h, params = mixed_inputs(n, L, batch, seed=800 + batch)
+        plan.set_maxwellians(dev(params, torch.float64))
+        ht = dev(h, torch.float32)
+        out = plan.apply(ht)
+        out = plan.apply(ht, out)    # replay
+        torch.cuda.synchronize()
+        assert torch.equal(out.cpu(), eager_result(n, L, om, "f32", "staged", h, params))
+
+
+@pytest.mark.parametrize("per_cu", [1, 2, 3, 4])
+def test_fused_workgroups_per_cu_do_not_change_results(per_cu):
+    n, L, om, batch = 16, 8.0, 0.74, 23
+    h, params = mixed_inputs(n, L, batch, seed=900)
+    ref = eager_result(n, L, om, "f32", "fused", h, params)
+    got = eager_result(n, L, om, "f32", "fused", h, params, fused_per_cu=per_cu)
+    assert torch.equal(got, ref)
+
+
+def test_option_errors():
+    lib = lc.library()
+    plan = lc.Plan(32, 8.0, 0.74, "f32")
+    assert lib.lincoll_set_option(plan._h, lc.OPTIONS["fused_per_cu"], 2) == lc.EINVAL   # n = 32 fits one
+    assert lib.lincoll_set_option(plan._h, lc.OPTIONS["graph"], 2) == lc.EINVAL
+    assert lib.lincoll_set_option(plan._h, 99, 0) == lc.EINVAL
+    p64 = lc.Plan(32, 8.0, 0.74, "f64")
+    assert lib.lincoll_set_option(p64._h, lc.OPTIONS["path"], lc.PATHS["fused"]) == lc.EINVAL
+    x = torch.zeros((2, 32, 32, 32), dtype=torch.float32, device=DEV)
+    p = ctypes.c_void_p(x.data_ptr())
+    assert lib.lincoll_autotune(plan._h, p, p, 2, 3) == lc.EINVAL                        # aliased
+    y = torch.zeros_like(x)
+    assert lib.lincoll_autotune(plan._h, p, ctypes.c_void_p(y.data_ptr()), 2, 0) == lc.EINVAL
+
+
+@pytest.mark.parametrize("n,batch", [(16, 37), (32, 64)])
+def test_autotune_picks_a_valid_configuration(n, batch):
+    L, om = 8.0, 0.74
+    h, params = mixed_inputs(n, L, batch, seed=1000 + n)
+    hin = h.astype(np.float32).astype(np.float64)
+    plan = lc.Plan(n, L, om, "f32")
+    plan.set_maxwellians(dev(params, torch.float64))
+    ht = dev(hin, torch.float32)
+    ms = plan.autotune(ht, reps=2)
+    assert ms > 0 and plan.info("tuned_ms") == ms
+    assert plan.info("path") in (1, 2)
+    assert 1 <= plan.info("fused_per_cu") <= (4 if n == 16 else 1)
+    out = plan.apply(ht)
+    out = plan.apply(ht, out)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    sample = [0, batch // 2, batch - 1]
+    ref = alg1.apply_batch(fd.make_plan(n, L, om), hin[sample], params[sample])
+    for i, b in enumerate(sample):
+        assert rel(got[b], ref[i]) <= 1e-5
