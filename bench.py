@@ -140,6 +140,9 @@ def main():
     ap.add_argument("--config", default="C3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-configuration tuner (lincoll_autotune) before timing")
+    ap.add_argument("--graph", type=int, default=None, help="force graph replay off (0) or on (1)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (reference kernel for counter runs)")
     a = ap.parse_args()
@@ -167,7 +170,14 @@ def main():
         plan = lincoll.Plan(n, L, om, a.dtype, path=a.path)
         plan.set_maxwellians(pt)
         J = int(plan.info("J"))
+        tuned_ms = None
+        if not a.no_tune and a.path == "auto":
+            tuned_ms = plan.autotune(ht, out, reps=3)   # untimed; picks path, workgroups/CU, graph replay
+        if a.graph is not None:
+            plan.set_option("graph", a.graph)
         path = "fused" if plan.info("path") == 2 else "staged"
+        launch = {"path": path, "graph": int(plan.info("graph")), "tuned_ms": tuned_ms,
+                  "fused_per_cu": int(plan.info("fused_per_cu")) if path == "fused" else None}
         for _ in range(a.warmup):
             plan.apply(ht, out)
         stream.synchronize()
@@ -203,7 +213,7 @@ def main():
         "config": {"workload": f"{a.config}: {B} cells, n={n}, box [-{L:g},{L:g})^3, VHS omega={om}, "
                                f"J={J}, eps=1e-9, per-cell Maxwellians" if a.config == "C3" else
                                f"{a.config}: {B} cells, n={n}, box [-{L:g},{L:g})^3, VHS omega={om}, J={J}",
-                   "cells": B, "n": n, "path": path},
+                   "cells": B, "n": n, "path": path, "launch": launch},
     }
     # Roofline of the dominant kernel.  On the fused path a step is exactly one
     # launch of the fused kernel on `stream`, so the event-timed step is that

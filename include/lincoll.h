@@ -47,13 +47,14 @@ typedef struct lincoll_plan_s* lincoll_plan_t;
 typedef enum {
   LINCOLL_F64 = 0,   /* every step in double */
   LINCOLL_F32 = 1,   /* transforms and mode products in float; setup, mask and projection in double */
-  LINCOLL_BF16X3 = 2 /* as F32, with the per-axis DFT stages of the gain loop as split-bf16 MFMA products */
+  LINCOLL_BF16X3 = 2 /* as F32, with the two in-plane forward DFT stages of the gain loop as split-bfloat16
+                        (hi + lo, three products, FP32 accumulation) matrix-core GEMMs; staged path, n = 32 */
 } lincoll_dtype_t;
 
 typedef enum {
   LINCOLL_PATH_AUTO = 0,    /* fused kernel where it exists, otherwise the staged kernels */
   LINCOLL_PATH_STAGED = 1,  /* batched per-stage kernels (every n and dtype) */
-  LINCOLL_PATH_FUSED = 2    /* one persistent workgroup per cell (F32/BF16X3 at n = 16, 32) */
+  LINCOLL_PATH_FUSED = 2    /* one persistent workgroup per cell (F32 at n = 16, 32) */
 } lincoll_path_t;
 
 typedef struct {

@@ -112,7 +112,7 @@ int validate(const lincoll_params_t* p) {
   if (p->max_batch < 0) return LINCOLL_EINVAL;
   if (p->path < 0 || p->path > 2) return LINCOLL_EINVAL;
   if (p->path == LINCOLL_PATH_FUSED && !fused_supported(p->n, p->dtype)) return LINCOLL_EINVAL;
-  if (p->dtype == LINCOLL_BF16X3 && !fused_supported(p->n, p->dtype)) return LINCOLL_EINVAL;
+  if (!staged_supported(p->n, p->dtype)) return LINCOLL_EINVAL;
   return LINCOLL_OK;
 }
 

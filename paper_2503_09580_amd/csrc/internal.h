@@ -83,6 +83,10 @@ hipError_t project_cells(const ProjectCtx& c);
 bool staged_supported(int n, int dtype);
 bool fused_supported(int n, int dtype);
 hipError_t fused_apply(const ApplyCtx& c);
+// BF16x3 matrix-core forward plane transform of the gain loop (n = 32):
+// out = (first ? 0 : out) + Phi_j * DFT2(in) over the planes [nplanes][32][32].
+hipError_t plane_fwd_bf16x3(const float2* in, float2* out, const float* table, int j, int nplanes, int first,
+                            int cus, hipStream_t s);
 size_t fused_scratch_bytes(int n, int nslots);
 int fused_max_per_cu(int n);
 int fused_slots(int n, int batch, int per_cu, int cus);

@@ -9,6 +9,8 @@
 // mode tables (K_j, Phi_j, Omega).  Frequencies use the natural FFT index
 // K in [0, n) with |k| = min(K, n-K): every spectral factor depends on |k|
 // only, so the phase origin of the grid cancels in each transform pair.
+#include <type_traits>
+
 #include "fft.h"
 #include "internal.h"
 
@@ -311,6 +313,14 @@ static hipError_t apply_n(const ApplyCtx& c) {
     k_plane<double, double, TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc,
                                                                             nplanes, 1);
     k_z_mid<TS, T, NN><<<gz2, 128, 0, c.stream>>>(W, Wq, fac, pref, c.Bc, B);
+    if constexpr (std::is_same<TS, float>::value && NN == 32) {
+      if (c.dtype == 2) {   // BF16x3: the forward in-plane DFT stages on the matrix cores
+        hipError_t e = plane_fwd_bf16x3(reinterpret_cast<const float2*>(Wq), reinterpret_cast<float2*>(Lp), Phi, j,
+                                        nplanes, j == 0, c.cus, c.stream);
+        if (e) return e;
+        continue;
+      }
+    }
     k_plane<TS, TS, TS, T, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(Wq, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes,
                                                                      j == 0);
   }
@@ -322,7 +332,10 @@ static hipError_t apply_n(const ApplyCtx& c) {
   return hipGetLastError();
 }
 
-bool staged_supported(int n, int) { return n == 8 || n == 16 || n == 32; }
+bool staged_supported(int n, int dtype) {
+  if (dtype == 2) return n == 32;   // BF16x3 matrix-core stage exists for n = 32
+  return n == 8 || n == 16 || n == 32;
+}
 
 hipError_t staged_apply(const ApplyCtx& c) {
   if (c.dtype == 0) {

@@ -1,0 +1,73 @@
+"""BF16x3 variant (matrix-core forward DFT stages of the gain loop) against
+the FP64 oracle and against the FP32 path on the same GPU.
+
+Bar: a bfloat16 hi + lo pair carries 16 significant bits, so each split
+operand is represented to within 2^-17 relative; the three-product form
+drops a further term of relative size 2^-16.  With two GEMM stages per
+transform this bounds the stage error by about 4 * 2^-16 = 6e-5 relative
+to the plane's magnitude; the apply is checked at 5e-5 per cell (relative
+l2), while the FP32 bar (1e-5) is not expected to hold for this dtype."""
+import numpy as np
+import pytest
+
+from oracle import alg1, fast_direct as fd
+from paper_2503_09580_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
+from test_gpu_parity import mixed_inputs, rel  # noqa: E402
+
+DEV = torch.device("cuda:0")
+BAR = 5e-5
+
+
+def run(dtype, h, params, n=32, L=8.0, om=0.74):
+    plan = lc.Plan(n, L, om, dtype)
+    plan.set_maxwellians(torch.from_numpy(np.ascontiguousarray(params)).to(DEV, torch.float64))
+    td = torch.float64 if dtype == "f64" else torch.float32
+    out = plan.apply(torch.from_numpy(np.ascontiguousarray(h)).to(DEV, td))
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+def test_bf16x3_c2_against_oracle():
+    h, params = wl.c2()
+    hin = h.astype(np.float32).astype(np.float64)
+    got = run("bf16x3", hin, params)
+    sample = [0, 13, 40, 63]
+    ref = alg1.apply_batch(fd.make_plan(32, 8.0, 0.74), hin[sample], np.repeat(params, len(sample), 0))
+    errs = [rel(got[b], ref[i]) for i, b in enumerate(sample)]
+    assert max(errs) <= BAR, errs
+
+
+def test_bf16x3_per_cell_maxwellians_ragged_batch():
+    h, params = mixed_inputs(32, 8.0, 37, seed=1200)
+    hin = h.astype(np.float32).astype(np.float64)
+    got = run("bf16x3", hin, params)
+    sample = [0, 17, 36]
+    ref = alg1.apply_batch(fd.make_plan(32, 8.0, 0.74), hin[sample], params[sample])
+    for i, b in enumerate(sample):
+        assert rel(got[b], ref[i]) <= BAR
+
+
+def test_bf16x3_full_c3_batch_against_gpu_fp64():
+    h, params = wl.c3()
+    hin = h.astype(np.float32).astype(np.float64)
+    got = torch.from_numpy(run("bf16x3", hin, params))
+    ref = torch.from_numpy(run("f64", hin, params))
+    d = (got - ref).reshape(len(h), -1).norm(dim=1) / ref.reshape(len(h), -1).norm(dim=1)
+    assert float(d.max()) <= BAR, float(d.max())
+
+
+def test_bf16x3_supported_only_at_n32():
+    p = lc.make_params(16, 8.0, 0.74, "bf16x3")
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lc.library().lincoll_plan_ex(ctypes.byref(p), ctypes.byref(h)) == lc.EINVAL
+    plan = lc.Plan(32, 8.0, 0.74, "bf16x3")
+    assert plan.info("path") == 1            # staged path (the fused kernel has no BF16x3 stage)
