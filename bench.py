@@ -107,6 +107,8 @@ def workload(cfg):
         h, p = wl.c2()
     elif cfg == "C1":
         h, p = wl.c1()
+    elif cfg == "C5":
+        h, p = wl.c5()
     else:
         raise SystemExit(f"unknown config {cfg}")
     c = wl.CONFIGS[cfg]
@@ -211,7 +213,9 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32+f64", "bf16x3": "bf16x3"}.get(a.dtype, a.dtype),
         "data": "synthetic",
         "config": {"workload": f"{a.config}: {B} cells, n={n}, box [-{L:g},{L:g})^3, VHS omega={om}, "
-                               f"J={J}, eps=1e-9, per-cell Maxwellians" if a.config == "C3" else
+                               f"J={J}, eps=1e-9, per-cell Maxwellians"
+                               + (", theta log-uniform in [0.5, 2]" if a.config == "C5" else "")
+                               if a.config in ("C3", "C5") else
                                f"{a.config}: {B} cells, n={n}, box [-{L:g},{L:g})^3, VHS omega={om}, J={J}",
                    "cells": B, "n": n, "path": path, "launch": launch},
     }

@@ -100,7 +100,7 @@ void dfree(void* p) {
 int validate(const lincoll_params_t* p) {
   if (!p) return LINCOLL_EINVAL;
   if (p->dtype != LINCOLL_F64 && p->dtype != LINCOLL_F32 && p->dtype != LINCOLL_BF16X3) return LINCOLL_EINVAL;
-  if (!(p->n == 8 || p->n == 16 || p->n == 32)) return LINCOLL_EINVAL;
+  if (!(p->n == 8 || p->n == 16 || p->n == 32 || p->n == 64)) return LINCOLL_EINVAL;
   if (!(p->L > 0.0) || !std::isfinite(p->L)) return LINCOLL_EINVAL;
   if (!(p->omega >= 0.5 && p->omega <= 1.0)) return LINCOLL_EINVAL;
   if (!(p->C > 0.0) || !std::isfinite(p->C)) return LINCOLL_EINVAL;

@@ -63,12 +63,9 @@ __global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, double2
     const uint32_t* mk2 = mk1 + (NN / 2) * MW;
     uint32_t k1[MW], k2[MW];
     static_for<0, MW>([&](auto w) { k1[w] = mk1[w]; k2[w] = mk2[w]; });
-    T hr[NN], hi[NN];
     static_for<0, NN>([&](auto z) {
       const T ez = T(f[2 * NN + z]);
       const T v1 = T(h1[z]), v2 = T(h2[z]);
-      hr[z] = v1;
-      hi[z] = v2;
       ar[z] = ((k1[z / 32] >> (z % 32)) & 1u) ? v1 / (m1 * ez) : T(0);
       ai[z] = ((k2[z / 32] >> (z % 32)) & 1u) ? v2 / (m2 * ez) : T(0);
     });
@@ -77,6 +74,12 @@ __global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, double2
     static_for<0, P>([&](auto k) {
       R[b1 + (size_t)k * NP] = double2{double(Ar[k]), double(Ai[k])};
       R[b2 + (size_t)k * NP] = double2{double(Br[k]), double(Bi[k])};
+    });
+    // h columns again (read back rather than kept live next to r)
+    T hr[NN], hi[NN];
+    static_for<0, NN>([&](auto z) {
+      hr[z] = T(h1[z]);
+      hi[z] = T(h2[z]);
     });
     fft<NN, false>(hr, hi);
     split_real_pair<NN>(hr, hi, Ar, Ai, Br, Bi);
@@ -150,7 +153,7 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restr
                                                 const typename V2<TS>::t* __restrict__ H, const TS* __restrict__ h,
                                                 const TS* __restrict__ nu, TS* __restrict__ out,
                                                 const TS* __restrict__ fac, const TS* __restrict__ pref, int Bc,
-                                                int batch) {
+                                                int batch, double2* __restrict__ park) {
   using C = typename V2<TS>::t;
   constexpr int P = NN / 2 + 1, NP = NN * NN, HALF = NP / 2;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -161,6 +164,22 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restr
   const int cc = Bc > 1 ? cell : 0;
   const size_t b1 = (size_t)cell * P * NP + col1, b2 = b1 + NN / 2;
   T Ar[P], Ai[P], Br[P], Bi[P];
+  // n = 64: two 64-point double pencils do not fit one thread's registers;
+  // L+ is transformed first and parked in double (this thread's own slots of
+  // a free work buffer), then combined with the loss pencil.
+  constexpr bool PARK = MODE == 0 && NN == 64;
+  if constexpr (PARK) {
+    T lr[NN], li[NN];
+    static_for<0, P>([&](auto k) {
+      const C a = Lp[b1 + (size_t)k * NP];
+      const C b = Lp[b2 + (size_t)k * NP];
+      Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
+    });
+    join_real_pair<NN>(Ar, Ai, Br, Bi, lr, li);
+    fft<NN, true>(lr, li);
+    double2* pk = park + (size_t)gid * NN;
+    static_for<0, NN>([&](auto z) { pk[z] = double2{double(lr[z]), double(li[z])}; });
+  }
   T ur[NN], ui[NN];
   static_for<0, P>([&](auto k) {
     const C a = H[b1 + (size_t)k * NP];
@@ -173,13 +192,15 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restr
   TS* o2 = o1 + (size_t)(NN / 2) * NN;
   if constexpr (MODE == 0) {
     T lr[NN], li[NN];
-    static_for<0, P>([&](auto k) {
-      const C a = Lp[b1 + (size_t)k * NP];
-      const C b = Lp[b2 + (size_t)k * NP];
-      Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
-    });
-    join_real_pair<NN>(Ar, Ai, Br, Bi, lr, li);
-    fft<NN, true>(lr, li);                     // L+ on column 1 (re), column 2 (im)
+    if constexpr (!PARK) {
+      static_for<0, P>([&](auto k) {
+        const C a = Lp[b1 + (size_t)k * NP];
+        const C b = Lp[b2 + (size_t)k * NP];
+        Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
+      });
+      join_real_pair<NN>(Ar, Ai, Br, Bi, lr, li);
+      fft<NN, true>(lr, li);                   // L+ on column 1 (re), column 2 (im)
+    }
     const TS* f = fac + (size_t)cc * 6 * NN;
     const T mx = T(pref[2 * cc]) * T(f[x]);
     const T m1 = mx * T(f[NN + y1]), m2 = mx * T(f[NN + y2]);
@@ -187,10 +208,20 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restr
     const TS* h2 = h1 + (size_t)(NN / 2) * NN;
     const TS* n1 = nu + ((size_t)cc * NP + col1) * NN;
     const TS* n2 = n1 + (size_t)(NN / 2) * NN;
+    const double2* pk = park + (size_t)gid * NN;
     static_for<0, NN>([&](auto z) {
       const T ez = T(f[2 * NN + z]);
-      o1[z] = TS(lr[z] - (m1 * ez) * ur[z] - T(n1[z]) * T(h1[z]));
-      o2[z] = TS(li[z] - (m2 * ez) * ui[z] - T(n2[z]) * T(h2[z]));
+      T l1, l2;
+      if constexpr (PARK) {
+        const double2 v = pk[z];   // parked L+ (read element by element)
+        l1 = T(v.x);
+        l2 = T(v.y);
+      } else {
+        l1 = lr[z];
+        l2 = li[z];
+      }
+      o1[z] = TS(l1 - (m1 * ez) * ur[z] - T(n1[z]) * T(h1[z]));
+      o2[z] = TS(l2 - (m2 * ez) * ui[z] - T(n2[z]) * T(h2[z]));
     });
   } else {
     static_for<0, NN>([&](auto z) {
@@ -328,13 +359,13 @@ static hipError_t apply_n(const ApplyCtx& c) {
                                                                   1);
   k_plane<TS, TS, TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
   k_z_inv<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(Lp, H, static_cast<const TS*>(c.h), static_cast<const TS*>(c.nu),
-                                                 static_cast<TS*>(c.out), fac, pref, c.Bc, B);
+                                                 static_cast<TS*>(c.out), fac, pref, c.Bc, B, W);
   return hipGetLastError();
 }
 
 bool staged_supported(int n, int dtype) {
   if (dtype == 2) return n == 32;   // BF16x3 matrix-core stage exists for n = 32
-  return n == 8 || n == 16 || n == 32;
+  return n == 8 || n == 16 || n == 32 || n == 64;
 }
 
 hipError_t staged_apply(const ApplyCtx& c) {
@@ -343,12 +374,14 @@ hipError_t staged_apply(const ApplyCtx& c) {
       case 8: return apply_n<double, double, 8>(c);
       case 16: return apply_n<double, double, 16>(c);
       case 32: return apply_n<double, double, 32>(c);
+      case 64: return apply_n<double, double, 64>(c);
     }
   } else {
     switch (c.n) {
       case 8: return apply_n<float, double, 8>(c);
       case 16: return apply_n<float, double, 16>(c);
       case 32: return apply_n<float, double, 32>(c);
+      case 64: return apply_n<float, double, 64>(c);
     }
   }
   return hipErrorInvalidValue;
@@ -367,7 +400,8 @@ hipError_t nu_chunk(const double* fac64, const double* pref64, const double* Om6
                                                                              ncell, nplanes, 1);
   k_plane<double, double, double, double, NN, true, 0, 0><<<gp, 64, 0, s>>>(planes, planes, nullptr, nullptr, 0, 0,
                                                                             ncell, nplanes, 1);
-  k_z_inv<double, double, NN, 1><<<gz2, 128, 0, s>>>(nullptr, planes, nullptr, nullptr, nu64, nullptr, nullptr, ncell, ncell);
+  k_z_inv<double, double, NN, 1><<<gz2, 128, 0, s>>>(nullptr, planes, nullptr, nullptr, nu64, nullptr, nullptr, ncell, ncell,
+                                                    nullptr);
   return hipGetLastError();
 }
 
@@ -377,6 +411,7 @@ hipError_t nu_chunk_dispatch(int n, const double* fac64, const double* pref64, c
     case 8: return nu_chunk<8>(fac64, pref64, Om64, planes, nu64, ncell, s);
     case 16: return nu_chunk<16>(fac64, pref64, Om64, planes, nu64, ncell, s);
     case 32: return nu_chunk<32>(fac64, pref64, Om64, planes, nu64, ncell, s);
+    case 64: return nu_chunk<64>(fac64, pref64, Om64, planes, nu64, ncell, s);
   }
   return hipErrorInvalidValue;
 }

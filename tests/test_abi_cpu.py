@@ -73,7 +73,7 @@ def test_null_handles_rejected():
 
 
 @pytest.mark.parametrize("n,L,omega,rule", [(8, 4.0, 1.0, 0), (16, 8.0, 0.74, 0), (32, 8.0, 0.5, 0),
-                                            (16, 8.0, 0.74, 1)])
+                                            (16, 8.0, 0.74, 1), (64, 10.0, 0.74, 0)])
 def test_host_tables_match_oracle(n, L, omega, rule):
     """Plan precomputation (C++, own Golub-Welsch) against the oracle
     (numpy eigensolver, dense DFTs): at most 1e-13 relative."""
