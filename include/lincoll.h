@@ -152,6 +152,15 @@ int lincoll_set_option(lincoll_plan_t plan, int key, int value);
  * reps in [1, 1000]. */
 int lincoll_autotune(lincoll_plan_t plan, const void* h, void* out, int batch, int reps);
 
+/* Advances f[b] in place by `steps` steps of the classical fourth-order
+ * Runge-Kutta scheme with step dt for the spatially homogeneous linearized
+ * equation df/dt = L[f] about the plan's Maxwellians (Sec. 4.2; four applies
+ * per step).  f: device [batch][n][n][n] in the apply dtype; the stage
+ * buffers belong to the plan.  With LINCOLL_OPT_GRAPH one whole step is
+ * recorded once (for this f, batch and dt) and replayed.  Same batch rules
+ * as lincoll_apply; steps >= 0. */
+int lincoll_rk4(lincoll_plan_t plan, void* f, int batch, double dt, int steps);
+
 /* Releases everything the plan owns (waits for its stream first). */
 void lincoll_destroy(lincoll_plan_t plan);
 

@@ -24,6 +24,8 @@ binary       O2: the binary-operator spectral method (Sec. 2.3, eq. (14))
              L_bin[h] = Q(M,h) + Q(h,M).
 projection   Orthogonal projection onto the complement of the collision
              invariants in the M^{-1}-weighted inner product.
+timestep     Classical RK4 for the spatially homogeneous linearized
+             equation df/dt = L[f] (Sec. 4.2).
 
 Readings of the paper that the oracle takes where the text is silent or
 inconsistent (each also implemented identically on the GPU side):

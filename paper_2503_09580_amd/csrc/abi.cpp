@@ -66,6 +66,14 @@ struct lincoll_plan_s {
     int batch, Bc, fused, per_cu, project;
     unsigned long gen;
   } gkey{};
+  // time stepping (lincoll_rk4): work buffers and the recorded step
+  int cap_rk = 0;
+  void* d_rk_k = nullptr;
+  void* d_rk_tmp = nullptr;
+  void* d_rk_acc = nullptr;
+  hipGraphExec_t rk_gexec = nullptr;
+  GraphKey rk_key{};
+  double rk_dt = 0.0;
 };
 
 namespace {
@@ -584,6 +592,74 @@ int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
   return LINCOLL_ENOTIMPL;
 }
 
+namespace {
+
+// One step of the classical fourth-order Runge-Kutta scheme for
+// df/dt = L[f]: k1 = L f, k2 = L(f + dt/2 k1), k3 = L(f + dt/2 k2),
+// k4 = L(f + dt k3), f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4).
+hipError_t rk4_step(lincoll_plan_t pl, void* f, int batch, double dt, hipStream_t s) {
+  const long cnt = (long)batch * pl->p.n * pl->p.n * pl->p.n;
+  const int dt_ = pl->p.dtype == LINCOLL_F64 ? 0 : 1;
+  void *k = pl->d_rk_k, *tmp = pl->d_rk_tmp, *acc = pl->d_rk_acc;
+  hipError_t e;
+  if ((e = launch_apply(pl, f, k, batch, s)) || (e = rk_stage(dt_, f, k, acc, tmp, cnt, dt / 6, dt / 2, 1, s)) ||
+      (e = launch_apply(pl, tmp, k, batch, s)) || (e = rk_stage(dt_, f, k, acc, tmp, cnt, dt / 3, dt / 2, 0, s)) ||
+      (e = launch_apply(pl, tmp, k, batch, s)) || (e = rk_stage(dt_, f, k, acc, tmp, cnt, dt / 3, dt, 0, s)) ||
+      (e = launch_apply(pl, tmp, k, batch, s)) || (e = rk_final(dt_, f, acc, k, cnt, dt / 6, s)))
+    return e;
+  return hipSuccess;
+}
+
+}  // namespace
+
+int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
+  if (!pl || !f || batch < 1 || steps < 0 || !std::isfinite(dt)) return LINCOLL_EINVAL;
+  if (pl->p.max_batch > 0 && batch > pl->p.max_batch) return LINCOLL_EINVAL;
+  if (pl->Bc != 1 && pl->Bc != batch) return LINCOLL_ENOTREADY;
+  int st = ensure_work(pl, batch);
+  if (st) return st;
+  hipError_t e;
+  if (batch > pl->cap_rk) {
+    const size_t bytes = (size_t)batch * pl->p.n * pl->p.n * pl->p.n * esize(pl->p.dtype);
+    if ((e = dalloc(pl, &pl->d_rk_k, bytes)) || (e = dalloc(pl, &pl->d_rk_tmp, bytes)) ||
+        (e = dalloc(pl, &pl->d_rk_acc, bytes)))
+      return hip_fail(pl, e);
+    pl->cap_rk = batch;
+  }
+  if (!pl->opt_graph) {
+    for (int i = 0; i < steps; ++i)
+      if ((e = rk4_step(pl, f, batch, dt, pl->stream))) return hip_fail(pl, e);
+    return LINCOLL_OK;
+  }
+  // record one step once, replay it `steps` times
+  const lincoll_plan_s::GraphKey key{f, nullptr, batch, pl->Bc, use_fused(pl) ? 1 : 0, pl->opt_per_cu,
+                                     pl->p.project, pl->alloc_gen};
+  const lincoll_plan_s::GraphKey& k = pl->rk_key;
+  const bool same = pl->rk_gexec && k.h == key.h && k.batch == key.batch && k.Bc == key.Bc && k.fused == key.fused &&
+                    k.per_cu == key.per_cu && k.project == key.project && k.gen == key.gen && pl->rk_dt == dt;
+  if (!same) {
+    if (pl->rk_gexec) (void)hipGraphExecDestroy(pl->rk_gexec);
+    pl->rk_gexec = nullptr;
+    if (!pl->cap_stream && (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking))) return hip_fail(pl, e);
+    if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal))) return hip_fail(pl, e);
+    const hipError_t el = rk4_step(pl, f, batch, dt, pl->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(pl->cap_stream, &g);
+    if (el) e = el;
+    if (!e) e = hipGraphInstantiate(&pl->rk_gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e) {
+      pl->rk_gexec = nullptr;
+      return hip_fail(pl, e);
+    }
+    pl->rk_key = key;
+    pl->rk_dt = dt;
+  }
+  for (int i = 0; i < steps; ++i)
+    if ((e = hipGraphLaunch(pl->rk_gexec, pl->stream))) return hip_fail(pl, e);
+  return LINCOLL_OK;
+}
+
 int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
   if (!pl || !val) return LINCOLL_EINVAL;
   switch (key) {
@@ -610,10 +686,12 @@ void lincoll_destroy(lincoll_plan_t pl) {
   if (!pl) return;
   (void)hipStreamSynchronize(pl->stream);
   drop_graph(pl);
+  if (pl->rk_gexec) (void)hipGraphExecDestroy(pl->rk_gexec);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   void* ptrs[] = {pl->d_Phi,  pl->d_Om,    pl->d_Om64,  pl->d_phi,  pl->d_Cdct, pl->d_params, pl->d_fac64,
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
-                  pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin};
+                  pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin,
+                  pl->d_rk_k, pl->d_rk_tmp, pl->d_rk_acc};
   for (void* p : ptrs) dfree(p);
   delete pl;
 }

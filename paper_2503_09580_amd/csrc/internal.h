@@ -87,6 +87,10 @@ hipError_t fused_apply(const ApplyCtx& c);
 // out = (first ? 0 : out) + Phi_j * DFT2(in) over the planes [nplanes][32][32].
 hipError_t plane_fwd_bf16x3(const float2* in, float2* out, const float* table, int j, int nplanes, int first,
                             int cus, hipStream_t s);
+// RK4 stage combinations (double arithmetic on the dtype's storage)
+hipError_t rk_stage(int dtype, const void* f, const void* k, void* acc, void* tmp, long count, double a, double b,
+                    int first, hipStream_t s);
+hipError_t rk_final(int dtype, void* f, const void* acc, const void* k, long count, double a, hipStream_t s);
 size_t fused_scratch_bytes(int n, int nslots);
 int fused_max_per_cu(int n);
 int fused_slots(int n, int batch, int per_cu, int cus);

@@ -23,7 +23,7 @@ OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2}
 SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
            "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
            "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",
-           "lincoll_set_option", "lincoll_autotune"]
+           "lincoll_set_option", "lincoll_autotune", "lincoll_rk4"]
 
 
 class LincollError(RuntimeError):
@@ -60,6 +60,7 @@ def _load():
         "lincoll_plan_tables": (ctypes.c_longlong, [P(Params), i, P(d), ctypes.c_longlong]),
         "lincoll_set_option": (i, [vp, i, i]),
         "lincoll_autotune": (i, [vp, vp, vp, i, i]),
+        "lincoll_rk4": (i, [vp, vp, i, d, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -185,6 +186,15 @@ class Plan:
                                      self._dev(out, self.tdtype, (n, n, n), "out"), h.shape[0], int(reps)),
                "lincoll_autotune")
         return self.info("tuned_ms")
+
+    def rk4(self, f, dt, steps):
+        """Advances f (contiguous [batch, n, n, n] tensor of the plan's dtype)
+        in place by `steps` RK4 steps of df/dt = L[f]."""
+        n = self.n
+        self._sync_stream()
+        _check(_lib.lincoll_rk4(self._h, self._dev(f, self.tdtype, (n, n, n), "f"), f.shape[0], float(dt),
+                                int(steps)), "lincoll_rk4")
+        return f
 
     def info(self, key):
         v = ctypes.c_double()

@@ -21,7 +21,7 @@ lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:lincoll|quadcoll)_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:lincoll|quadcoll)_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported():
