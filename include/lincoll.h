@@ -104,8 +104,17 @@ int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
  * dtype.  x == y is allowed. */
 int lincoll_project(lincoll_plan_t plan, const void* x, void* y, int batch);
 
-/* Binary operator Q(f,f) of eq. (14) with a hemisphere rule; not provided
- * by this build: returns LINCOLL_ENOTIMPL. */
+/* out[b] = Q(f[b], f[b]), the binary collision operator by the spectral
+ * method of Sec. 2.3, eq. (14) (no conservation fix), with the plan's
+ * g-quadrature (W_j, g_j, as for the linearized operator) and a product rule
+ * on the hemisphere: the positive nodes of the LINCOLL_OPT_SPHERE_POLAR-point
+ * Gauss-Legendre rule (default 8, i.e. 4 polar cosines) times
+ * LINCOLL_OPT_SPHERE_AZIMUTH equispaced azimuths (default 16); 64 points by
+ * default.  Always FP64, whatever the plan's dtype: f and out are device
+ * double [batch][n][n][n], not overlapping.  Independent of the Maxwellians.
+ * Work volumes (7 n^3 doubles complex per cell) belong to the plan.  Cost:
+ * per cell 2 J M + J + 4 complex 3-D transforms (M hemisphere points).
+ * n = 8, 16, 32; other n give LINCOLL_ENOTIMPL. */
 int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 
 #define LINCOLL_INFO_N 0
@@ -138,10 +147,14 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
  *                            0 = default (the maximum), n = 16: 1..4,
  *                            n = 32: 1.
  *   LINCOLL_OPT_PATH         a lincoll_path_t the plan's n and dtype support.
+ *   LINCOLL_OPT_SPHERE_POLAR, LINCOLL_OPT_SPHERE_AZIMUTH
+ *                            hemisphere rule of quadcoll_apply.
  * Returns LINCOLL_EINVAL for an unknown key or an unsupported value. */
 #define LINCOLL_OPT_GRAPH 0
 #define LINCOLL_OPT_FUSED_PER_CU 1
 #define LINCOLL_OPT_PATH 2
+#define LINCOLL_OPT_SPHERE_POLAR 3    /* quadcoll: Gauss-Legendre order on [-1,1] (even, 2..64; positive nodes used) */
+#define LINCOLL_OPT_SPHERE_AZIMUTH 4  /* quadcoll: azimuths (1..256) */
 int lincoll_set_option(lincoll_plan_t plan, int key, int value);
 
 /* Launch-configuration tuner: times `reps` applies of every supported

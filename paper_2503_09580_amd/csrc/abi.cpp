@@ -74,6 +74,12 @@ struct lincoll_plan_s {
   hipGraphExec_t rk_gexec = nullptr;
   GraphKey rk_key{};
   double rk_dt = 0.0;
+  // binary operator (quadcoll_apply): hemisphere rule, tables, work volumes
+  int sphere_polar = 8, sphere_azim = 16;
+  int cap_qc = 0;
+  double* d_Ws = nullptr;
+  double* d_qV = nullptr;
+  double2 *d_qF = nullptr, *d_qGp = nullptr, *d_qGm = nullptr, *d_qC = nullptr, *d_qS = nullptr, *d_qQ = nullptr;
 };
 
 namespace {
@@ -514,6 +520,14 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       if (value < 0 || value > fused_max_per_cu(pl->p.n)) return LINCOLL_EINVAL;
       pl->opt_per_cu = value;
       break;
+    case LINCOLL_OPT_SPHERE_POLAR:
+      if (value < 2 || value > 64 || value % 2) return LINCOLL_EINVAL;
+      pl->sphere_polar = value;
+      break;
+    case LINCOLL_OPT_SPHERE_AZIMUTH:
+      if (value < 1 || value > 256) return LINCOLL_EINVAL;
+      pl->sphere_azim = value;
+      break;
     case LINCOLL_OPT_PATH:
       if (value < LINCOLL_PATH_AUTO || value > LINCOLL_PATH_FUSED) return LINCOLL_EINVAL;
       if (value == LINCOLL_PATH_FUSED && !fused_supported(pl->p.n, pl->p.dtype)) return LINCOLL_EINVAL;
@@ -589,7 +603,60 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
 
 int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
   if (!pl || !f || !out || batch < 1) return LINCOLL_EINVAL;
-  return LINCOLL_ENOTIMPL;
+  if (!quadcoll_supported(pl->p.n)) return LINCOLL_ENOTIMPL;
+  if (pl->p.max_batch > 0 && batch > pl->p.max_batch) return LINCOLL_EINVAL;
+  const int n = pl->p.n, J = pl->t.J, Q = pl->t.Q;
+  const size_t n3 = (size_t)n * n * n, bytes = (size_t)batch * n3 * sizeof(double);
+  const char* a = static_cast<const char*>(f);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return LINCOLL_EINVAL;   // overlap
+  std::vector<double> mu, wmu;
+  if (!hemisphere_polar(pl->sphere_polar, mu, wmu)) return LINCOLL_EINVAL;
+  hipError_t e;
+  if (!pl->d_Ws) {
+    // W_j s_j(|k|^2) = Phi_j / (4 pi^2), FP64
+    std::vector<double> ws(pl->t.Phi);
+    for (auto& v : ws) v /= 4.0 * M_PI * M_PI;
+    if ((e = dalloc(pl, &pl->d_Ws, ws.size() * sizeof(double))) ||
+        (e = hipMemcpy(pl->d_Ws, ws.data(), ws.size() * sizeof(double), hipMemcpyHostToDevice)))
+      return hip_fail(pl, e);
+  }
+  if (batch > pl->cap_qc) {
+    const size_t cb = (size_t)batch * n3 * sizeof(double2);
+    if ((e = dalloc(pl, &pl->d_qV, bytes)) || (e = dalloc(pl, &pl->d_qF, cb)) || (e = dalloc(pl, &pl->d_qGp, cb)) ||
+        (e = dalloc(pl, &pl->d_qGm, cb)) || (e = dalloc(pl, &pl->d_qC, cb)) || (e = dalloc(pl, &pl->d_qS, cb)) ||
+        (e = dalloc(pl, &pl->d_qQ, cb)))
+      return hip_fail(pl, e);
+    pl->cap_qc = batch;
+  }
+  std::vector<double> st(mu.size());
+  for (size_t i = 0; i < mu.size(); ++i) st[i] = std::sqrt(1.0 - mu[i] * mu[i]);
+  QuadCtx c;
+  c.n = n;
+  c.J = J;
+  c.Q = Q;
+  c.batch = batch;
+  c.L = pl->p.L;
+  c.stream = pl->stream;
+  c.f = static_cast<const double*>(f);
+  c.out = static_cast<double*>(out);
+  c.V = pl->d_qV;
+  c.Fk = pl->d_qF;
+  c.Gp = pl->d_qGp;
+  c.Gm = pl->d_qGm;
+  c.C = pl->d_qC;
+  c.S = pl->d_qS;
+  c.Qk = pl->d_qQ;
+  c.Om64 = pl->d_Om64;
+  c.Ws = pl->d_Ws;
+  c.g = pl->t.g.data();
+  c.mu = mu.data();
+  c.st = st.data();
+  c.wpolar = wmu.data();
+  c.npolar = (int)mu.size();
+  c.nazim = pl->sphere_azim;
+  if ((e = quadcoll_apply_fp64(c))) return hip_fail(pl, e);
+  return LINCOLL_OK;
 }
 
 namespace {
@@ -691,7 +758,8 @@ void lincoll_destroy(lincoll_plan_t pl) {
   void* ptrs[] = {pl->d_Phi,  pl->d_Om,    pl->d_Om64,  pl->d_phi,  pl->d_Cdct, pl->d_params, pl->d_fac64,
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
                   pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin,
-                  pl->d_rk_k, pl->d_rk_tmp, pl->d_rk_acc};
+                  pl->d_rk_k, pl->d_rk_tmp, pl->d_rk_acc, pl->d_Ws, pl->d_qV, pl->d_qF, pl->d_qGp,
+                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ};
   for (void* p : ptrs) dfree(p);
   delete pl;
 }

@@ -207,4 +207,21 @@ bool build_tables(const TableParams& tp, HostTables& t) {
   return true;
 }
 
+// Hemisphere product rule for the binary operator (Sec. 2.3, eq. (14)): the
+// positive nodes mu_i of the n_polar-point Gauss-Legendre rule on [-1, 1]
+// (polar cosines) with their weights; combined with n_azimuth equispaced
+// azimuths and weights w_i / n_azimuth the rule sums to 1 over S^2_+.
+bool hemisphere_polar(int n_polar, std::vector<double>& mu, std::vector<double>& w) {
+  std::vector<double> x, wx;
+  if (n_polar < 2 || n_polar % 2 || !gauss_jacobi(n_polar, 0.0, 0.0, x, wx)) return false;
+  mu.clear();
+  w.clear();
+  for (int i = 0; i < n_polar; ++i)
+    if (x[i] > 0.0) {
+      mu.push_back(x[i]);
+      w.push_back(wx[i]);
+    }
+  return (int)mu.size() == n_polar / 2;
+}
+
 }  // namespace lincoll

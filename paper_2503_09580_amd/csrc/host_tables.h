@@ -22,4 +22,8 @@ struct HostTables {
 
 bool build_tables(const TableParams& tp, HostTables& t);
 
+// Positive Gauss-Legendre nodes (polar cosines) and weights of the
+// n_polar-point rule (n_polar even) for the hemisphere product rule.
+bool hemisphere_polar(int n_polar, std::vector<double>& mu, std::vector<double>& w);
+
 }  // namespace lincoll

@@ -77,6 +77,26 @@ struct ProjectCtx {
   const double* Ainv = nullptr;
 };
 
+// Binary operator Q(f, f) (eq. (14)), FP64.
+struct QuadCtx {
+  int n = 0, J = 0, Q = 0, batch = 0;
+  double L = 0.0;
+  hipStream_t stream = nullptr;
+  const double* f = nullptr;     // [batch][n^3] physical
+  double* out = nullptr;         // [batch][n^3]
+  double* V = nullptr;           // [batch][n^3] loss field
+  double2 *Fk = nullptr, *Gp = nullptr, *Gm = nullptr, *C = nullptr, *S = nullptr, *Qk = nullptr;   // [batch][n^3]
+  const double* Om64 = nullptr;  // [Q] Omega / n^3
+  const double* Ws = nullptr;    // [J][Q] W_j s_j(|k|^2)
+  const double* g = nullptr;     // host [J]
+  const double* mu = nullptr;    // host [npolar] polar cosines
+  const double* st = nullptr;    // host [npolar] sqrt(1 - mu^2)
+  const double* wpolar = nullptr;   // host [npolar] polar weights
+  int npolar = 0, nazim = 0;
+};
+bool quadcoll_supported(int n);
+hipError_t quadcoll_apply_fp64(const QuadCtx& c);
+
 hipError_t staged_apply(const ApplyCtx& c);
 hipError_t setup_cells(const SetupCtx& c);
 hipError_t project_cells(const ProjectCtx& c);

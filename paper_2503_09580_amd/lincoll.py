@@ -19,7 +19,7 @@ PATHS = {"auto": 0, "staged": 1, "fused": 2}
 TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
 INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
         "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11}
-OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2}
+OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2, "sphere_polar": 3, "sphere_azimuth": 4}
 SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
            "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
            "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",
@@ -186,6 +186,17 @@ class Plan:
                                      self._dev(out, self.tdtype, (n, n, n), "out"), h.shape[0], int(reps)),
                "lincoll_autotune")
         return self.info("tuned_ms")
+
+    def quadcoll(self, f, out=None):
+        """Q(f, f) by eq. (14) for a float64 CUDA tensor [batch, n, n, n]."""
+        n = self.n
+        torch = self._torch
+        if out is None:
+            out = torch.empty_like(f)
+        self._sync_stream()
+        _check(_lib.quadcoll_apply(self._h, self._dev(f, torch.float64, (n, n, n), "f"),
+                                   self._dev(out, torch.float64, (n, n, n), "out"), f.shape[0]), "quadcoll_apply")
+        return out
 
     def rk4(self, f, dt, steps):
         """Advances f (contiguous [batch, n, n, n] tensor of the plan's dtype)

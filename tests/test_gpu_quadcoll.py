@@ -1,0 +1,68 @@
+"""quadcoll_apply (binary operator Q(f, f), eq. (14), hemisphere product rule)
+through the C ABI against the oracle's binary method (O2), FP64, 1e-12.
+
+Also the polarisation identity Q(M+h) - Q(M) - Q(h) = Q(M,h) + Q(h,M), i.e.
+the linearized binary operator of Sec. 4.1, against O2's direct evaluation of
+that linearization (bilinearity of the GPU evaluation)."""
+import numpy as np
+import pytest
+
+from oracle import binary, fast_direct as fd, quadrature
+from paper_2503_09580_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
+from test_gpu_parity import mixed_inputs, rel  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def gpu_q(n, L, om, f, polar=8, azim=16):
+    plan = lc.Plan(n, L, om, "f64")
+    plan.set_option("sphere_polar", polar)
+    plan.set_option("sphere_azimuth", azim)
+    out = plan.quadcoll(torch.from_numpy(np.ascontiguousarray(f)).to(DEV, torch.float64))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,L,om,polar,azim", [(8, 4.0, 1.0, 8, 16), (16, 8.0, 0.74, 8, 16), (16, 8.0, 0.5, 6, 10)])
+def test_quadcoll_matches_binary_oracle(n, L, om, polar, azim):
+    h, params = mixed_inputs(n, L, 3, seed=1600 + n + polar)
+    f = h + np.stack([wl.maxwellian(n, L, q[0], q[1:4], q[4]) for q in params])
+    got = gpu_q(n, L, om, f, polar, azim)
+    plan = fd.make_plan(n, L, om)
+    sphere = quadrature.hemisphere_product_rule(polar, azim)
+    for b in range(3):
+        ref = binary.q_binary(plan, sphere, f[b], f[b], method="fast")
+        assert rel(got[b], ref) <= 1e-12, (b, rel(got[b], ref))
+
+
+def test_polarisation_gives_the_linearized_binary_operator():
+    n, L, om = 16, 8.0, 0.74
+    M = wl.maxwellian(n, L, 1.0, (0, 0, 0), 1.0)
+    h, _ = mixed_inputs(n, L, 1, seed=1700, per_cell=False)
+    q = gpu_q(n, L, om, np.stack([M + h[0], M, h[0]]))
+    lin_gpu = q[0] - q[1] - q[2]
+    plan = fd.make_plan(n, L, om)
+    ref = binary.linearized_binary(plan, quadrature.hemisphere_product_rule(8, 16), h[0], M)
+    assert rel(lin_gpu, ref) <= 1e-10, rel(lin_gpu, ref)
+
+
+def test_quadcoll_errors():
+    import ctypes
+    lib = lc.library()
+    plan = lc.Plan(16, 8.0, 0.74, "f64")
+    x = torch.zeros((2, 16, 16, 16), dtype=torch.float64, device=DEV)
+    p = ctypes.c_void_p(x.data_ptr())
+    assert lib.quadcoll_apply(plan._h, p, p, 2) == lc.EINVAL               # aliased
+    assert lib.lincoll_set_option(plan._h, lc.OPTIONS["sphere_polar"], 7) == lc.EINVAL
+    big = lc.Plan(64, 10.0, 0.74, "f32")
+    y = torch.zeros((1, 64, 64, 64), dtype=torch.float64, device=DEV)
+    z = torch.zeros_like(y)
+    assert lib.quadcoll_apply(big._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(z.data_ptr()), 1) == lc.ENOTIMPL
