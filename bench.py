@@ -132,14 +132,130 @@ def cpu_baseline(cfg, h, params, c, budget_s=12.0):
             "sample": f"first {done} cells of {cfg}, one at a time, FP64, {dt:.1f} s on {platform.processor() or platform.machine()}"}
 
 
+def quadcoll_flops_per_cell(n, J, M):
+    """(2 J M + J + 4) complex 3-D transforms at 5 N log2 N (N = n^3) plus
+    ~10 n^3 per hemisphere point and node for phases and products."""
+    N3 = n ** 3
+    return (2 * J * M + J + 4) * 5.0 * N3 * math.log2(N3) + 10.0 * J * M * N3
+
+
+def bench_quadcoll(a, torch, lincoll, dev):
+    """Q(f, f) (eq. (14), 64-point hemisphere rule, FP64) over 256 cells at
+    n = 32 (the cell count of the steady-state workload): f = local
+    Maxwellian + perturbation of the C3 generator's first 256 cells."""
+    from paper_2503_09580_amd import workloads as wl
+    B = 256
+    h, params = wl.c3(batch=4096, cells=np.arange(B))
+    n, L, om = 32, 8.0, 0.74
+    f = h + np.stack([wl.maxwellian(n, L, q[0], q[1:4], q[4]) for q in params])
+    ft = torch.from_numpy(f).to(dev, torch.float64)
+    out = torch.empty_like(ft)
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        plan = lincoll.Plan(n, L, om, "f64")
+        J = int(plan.info("J"))
+        for _ in range(max(1, a.warmup)):
+            plan.quadcoll(ft, out)
+        stream.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = min(a.steps, 5)
+        ev0.record(stream)
+        for _ in range(steps):
+            plan.quadcoll(ft, out)
+        ev1.record(stream)
+        ev1.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    M = 64
+    fl = quadcoll_flops_per_cell(n, J, M) * B
+    ach = fl / (ms / 1e3) / 1e12
+    rec = {"metric": "Q(f,f) applies/sec at N=32 (FP64, 64 hemisphere points)", "value": B / (ms / 1e3),
+           "unit": "applies/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{B} cells, n={n}, box [-{L:g},{L:g})^3, VHS omega={om}, J={J}, "
+                                  f"hemisphere 4 polar x 16 azimuths", "cells": B, "n": n},
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_VALU_TFLOPS, "traffic": None,
+                        "kernel": "quadcoll_apply (all launches of one step)"}}
+    if not a.no_cpu:
+        from oracle import binary, fast_direct, quadrature
+        plan = fast_direct.make_plan(n, L, om)
+        sph = quadrature.hemisphere_product_rule(8, 16)
+        t0 = time.perf_counter()
+        binary.q_binary(plan, sph, f[0], f[0], method="fast")
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": 1.0 / dt, "unit": "applies/s", "cores": 1, "kind": "oracle",
+                               "sample": f"cell 0, binary-method oracle with library FFT, FP64, {dt:.1f} s"}
+    print(json.dumps(rec))
+
+
+def bench_rk4(a, torch, lincoll, dev):
+    """The paper's timed workload (Table 5, Case 1): 100 RK4 steps (dt = 0.1)
+    of df/dt = L[f], n = 32 (N = 16), R = 6, L = (3 + sqrt 2) R / 4, Maxwell
+    molecules (omega = 1, B = 1/(4 pi)), one homogeneous cell, f^(1) initial
+    data, cutoff 1e-9; FP64 unless --dtype says otherwise."""
+    from paper_2503_09580_amd import workloads as wl
+    n, R = 32, 6.0
+    L = (3.0 + math.sqrt(2.0)) * R / 4.0
+    dtype = a.dtype if a.dtype in ("f64", "f32") else "f64"
+    td = torch.float64 if dtype == "f64" else torch.float32
+    f0 = wl.paper_f1(n, L)[None]
+    stream = torch.cuda.Stream(device=dev)
+    steps = 100
+    with torch.cuda.stream(stream):
+        plan = lincoll.Plan(n, L, 1.0, dtype, R=R)
+        plan.set_option("graph", 1)
+        f = torch.from_numpy(f0).to(dev, td)
+        plan.rk4(f, 0.1, max(1, a.warmup))
+        stream.synchronize()
+        f = torch.from_numpy(f0).to(dev, td)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        plan.rk4(f, 0.1, steps)
+        ev1.record(stream)
+        ev1.synchronize()
+        path = "fused" if plan.info("path") == 2 else "staged"
+    ms = ev0.elapsed_time(ev1)
+    J = n // 2 + 1
+    paper_s = 2.81          # Table 5, Case 1, linearized operator, 100 steps, one CPU thread
+    value = steps / (ms / 1e3)
+    fl = 4 * alg_flops_per_cell(n, J) * steps
+    ach = fl / (ms / 1e3) / 1e12
+    rec = {"metric": "RK4 steps/sec of df/dt = L[f] (Table 5, Case 1)", "value": value, "unit": "steps/s",
+           "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": ms / steps, "higher_is_better": True,
+           "scaling": "strong", "vs_baseline": value / (100.0 / paper_s),
+           "vs_baseline_note": "paper: 100 steps in 2.81 s on one Intel i7-13800H thread, FP64 (other hardware)",
+           "dtype": dtype, "data": "synthetic (closed-form f^(1))",
+           "config": {"workload": f"1 cell, n={n}, R={R:g}, L={L:.4f}, omega=1 (Maxwell), dt=0.1, 100 steps",
+                      "path": path, "graph": 1},
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_VALU_TFLOPS, "traffic": None,
+                        "kernel": "lincoll_rk4 (one recorded graph per step)",
+                        "note": "one cell cannot fill 256 CUs: latency-bound by construction"}}
+    if not a.no_cpu:
+        from oracle import fast_direct, timestep
+        plan = fast_direct.make_plan(n, L, 1.0, R=R)
+        p = np.array([[1.0, 0, 0, 0, 1.0]])
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 10.0 and k < 20:
+            timestep.rk4(plan, f0, p, 0.1, 1)
+            k += 1
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": k / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{k} RK4 steps of the same problem by the oracle (Algorithm 1, FP64)"}
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--dtype", default=None, help="f32 (default for apply), f64 (default for rk4), bf16x3")
     ap.add_argument("--path", default="auto")
     ap.add_argument("--config", default="C3")
+    ap.add_argument("--op", default="apply", choices=["apply", "quadcoll", "rk4"],
+                    help="apply: batched L[h] (default); quadcoll: binary Q(f,f); rk4: Table 5 time stepping")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -148,6 +264,8 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (reference kernel for counter runs)")
     a = ap.parse_args()
+    if a.dtype is None:
+        a.dtype = "f64" if a.op == "rk4" else "f32"
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; per-cell work has no cross-GPU traffic, "
                                    "so N GPUs would each run this workload on their own share of cells",
@@ -158,6 +276,10 @@ def main():
     from paper_2503_09580_amd import lincoll
 
     dev = torch.device("cuda:0")
+    if a.op == "quadcoll":
+        return bench_quadcoll(a, torch, lincoll, dev)
+    if a.op == "rk4":
+        return bench_rk4(a, torch, lincoll, dev)
     h, params, c = workload(a.config)
     n, L, om, B = c["n"], c["L"], c["omega"], h.shape[0]
     td = torch.float64 if a.dtype == "f64" else torch.float32

@@ -167,3 +167,17 @@ def burnett(n, L, nn, l):
     rad = eval_genlaguerre(nn, l + 0.5, r2 / 2.0) * r ** l
     ang = eval_legendre(l, c) if l > 0 else np.ones_like(c)
     return maxwellian(n, L, 1.0, (0, 0, 0), 1.0) * rad * ang
+
+
+def paper_f1(n, L):
+    """Initial/test distribution f^(1) of Sec. 4 (Cases of Sec. 4.1-4.2) as
+    printed: four shifted Gaussians, u = sqrt 2, theta = 1/3, prefactor
+    1/(4 pi^(3/2)) (its mass is (2/3)^(3/2), see the readings)."""
+    v = axis(n, L)
+    VX, VY, VZ = np.meshgrid(v, v, v, indexing="ij")
+    u, th = math.sqrt(2.0), 1.0 / 3.0
+
+    def e(a, b):
+        return np.exp(-((VX + a) ** 2 + (VY + b) ** 2 + VZ ** 2) / (2 * th))
+
+    return (e(u, 0) + e(-u, 0) + e(0, u) + e(0, -u)) / (4 * math.pi ** 1.5)

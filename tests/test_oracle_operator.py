@@ -208,12 +208,7 @@ def test_loss_terms_identical_between_methods():
 
 
 def f1(n, L):
-    """Test function f^(1) of Sec. 4 as printed (u = sqrt 2, theta = 1/3)."""
-    v = wl.axis(n, L)
-    VX, VY, VZ = np.meshgrid(v, v, v, indexing="ij")
-    u, th = math.sqrt(2.0), 1.0 / 3.0
-    e = lambda a, b: np.exp(-((VX + a) ** 2 + (VY + b) ** 2 + VZ ** 2) / (2 * th))
-    return (e(u, 0) + e(-u, 0) + e(0, u) + e(0, -u)) / (4 * math.pi ** 1.5)
+    return wl.paper_f1(n, L)
 
 
 def load_table1():
