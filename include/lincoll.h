@@ -129,7 +129,9 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_GRAPH 9         /* 1 if applies replay a captured graph (LINCOLL_OPT_GRAPH) */
 #define LINCOLL_INFO_FUSED_PER_CU 10 /* fused-path workgroups per compute unit in effect */
 #define LINCOLL_INFO_TUNED_MS 11     /* ms per apply of the configuration lincoll_autotune chose (0 if never run) */
-/* Reads one plan property into *val. */
+/* Reads one plan property into *val.  With plan == NULL only
+ * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
+ * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */
 int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
 
 /* Execution options (batching row of the design: launch shape and launch

@@ -86,8 +86,13 @@ namespace {
 
 size_t esize(int dtype) { return dtype == LINCOLL_F64 ? sizeof(double) : sizeof(float); }
 
+// Last HIP error seen on this thread (plan creation destroys a failed plan,
+// so its code is kept here as well).
+thread_local int g_last_hip = 0;
+
 int hip_fail(lincoll_plan_t pl, hipError_t e) {
   if (pl) pl->last_hip = (int)e;
+  g_last_hip = (int)e;
   return e == hipErrorOutOfMemory ? LINCOLL_ENOMEM : LINCOLL_EHIP;
 }
 
@@ -728,6 +733,10 @@ int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
 }
 
 int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
+  if (!pl && val && key == LINCOLL_INFO_HIP_ERROR) {   // last HIP error of this thread
+    *val = g_last_hip;
+    return LINCOLL_OK;
+  }
   if (!pl || !val) return LINCOLL_EINVAL;
   switch (key) {
     case LINCOLL_INFO_N: *val = pl->p.n; break;

@@ -27,9 +27,11 @@ SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll
 
 
 class LincollError(RuntimeError):
-    def __init__(self, status, what):
-        super().__init__(f"{what}: {_lib.lincoll_strerror(status).decode()} ({status})")
+    def __init__(self, status, what, hip_error=None):
+        extra = f", hipError {hip_error}" if hip_error else ""
+        super().__init__(f"{what}: {_lib.lincoll_strerror(status).decode()} ({status}{extra})")
         self.status = status
+        self.hip_error = hip_error
 
 
 class Params(ctypes.Structure):
@@ -40,6 +42,11 @@ class Params(ctypes.Structure):
 
 
 def _load():
+    # torch bundles its own HIP runtime with the same soname as the system
+    # one the library links; whichever is loaded first serves the process.
+    # Load torch's first so that the library and torch share one runtime
+    # (loading the library first left hipGetDevice without a device).
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"liblincoll.so not built at {LIB_PATH}; run python -m paper_2503_09580_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
@@ -101,7 +108,12 @@ def plan_tables(n, L, omega, table, **kw):
 
 def _check(st, what):
     if st != OK:
-        raise LincollError(st, what)
+        hip = None
+        if st == EHIP:
+            v = ctypes.c_double()
+            if _lib.lincoll_get_info(None, INFO["hip_error"], ctypes.byref(v)) == OK:
+                hip = int(v.value)
+        raise LincollError(st, what, hip)
 
 
 class Plan:

@@ -67,6 +67,7 @@ def test_null_handles_rejected():
     assert lib.quadcoll_apply(nullp, nullp, nullp, 1) == lc.EINVAL
     v = ctypes.c_double()
     assert lib.lincoll_get_info(nullp, 0, ctypes.byref(v)) == lc.EINVAL
+    assert lib.lincoll_get_info(nullp, lc.INFO["hip_error"], ctypes.byref(v)) == lc.OK   # thread's last HIP error
     assert lib.lincoll_set_option(nullp, 0, 1) == lc.EINVAL
     assert lib.lincoll_autotune(nullp, nullp, nullp, 1, 3) == lc.EINVAL
     lib.lincoll_destroy(nullp)
