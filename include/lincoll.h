@@ -41,6 +41,7 @@ extern "C" {
 #define LINCOLL_EHIP -3      /* a HIP runtime call failed (lincoll_get_info LINCOLL_INFO_HIP_ERROR) */
 #define LINCOLL_ENOTREADY -4 /* batch does not match the Maxwellians set (neither 1 nor batch) */
 #define LINCOLL_ENOTIMPL -5  /* operation not provided by this build */
+#define LINCOLL_EDIVERGED -6 /* an iterate left the admissible set (density or temperature <= 0, non-finite values) */
 
 typedef struct lincoll_plan_s* lincoll_plan_t;
 
@@ -129,6 +130,8 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_GRAPH 9         /* 1 if applies replay a captured graph (LINCOLL_OPT_GRAPH) */
 #define LINCOLL_INFO_FUSED_PER_CU 10 /* fused-path workgroups per compute unit in effect */
 #define LINCOLL_INFO_TUNED_MS 11     /* ms per apply of the configuration lincoll_autotune chose (0 if never run) */
+#define LINCOLL_INFO_L 12            /* half-width L of the velocity box */
+#define LINCOLL_INFO_PROJECT 13      /* 1 if applies return P L P */
 /* Reads one plan property into *val.  With plan == NULL only
  * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
  * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */
@@ -157,6 +160,7 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
 #define LINCOLL_OPT_PATH 2
 #define LINCOLL_OPT_SPHERE_POLAR 3    /* quadcoll: Gauss-Legendre order on [-1,1] (even, 2..64; positive nodes used) */
 #define LINCOLL_OPT_SPHERE_AZIMUTH 4  /* quadcoll: azimuths (1..256) */
+#define LINCOLL_OPT_PROJECT 5         /* 0 | 1: as lincoll_params_t.project */
 int lincoll_set_option(lincoll_plan_t plan, int key, int value);
 
 /* Launch-configuration tuner: times `reps` applies of every supported
@@ -175,6 +179,91 @@ int lincoll_autotune(lincoll_plan_t plan, const void* h, void* out, int batch, i
  * recorded once (for this f, batch and dt) and replayed.  Same batch rules
  * as lincoll_apply; steps >= 0. */
 int lincoll_rk4(lincoll_plan_t plan, void* f, int batch, double dt, int steps);
+
+/* ---- Steady 1-D problem with diffuse walls (Sec. 5, Appendix B) ----------
+ * v1 d_x f = Q(f,f)/Kn on x in (x_l, x_r), first-order upwind finite volumes
+ * (eq. (discrete_eq)) on nx cells, the plan's velocity grid, fully
+ * accommodating walls (eq. (maxwell_bc)) through ghost cells, and the
+ * total-mass constraint dx h_v^3 sum f = C (eq. (total_mass)).
+ * Readings this library takes where the printed scheme leaves a choice:
+ *   - wall densities make the discrete mass flux through each wall exactly
+ *     zero: ghost f_0 = rho_L E_L with rho_L = -sum v1- f_1 / sum v1+ E_L,
+ *     E_W(v) = exp(-|v-u_W|^2/(2 theta_W)), and the mirror image at x_r (the
+ *     printed constants are the continuum limit of this normalisation);
+ *   - the residual r = T[f] - Q(f,f)/Kn uses Q with the mass fix Q^_0 = 0
+ *     (Sec. 2.3), i.e. Q minus its mean over the velocity grid, per cell;
+ *   - the modified Newton operator (eq. (modified_Newton)) is
+ *     A g = T[g] - P L P g / Kn with L about each cell's local Maxwellian
+ *     (its discrete density, velocity and temperature) and P the invariant
+ *     projection of lincoll_project, so every Krylov vector keeps zero mass;
+ *   - every Newton iterate, and the initial guess of eq. (initial), is
+ *     rescaled to the discrete mass C.
+ * Norms: sqrt(dx h_v^3 sum r^2) (Appendix B).
+ * Arrays f, r, g, out: device double [nx][n][n][n] (cell-major; the plan's
+ * velocity layout inside a cell).  The plan supplies n, L, the collision
+ * kernel, the hemisphere rule of quadcoll_apply (residual, FP64 always) and
+ * the apply dtype of the Newton operator; these calls replace its Maxwellians
+ * with the local ones of f and use its stream.  Work memory is allocated per
+ * call and freed before return; every call synchronises the plan's stream. */
+typedef struct {
+  int nx;                   /* cells, >= 1 (and <= the plan's max_batch if set) */
+  double x_l, x_r;          /* slab ends, x_l < x_r (default -0.5, 0.5) */
+  double kn;                /* Knudsen number > 0 (default 0.1) */
+  double mass;              /* C > 0 (default 1) */
+  double theta_l, theta_r;  /* wall temperatures > 0 (default 1, 1.5) */
+  double u_l[3], u_r[3];    /* wall velocities (default 0) */
+  double tol;               /* Newton stops when the residual norm < tol (default 1e-5) */
+  double inner_rtol;        /* inner stop: residual <= inner_rtol * |r| ... (default 1e-3) */
+  double inner_atol;        /* ... or <= inner_atol (default 1e-7) (Sec. 5.2) */
+  int max_newton;           /* Newton steps, >= 0 (default 30) */
+  int max_inner;            /* inner iterations per Newton step, >= 1 (default 2000) */
+  int restart;              /* GMRES cycle length, 1..64 (default 30) */
+  int init;                 /* 1: start from eq. (initial); 0: from f as passed (default 1) */
+  int precond;              /* right preconditioner of the inner GMRES, lincoll_precond_t (default SWEEP) */
+} lincoll_steady_params_t;
+
+typedef enum {
+  LINCOLL_PRECOND_NONE = 0,  /* plain GMRES */
+  LINCOLL_PRECOND_SWEEP = 1  /* one transport sweep z = (T + diag(nu)/Kn)^-1 y: the upwind recurrence of the
+                                source iteration (Sec. 5.1) with nu(v) the loss collision frequency of each
+                                cell's L; left wall ghost from z, right ghost empty (a fixed linear map) */
+} lincoll_precond_t;
+
+typedef struct {
+  int newton_iters;         /* Newton steps taken (= binary-operator evaluations - 1) */
+  int inner_iters;          /* linearized-operator evaluations, all steps */
+  int converged;            /* 1 if the residual fell below tol */
+  double residual;          /* final residual norm */
+  double mass;              /* final discrete mass */
+  double res_history[65];   /* residual norm before step k, k = 0..min(newton_iters, 64) */
+  int inner_history[64];    /* inner iterations of step k */
+  double ms_total, ms_residual, ms_inner;   /* wall clock: whole solve, residuals, inner solves */
+} lincoll_steady_report_t;
+
+/* Fills *sp with the defaults above for nx cells. */
+void lincoll_steady_default(lincoll_steady_params_t* sp, int nx);
+
+/* r = T[f] - (Q(f,f) - mean Q)/Kn per cell (eq. (discrete_eq) as a
+ * residual); *norm (host, may be NULL) = its norm.  r may be NULL to get the
+ * norm only.  f and r must not overlap.  Synchronous. */
+int lincoll_steady_residual(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f, double* r,
+                            double* norm);
+
+/* out = T[g] - P L P g / Kn with L about the local Maxwellians of f (the
+ * modified Newton operator, eq. (modified_Newton)); the plan's Maxwellians
+ * are set to those of f.  g and out must not overlap.  Synchronous. */
+int lincoll_steady_newton_apply(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                                const double* g, double* out);
+
+/* Modified Newton iteration (Sec. 5.1): f <- f - g with A g = r(f) solved by
+ * restarted flexible GMRES from g = 0 (right preconditioner sp->precond,
+ * classical Gram-Schmidt, FP64 vectors, the plan's apply dtype inside A) to
+ * the inner tolerances; stops at the
+ * residual tolerance or after max_newton steps.  f is overwritten with the
+ * last iterate; rep (host, may be NULL) receives the history.  Returns
+ * LINCOLL_OK also when not converged (see rep->converged). */
+int lincoll_steady_solve(lincoll_plan_t plan, const lincoll_steady_params_t* sp, double* f,
+                         lincoll_steady_report_t* rep);
 
 /* Releases everything the plan owns (waits for its stream first). */
 void lincoll_destroy(lincoll_plan_t plan);

@@ -270,6 +270,7 @@ const char* lincoll_strerror(int s) {
     case LINCOLL_EHIP: return "HIP runtime error";
     case LINCOLL_ENOTREADY: return "Maxwellians not set for this batch";
     case LINCOLL_ENOTIMPL: return "not implemented";
+    case LINCOLL_EDIVERGED: return "iteration diverged";
   }
   return "unknown status";
 }
@@ -533,6 +534,10 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       if (value < 1 || value > 256) return LINCOLL_EINVAL;
       pl->sphere_azim = value;
       break;
+    case LINCOLL_OPT_PROJECT:
+      if (value != 0 && value != 1) return LINCOLL_EINVAL;
+      pl->p.project = value;
+      break;
     case LINCOLL_OPT_PATH:
       if (value < LINCOLL_PATH_AUTO || value > LINCOLL_PATH_FUSED) return LINCOLL_EINVAL;
       if (value == LINCOLL_PATH_FUSED && !fused_supported(pl->p.n, pl->p.dtype)) return LINCOLL_EINVAL;
@@ -732,6 +737,19 @@ int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
   return LINCOLL_OK;
 }
 
+}  // extern "C"
+
+namespace lincoll {
+hipStream_t plan_stream(const lincoll_plan_s* pl) { return pl->stream; }
+const void* plan_nu(const lincoll_plan_s* pl) { return pl->d_nu; }
+void plan_note_hip(lincoll_plan_s* pl, hipError_t e) {
+  pl->last_hip = (int)e;
+  g_last_hip = (int)e;
+}
+}  // namespace lincoll
+
+extern "C" {
+
 int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
   if (!pl && val && key == LINCOLL_INFO_HIP_ERROR) {   // last HIP error of this thread
     *val = g_last_hip;
@@ -753,6 +771,8 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
       *val = pl->opt_per_cu > 0 ? pl->opt_per_cu : fused_max_per_cu(pl->p.n);
       break;
     case LINCOLL_INFO_TUNED_MS: *val = pl->tuned_ms; break;
+    case LINCOLL_INFO_L: *val = pl->p.L; break;
+    case LINCOLL_INFO_PROJECT: *val = pl->p.project; break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;

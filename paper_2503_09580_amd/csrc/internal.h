@@ -4,7 +4,16 @@
 
 #include <cstdint>
 
+struct lincoll_plan_s;
+
 namespace lincoll {
+
+// Plan accessors for host code outside the ABI translation unit.
+hipStream_t plan_stream(const lincoll_plan_s* pl);
+void plan_note_hip(lincoll_plan_s* pl, hipError_t e);   // records e as the plan's last HIP error
+// Loss collision frequency nu = iDFT[Omega DFT[M]] of the Maxwellians set,
+// [Bc][n^3], double for LINCOLL_F64 plans and float otherwise.
+const void* plan_nu(const lincoll_plan_s* pl);
 
 // Row strides of the device mode tables (K_j octants and Phi_j radial
 // tables), padded to whole blocks of 512 values so that the fused kernel copies

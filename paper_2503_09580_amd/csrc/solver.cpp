@@ -1,0 +1,441 @@
+// Steady 1-D problem with diffuse walls (Sec. 5, Appendix B): residual,
+// modified Newton operator and the modified Newton iteration with restarted
+// GMRES as the inner solver.  Host orchestration only; the operator
+// applications are the library's own entry points (quadcoll_apply for the
+// residual, lincoll_apply with the invariant projection inside the Newton
+// operator) and the remaining steps are the kernels of steady.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lincoll.h"
+#include "internal.h"
+#include "steady.h"
+
+using namespace lincoll;
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); }
+
+#define HIPCK(x)                                                             \
+  do {                                                                       \
+    const hipError_t e_ = (x);                                               \
+    if (e_ != hipSuccess) {                                                  \
+      plan_note_hip(pl, e_);                                                 \
+      return e_ == hipErrorOutOfMemory ? LINCOLL_ENOMEM : LINCOLL_EHIP;      \
+    }                                                                        \
+  } while (0)
+#define STCK(x)                 \
+  do {                          \
+    const int s_ = (x);         \
+    if (s_ != LINCOLL_OK) return s_; \
+  } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_params(const lincoll_steady_params_t* sp) {
+  if (!sp || sp->nx < 1) return LINCOLL_EINVAL;
+  if (!std::isfinite(sp->x_l) || !std::isfinite(sp->x_r) || !(sp->x_l < sp->x_r)) return LINCOLL_EINVAL;
+  if (!finite_pos(sp->kn) || !finite_pos(sp->mass) || !finite_pos(sp->theta_l) || !finite_pos(sp->theta_r))
+    return LINCOLL_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(sp->u_l[d]) || !std::isfinite(sp->u_r[d])) return LINCOLL_EINVAL;
+  if (!(sp->tol >= 0.0) || !(sp->inner_rtol >= 0.0) || !(sp->inner_atol >= 0.0)) return LINCOLL_EINVAL;
+  if (sp->max_newton < 0 || sp->max_inner < 1 || sp->restart < 1 || sp->restart > GMRES_MAXK - 1)
+    return LINCOLL_EINVAL;
+  if (sp->init != 0 && sp->init != 1) return LINCOLL_EINVAL;
+  if (sp->precond != LINCOLL_PRECOND_NONE && sp->precond != LINCOLL_PRECOND_SWEEP) return LINCOLL_EINVAL;
+  return LINCOLL_OK;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+struct Solver {
+  lincoll_plan_t pl = nullptr;
+  hipStream_t s = nullptr;
+  lincoll_steady_params_t sp{};
+  int n = 0, nx = 0, dtype = 0;
+  long n3 = 0, N = 0;
+  double L = 0.0, hv = 0.0, h3 = 0.0, dx = 0.0, wnorm = 0.0;   // wnorm = sqrt(dx h_v^3)
+  WallGeom wg{};
+  int project_before = 0;
+  bool project_set = false;
+  long matvecs = 0;
+  std::vector<void*> owned;
+  // small buffers
+  double *d_sums = nullptr, *d_ysums = nullptr, *d_params = nullptr, *d_wall = nullptr;
+  double *d_partial = nullptr, *d_red = nullptr, *d_y = nullptr;
+  // fields of N values
+  double* d_q = nullptr;   // Q(f, f)
+  void* d_in = nullptr;    // apply input (plan dtype)
+  void* d_o = nullptr;     // apply output (plan dtype)
+
+  ~Solver() {
+    if (s) (void)hipStreamSynchronize(s);
+    for (void* p : owned) (void)hipFree(p);
+    if (project_set) (void)lincoll_set_option(pl, LINCOLL_OPT_PROJECT, project_before);
+  }
+
+  template <typename P>
+  int alloc(P** p, size_t bytes) {
+    void* q = nullptr;
+    HIPCK(hipMalloc(&q, bytes));
+    owned.push_back(q);
+    *p = static_cast<P*>(q);
+    return LINCOLL_OK;
+  }
+
+  int init(lincoll_plan_t plan, const lincoll_steady_params_t* params) {
+    pl = plan;
+    if (!pl) return LINCOLL_EINVAL;
+    STCK(check_params(params));
+    sp = *params;
+    double v;
+    STCK(lincoll_get_info(pl, LINCOLL_INFO_N, &v));
+    n = (int)v;
+    if (n != 8 && n != 16 && n != 32) return LINCOLL_ENOTIMPL;   // the residual's binary operator
+    STCK(lincoll_get_info(pl, LINCOLL_INFO_DTYPE, &v));
+    dtype = (int)v;
+    STCK(lincoll_get_info(pl, LINCOLL_INFO_L, &v));
+    L = v;
+    STCK(lincoll_get_info(pl, LINCOLL_INFO_PROJECT, &v));
+    project_before = (int)v;
+    s = plan_stream(pl);
+    nx = sp.nx;
+    n3 = (long)n * n * n;
+    N = (long)nx * n3;
+    hv = 2.0 * L / n;
+    h3 = hv * hv * hv;
+    dx = (sp.x_r - sp.x_l) / nx;
+    wnorm = std::sqrt(dx * h3);
+    // walls: shapes E_W and the incoming-flux normalisations sum v1+ E_L, sum v1- E_R
+    const double* us[2] = {sp.u_l, sp.u_r};
+    const double th[2] = {sp.theta_l, sp.theta_r};
+    for (int w = 0; w < 2; ++w) {
+      for (int d = 0; d < 3; ++d) wg.u[w][d] = us[w][d];
+      wg.theta[w] = th[w];
+      double acc = 0.0;
+      for (int i1 = 0; i1 < n; ++i1) {
+        const double v1 = -L + i1 * hv;
+        if (w == 0 ? !(v1 > 0.0) : !(v1 < 0.0)) continue;
+        for (int i2 = 0; i2 < n; ++i2)
+          for (int i3 = 0; i3 < n; ++i3) {
+            const double a = v1 - us[w][0], b = -L + i2 * hv - us[w][1], c = -L + i3 * hv - us[w][2];
+            acc += v1 * std::exp(-(a * a + b * b + c * c) / (2.0 * th[w]));
+          }
+      }
+      if (acc == 0.0) return LINCOLL_EINVAL;
+      wg.flux_in[w] = acc;
+    }
+    const size_t nb = vec_blocks(N);
+    STCK(alloc(&d_sums, (size_t)nx * SUMS_STRIDE * sizeof(double)));
+    STCK(alloc(&d_ysums, (size_t)nx * SUMS_STRIDE * sizeof(double)));
+    STCK(alloc(&d_params, (size_t)nx * 5 * sizeof(double)));
+    STCK(alloc(&d_wall, 8 * sizeof(double)));
+    STCK(alloc(&d_partial, nb * GMRES_MAXK * sizeof(double)));
+    STCK(alloc(&d_red, (GMRES_MAXK + 1) * sizeof(double)));
+    STCK(alloc(&d_y, GMRES_MAXK * sizeof(double)));
+    return LINCOLL_OK;
+  }
+
+  int host_copy(void* dst, const void* src, size_t bytes) {
+    HIPCK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    return LINCOLL_OK;
+  }
+
+  // plain dot product <a, b> on the host
+  int dot(const double* a, const double* b, double* out) {
+    HIPCK(st_mdot(a, N, 1, b, d_partial, d_red, s));
+    return host_copy(out, d_red, sizeof(double));
+  }
+
+  // r = T[f] - (Q(f,f) - mean Q)/Kn; *norm = sqrt(dx h^3 |r|^2)
+  int residual(const double* f, double* r, double* norm) {
+    if (!d_q) STCK(alloc(&d_q, (size_t)N * sizeof(double)));
+    STCK(quadcoll_apply(pl, f, d_q, nx));
+    HIPCK(st_cell_sums(d_q, nx, n, L, d_ysums, s));
+    HIPCK(st_wall_sums(f, nx, n, L, d_wall, s));
+    HIPCK(st_transport(f, d_wall, wg, d_q, 0, -1.0 / sp.kn, d_ysums, r, nx, n, L, dx, s));
+    if (norm) {
+      double v = 0.0;
+      STCK(dot(r, r, &v));
+      *norm = std::sqrt(v) * wnorm;
+    }
+    return LINCOLL_OK;
+  }
+
+  // Maxwellians of the plan <- local Maxwellians of f (checked on the host)
+  int set_local(const double* f) {
+    HIPCK(st_cell_sums(f, nx, n, L, d_sums, s));
+    HIPCK(st_params(d_sums, nx, n, L, d_params, s));
+    std::vector<double> hp((size_t)nx * 5);
+    STCK(host_copy(hp.data(), d_params, hp.size() * sizeof(double)));
+    for (int c = 0; c < nx; ++c) {
+      const double* q = &hp[(size_t)c * 5];
+      if (!finite_pos(q[0]) || !finite_pos(q[4]) || !std::isfinite(q[1]) || !std::isfinite(q[2]) ||
+          !std::isfinite(q[3]))
+        return LINCOLL_EDIVERGED;
+    }
+    STCK(lincoll_set_maxwellians(pl, d_params, nx));
+    if (!project_set) {
+      STCK(lincoll_set_option(pl, LINCOLL_OPT_PROJECT, 1));
+      project_set = true;
+    }
+    return LINCOLL_OK;
+  }
+
+  // out = T[x] - P L P x / Kn about the Maxwellians set by set_local
+  int matvec(const double* x, double* out) {
+    if (!d_o) {
+      const size_t es = dtype == LINCOLL_F64 ? sizeof(double) : sizeof(float);
+      STCK(alloc(&d_in, (size_t)N * es));
+      STCK(alloc(&d_o, (size_t)N * es));
+    }
+    // the apply always reads the same buffer, so a recorded graph replays
+    if (dtype == LINCOLL_F64)
+      HIPCK(st_axpby(static_cast<double*>(d_in), 1.0, x, 0.0, nullptr, N, s));
+    else
+      HIPCK(st_to_f32(x, static_cast<float*>(d_in), N, s));
+    STCK(lincoll_apply(pl, d_in, d_o, nx));
+    HIPCK(st_wall_sums(x, nx, n, L, d_wall, s));
+    HIPCK(st_transport(x, d_wall, wg, d_o, dtype != LINCOLL_F64, -1.0 / sp.kn, nullptr, out, nx, n, L, dx, s));
+    ++matvecs;
+    return LINCOLL_OK;
+  }
+
+  // rescales f to the discrete mass C; *mass_before receives its mass before
+  int constrain(double* f, double* mass_before) {
+    HIPCK(st_cell_sums(f, nx, n, L, d_sums, s));
+    std::vector<double> hs((size_t)nx * SUMS_STRIDE);
+    STCK(host_copy(hs.data(), d_sums, hs.size() * sizeof(double)));
+    double m = 0.0;
+    for (int c = 0; c < nx; ++c) m += hs[(size_t)c * SUMS_STRIDE];
+    m *= dx * h3;
+    if (mass_before) *mass_before = m;
+    if (!finite_pos(m)) return LINCOLL_EDIVERGED;
+    HIPCK(st_axpby(f, sp.mass / m, f, 0.0, nullptr, N, s));
+    return LINCOLL_OK;
+  }
+
+  // z = M^-1 v, the right preconditioner (z = v without one)
+  int precondition(const double* v, double* z) {
+    if (sp.precond == LINCOLL_PRECOND_SWEEP)
+      HIPCK(st_sweep(v, z, plan_nu(pl), dtype != LINCOLL_F64, d_wall, wg, nx, n, L, dx, sp.kn, s));
+    else
+      HIPCK(st_axpby(z, 1.0, v, 0.0, nullptr, N, s));
+    return LINCOLL_OK;
+  }
+
+  // Restarted flexible GMRES for A x = b from x = 0 with right
+  // preconditioning (A M^-1 u = b, x = M^-1 u; the preconditioned vectors Z
+  // are kept, so M may change between iterations) and classical Gram-Schmidt.
+  // Stops when the weighted residual <= max(inner_rtol |b|, inner_atol) or
+  // after max_inner operator evaluations.  V: (restart + 1) vectors, Z:
+  // restart vectors, tmp: one.
+  int gmres(const double* b, double bnorm, double* x, double* V, double* Z, double* tmp, int* iters) {
+    const int m = sp.restart;
+    const double target = std::max(sp.inner_rtol * bnorm * wnorm, sp.inner_atol) / wnorm;   // plain norm
+    const long start = matvecs;
+    HIPCK(hipMemsetAsync(x, 0, (size_t)N * sizeof(double), s));
+    double beta = bnorm;
+    *iters = 0;
+    if (!(beta > target)) return LINCOLL_OK;
+    HIPCK(st_axpby(V, 1.0 / beta, b, 0.0, nullptr, N, s));
+    std::vector<double> R((size_t)m * m, 0.0), cs(m), sn(m), g(m + 1), col(m + 2), y(m);
+    for (;;) {
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int j = 0;
+      bool stop = false;
+      while (j < m) {
+        double* w = V + (long)(j + 1) * N;
+        double* zj = Z + (long)j * N;
+        STCK(precondition(V + (long)j * N, zj));
+        STCK(matvec(zj, w));
+        HIPCK(st_mdot(V, N, j + 1, w, d_partial, d_red, s));
+        HIPCK(st_update(w, V, N, j + 1, d_red, d_partial, d_red + (j + 1), s));
+        STCK(host_copy(col.data(), d_red, (size_t)(j + 2) * sizeof(double)));
+        const double hn = std::sqrt(std::max(col[j + 1], 0.0));
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+          col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+          col[i] = t;
+        }
+        const double rr = std::hypot(col[j], col[j + 1]);
+        cs[j] = rr > 0.0 ? col[j] / rr : 1.0;
+        sn[j] = rr > 0.0 ? col[j + 1] / rr : 0.0;
+        col[j] = rr;
+        for (int i = 0; i <= j; ++i) R[(size_t)i * m + j] = col[i];
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        const double resid = std::fabs(g[j + 1]);
+        ++j;
+        if (!(hn > 0.0) || !std::isfinite(resid)) {   // breakdown (exact) or non-finite values
+          stop = true;
+          break;
+        }
+        HIPCK(st_axpby(w, 1.0 / hn, w, 0.0, nullptr, N, s));
+        if (resid <= target || matvecs - start >= sp.max_inner) {
+          stop = true;
+          break;
+        }
+      }
+      for (int i = j - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < j; ++k) t -= R[(size_t)i * m + k] * y[k];
+        y[i] = t / R[(size_t)i * m + i];
+      }
+      HIPCK(hipMemcpyAsync(d_y, y.data(), (size_t)j * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCK(st_combine(x, Z, N, j, d_y, s));
+      HIPCK(hipStreamSynchronize(s));   // y is read from host memory
+      if (stop || matvecs - start >= sp.max_inner) break;
+      // restart from the true residual b - A x
+      STCK(matvec(x, tmp));
+      HIPCK(st_axpby(V, 1.0, b, -1.0, tmp, N, s));
+      double bb = 0.0;
+      STCK(dot(V, V, &bb));
+      beta = std::sqrt(bb);
+      if (!(beta > target) || matvecs - start >= sp.max_inner) break;
+      HIPCK(st_axpby(V, 1.0 / beta, V, 0.0, nullptr, N, s));
+    }
+    *iters = (int)(matvecs - start);
+    return LINCOLL_OK;
+  }
+
+  int solve(double* f, lincoll_steady_report_t* rep) {
+    const clk::time_point t0 = clk::now();
+    lincoll_steady_report_t rp;
+    std::memset(&rp, 0, sizeof(rp));
+    double *r = nullptr, *gcor = nullptr, *V = nullptr, *Z = nullptr, *tmp = nullptr;
+    STCK(alloc(&r, (size_t)N * sizeof(double)));
+    STCK(alloc(&gcor, (size_t)N * sizeof(double)));
+    STCK(alloc(&tmp, (size_t)N * sizeof(double)));
+    STCK(alloc(&V, (size_t)(sp.restart + 1) * N * sizeof(double)));
+    STCK(alloc(&Z, (size_t)sp.restart * N * sizeof(double)));
+    if (sp.init) HIPCK(st_initial(f, nx, n, L, sp.x_l, sp.x_r, sp.theta_l, sp.theta_r, sp.mass, s));
+    int status = constrain(f, nullptr);
+    for (int k = 0; status == LINCOLL_OK; ++k) {
+      clk::time_point t = clk::now();
+      double res = 0.0;
+      if ((status = residual(f, r, &res))) break;
+      rp.ms_residual += ms_since(t);
+      if (k <= 64) rp.res_history[k] = res;
+      rp.residual = res;
+      if (!std::isfinite(res)) {
+        status = LINCOLL_EDIVERGED;
+        break;
+      }
+      if (res < sp.tol) {
+        rp.converged = 1;
+        break;
+      }
+      if (k == sp.max_newton) break;
+      t = clk::now();
+      int its = 0;
+      if ((status = set_local(f)) || (status = gmres(r, res / wnorm, gcor, V, Z, tmp, &its))) break;
+      rp.ms_inner += ms_since(t);
+      if (k < 64) rp.inner_history[k] = its;
+      rp.inner_iters += its;
+      rp.newton_iters = k + 1;
+      if (hipError_t e = st_axpby(f, 1.0, f, -1.0, gcor, N, s)) {
+        plan_note_hip(pl, e);
+        status = LINCOLL_EHIP;
+        break;
+      }
+      status = constrain(f, nullptr);
+    }
+    if (status == LINCOLL_OK || status == LINCOLL_EDIVERGED) {
+      double m = 0.0;
+      if (constrain_mass(f, &m) == LINCOLL_OK) rp.mass = m;
+    }
+    rp.ms_total = ms_since(t0);
+    if (rep) *rep = rp;
+    return status;
+  }
+
+  // discrete mass of f (no rescaling)
+  int constrain_mass(const double* f, double* m) {
+    HIPCK(st_cell_sums(f, nx, n, L, d_sums, s));
+    std::vector<double> hs((size_t)nx * SUMS_STRIDE);
+    STCK(host_copy(hs.data(), d_sums, hs.size() * sizeof(double)));
+    double t = 0.0;
+    for (int c = 0; c < nx; ++c) t += hs[(size_t)c * SUMS_STRIDE];
+    *m = t * dx * h3;
+    return LINCOLL_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void lincoll_steady_default(lincoll_steady_params_t* sp, int nx) {
+  if (!sp) return;
+  std::memset(sp, 0, sizeof(*sp));
+  sp->nx = nx;
+  sp->x_l = -0.5;
+  sp->x_r = 0.5;
+  sp->kn = 0.1;
+  sp->mass = 1.0;
+  sp->theta_l = 1.0;
+  sp->theta_r = 1.5;
+  sp->tol = 1e-5;
+  sp->inner_rtol = 1e-3;
+  sp->inner_atol = 1e-7;
+  sp->max_newton = 30;
+  sp->max_inner = 2000;
+  sp->restart = 30;
+  sp->init = 1;
+  sp->precond = LINCOLL_PRECOND_SWEEP;
+}
+
+int lincoll_steady_residual(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f, double* r,
+                            double* norm) {
+  if (!plan || !f) return LINCOLL_EINVAL;
+  Solver S;
+  STCK(S.init(plan, sp));
+  if (r && overlap(f, r, (size_t)S.N * sizeof(double))) return LINCOLL_EINVAL;
+  double* out = r;
+  if (!out) STCK(S.alloc(&out, (size_t)S.N * sizeof(double)));
+  double v = 0.0;
+  STCK(S.residual(f, out, &v));
+  lincoll_plan_t pl = plan;
+  HIPCK(hipStreamSynchronize(S.s));
+  if (norm) *norm = v;
+  return LINCOLL_OK;
+}
+
+int lincoll_steady_newton_apply(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                                const double* g, double* out) {
+  if (!plan || !f || !g || !out) return LINCOLL_EINVAL;
+  Solver S;
+  STCK(S.init(plan, sp));
+  if (overlap(g, out, (size_t)S.N * sizeof(double))) return LINCOLL_EINVAL;
+  STCK(S.set_local(f));
+  STCK(S.matvec(g, out));
+  lincoll_plan_t pl = plan;
+  HIPCK(hipStreamSynchronize(S.s));
+  return LINCOLL_OK;
+}
+
+int lincoll_steady_solve(lincoll_plan_t plan, const lincoll_steady_params_t* sp, double* f,
+                         lincoll_steady_report_t* rep) {
+  if (!plan || !f) return LINCOLL_EINVAL;
+  Solver S;
+  STCK(S.init(plan, sp));
+  return S.solve(f, rep);
+}
+
+}  // extern "C"

@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, double2
   if (gid >= (long)batch * HALF) return;
   const int cell = (int)(gid / HALF), c = (int)(gid % HALF);
   const int x = c / (NN / 2), y1 = c % (NN / 2), y2 = y1 + NN / 2;
-  const int col1 = x * NN + y1, col2 = col1 + NN / 2;
+  const int col1 = x * NN + y1;
   const int cc = Bc > 1 ? cell : 0;
   const TS* f = fac + (size_t)cc * 6 * NN;
   const T mx = T(pref[2 * cc]) * T(f[x]);

@@ -13,17 +13,19 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "liblincoll.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENOTIMPL = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENOTIMPL, EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 DTYPES = {"f64": 0, "f32": 1, "bf16x3": 2}
 PATHS = {"auto": 0, "staged": 1, "fused": 2}
 TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
 INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
-        "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11}
-OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2, "sphere_polar": 3, "sphere_azimuth": 4}
+        "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11, "L": 12, "project": 13}
+PRECONDS = {"none": 0, "sweep": 1}
+OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2, "sphere_polar": 3, "sphere_azimuth": 4, "project": 5}
 SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
            "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
            "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",
-           "lincoll_set_option", "lincoll_autotune", "lincoll_rk4"]
+           "lincoll_set_option", "lincoll_autotune", "lincoll_rk4", "lincoll_steady_default",
+           "lincoll_steady_residual", "lincoll_steady_newton_apply", "lincoll_steady_solve"]
 
 
 class LincollError(RuntimeError):
@@ -39,6 +41,43 @@ class Params(ctypes.Structure):
                 ("C", ctypes.c_double), ("R", ctypes.c_double), ("J", ctypes.c_int),
                 ("eps", ctypes.c_double), ("quad_rule", ctypes.c_int), ("project", ctypes.c_int),
                 ("max_batch", ctypes.c_int), ("dtype", ctypes.c_int), ("path", ctypes.c_int)]
+
+
+class SteadyParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("x_l", ctypes.c_double), ("x_r", ctypes.c_double),
+                ("kn", ctypes.c_double), ("mass", ctypes.c_double), ("theta_l", ctypes.c_double),
+                ("theta_r", ctypes.c_double), ("u_l", ctypes.c_double * 3), ("u_r", ctypes.c_double * 3),
+                ("tol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("inner_atol", ctypes.c_double),
+                ("max_newton", ctypes.c_int), ("max_inner", ctypes.c_int), ("restart", ctypes.c_int),
+                ("init", ctypes.c_int), ("precond", ctypes.c_int)]
+
+
+class SteadyReport(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("converged", ctypes.c_int),
+                ("residual", ctypes.c_double), ("mass", ctypes.c_double),
+                ("res_history", ctypes.c_double * 65), ("inner_history", ctypes.c_int * 64),
+                ("ms_total", ctypes.c_double), ("ms_residual", ctypes.c_double), ("ms_inner", ctypes.c_double)]
+
+    def as_dict(self):
+        k = min(self.newton_iters, 64)
+        return {"newton_iters": self.newton_iters, "inner_iters": self.inner_iters,
+                "converged": bool(self.converged), "residual": self.residual, "mass": self.mass,
+                "res_history": list(self.res_history[:k + 1]), "inner_history": list(self.inner_history[:k]),
+                "ms_total": self.ms_total, "ms_residual": self.ms_residual, "ms_inner": self.ms_inner}
+
+
+def steady_params(nx, **kw):
+    """SteadyParams with the library defaults for nx cells, then kw
+    (u_l / u_r as 3-sequences)."""
+    sp = SteadyParams()
+    _lib.lincoll_steady_default(ctypes.byref(sp), int(nx))
+    for k, v in kw.items():
+        if k in ("u_l", "u_r"):
+            v = (ctypes.c_double * 3)(*[float(a) for a in v])
+        if k == "precond" and isinstance(v, str):
+            v = PRECONDS[v]
+        setattr(sp, k, v)
+    return sp
 
 
 def _load():
@@ -68,6 +107,10 @@ def _load():
         "lincoll_set_option": (i, [vp, i, i]),
         "lincoll_autotune": (i, [vp, vp, vp, i, i]),
         "lincoll_rk4": (i, [vp, vp, i, d, i]),
+        "lincoll_steady_default": (None, [P(SteadyParams), i]),
+        "lincoll_steady_residual": (i, [vp, P(SteadyParams), vp, vp, P(d)]),
+        "lincoll_steady_newton_apply": (i, [vp, P(SteadyParams), vp, vp, vp]),
+        "lincoll_steady_solve": (i, [vp, P(SteadyParams), vp, P(SteadyReport)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -218,6 +261,40 @@ class Plan:
         _check(_lib.lincoll_rk4(self._h, self._dev(f, self.tdtype, (n, n, n), "f"), f.shape[0], float(dt),
                                 int(steps)), "lincoll_rk4")
         return f
+
+    def _field(self, t, name):
+        n = self.n
+        if t.dim() != 4 or tuple(t.shape[1:]) != (n, n, n):
+            raise ValueError(f"{name} must be [nx, {n}, {n}, {n}]")
+        return self._dev(t, self._torch.float64, None, name)
+
+    def steady_residual(self, sp, f, r=None):
+        """(r, norm): residual of the steady problem sp (SteadyParams) at f
+        (float64 CUDA tensor [nx, n, n, n])."""
+        if r is None:
+            r = self._torch.empty_like(f)
+        v = ctypes.c_double()
+        self._sync_stream()
+        _check(_lib.lincoll_steady_residual(self._h, ctypes.byref(sp), self._field(f, "f"), self._field(r, "r"),
+                                            ctypes.byref(v)), "lincoll_steady_residual")
+        return r, v.value
+
+    def steady_newton_apply(self, sp, f, g, out=None):
+        """out = T[g] - P L P g / Kn about the local Maxwellians of f."""
+        if out is None:
+            out = self._torch.empty_like(g)
+        self._sync_stream()
+        _check(_lib.lincoll_steady_newton_apply(self._h, ctypes.byref(sp), self._field(f, "f"), self._field(g, "g"),
+                                                self._field(out, "out")), "lincoll_steady_newton_apply")
+        return out
+
+    def steady_solve(self, sp, f):
+        """Modified Newton solve in place on f; returns the report as a dict."""
+        rep = SteadyReport()
+        self._sync_stream()
+        _check(_lib.lincoll_steady_solve(self._h, ctypes.byref(sp), self._field(f, "f"), ctypes.byref(rep)),
+               "lincoll_steady_solve")
+        return rep.as_dict()
 
     def info(self, key):
         v = ctypes.c_double()

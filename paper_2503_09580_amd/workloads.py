@@ -15,6 +15,10 @@ the configurations below are synthetic stand-ins of the same kind:
       drifting anisotropic (bi-)Maxwellian; also Burnett functions (omega=1)
   C3  n=32, L=8,  omega=0.74, 4096 cells along a 1-D grid with sinusoidal
       rho, u, theta (amplitude 0.2), h_i = M_i p_i((v-u_i)/sqrt(theta_i))
+  C4  n=32, L=8,  omega=0.74, the steady 1-D slab x in [-0.5, 0.5] on 256
+      cells, wall temperatures 1 and 1.5, Kn = 0.1, total mass 1 (Sec. 5.2,
+      the heat-transfer case); states from the solver, test states from
+      slab_state
   C5  n=64, L=10, omega=0.74, 512 cells, rho=1, u=0, theta log-uniform in
       [0.5, 2], h_i = M_i p_i(v/sqrt(theta_i))
 p is a polynomial of total degree <= 4 (35 monomials) with coefficients
@@ -29,6 +33,7 @@ CONFIGS = {
     "C2": dict(n=32, L=8.0, omega=0.74, batch=64, seed=202),
     "C3": dict(n=32, L=8.0, omega=0.74, batch=4096, seed=303),
     "C5": dict(n=64, L=10.0, omega=0.74, batch=512, seed=505),
+    "C4": dict(n=32, L=8.0, omega=0.74, nx=256, kn=0.1, theta_l=1.0, theta_r=1.5, mass=1.0),
 }
 
 MONOMIALS = [(a, b, c) for a in range(5) for b in range(5) for c in range(5) if a + b + c <= 4]
@@ -181,3 +186,24 @@ def paper_f1(n, L):
         return np.exp(-((VX + a) ** 2 + (VY + b) ** 2 + VZ ** 2) / (2 * th))
 
     return (e(u, 0) + e(-u, 0) + e(0, u) + e(0, -u)) / (4 * math.pi ** 1.5)
+
+
+def slab_state(n, L, nx, theta_l=1.0, theta_r=1.5, seed=404, amp=0.05):
+    """Seeded non-equilibrium states of the 1-D slab on nx cells: per cell a
+    Maxwellian whose temperature runs linearly from theta_l to theta_r, with
+    density and drift perturbed by amp-sized seeded values, times
+    (1 + p((v-u)/sqrt(theta))) with a small seeded polynomial p; and a
+    seeded perturbation g of the same shape (M_c times a polynomial).
+    Returns (f, g), each [nx][n][n][n]."""
+    rng = np.random.default_rng(seed)
+    f = np.empty((nx, n, n, n))
+    g = np.empty((nx, n, n, n))
+    for c in range(nx):
+        x = (c + 0.5) / nx
+        th = theta_l + (theta_r - theta_l) * x
+        rho = 1.0 + amp * rng.uniform(-1.0, 1.0)
+        u = amp * rng.uniform(-1.0, 1.0, size=3)
+        M = maxwellian(n, L, rho, u, th)
+        f[c] = M * (1.0 + poly_eval(n, L, poly_coeffs(rng, std=0.2 * amp), u, math.sqrt(th)))
+        g[c] = M * poly_eval(n, L, poly_coeffs(rng), u, math.sqrt(th))
+    return f, g

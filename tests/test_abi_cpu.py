@@ -70,6 +70,11 @@ def test_null_handles_rejected():
     assert lib.lincoll_get_info(nullp, lc.INFO["hip_error"], ctypes.byref(v)) == lc.OK   # thread's last HIP error
     assert lib.lincoll_set_option(nullp, 0, 1) == lc.EINVAL
     assert lib.lincoll_autotune(nullp, nullp, nullp, 1, 3) == lc.EINVAL
+    sp = lc.steady_params(4)
+    rep = lc.SteadyReport()
+    assert lib.lincoll_steady_residual(nullp, ctypes.byref(sp), nullp, nullp, None) == lc.EINVAL
+    assert lib.lincoll_steady_newton_apply(nullp, ctypes.byref(sp), nullp, nullp, nullp) == lc.EINVAL
+    assert lib.lincoll_steady_solve(nullp, ctypes.byref(sp), nullp, ctypes.byref(rep)) == lc.EINVAL
     lib.lincoll_destroy(nullp)
 
 
@@ -101,3 +106,12 @@ def test_plan_tables_rejects_small_buffer():
     out = (ctypes.c_double * 2)()
     assert lib.lincoll_plan_tables(ctypes.byref(p), 0, out, 2) == lc.EINVAL
     assert lib.lincoll_plan_tables(ctypes.byref(p), 99, None, 0) == lc.EINVAL
+
+
+def test_steady_defaults():
+    sp = lc.steady_params(256)
+    assert (sp.nx, sp.x_l, sp.x_r, sp.kn, sp.mass, sp.theta_l, sp.theta_r) == (256, -0.5, 0.5, 0.1, 1.0, 1.0, 1.5)
+    assert (sp.tol, sp.inner_rtol, sp.inner_atol) == (1e-5, 1e-3, 1e-7)
+    assert (sp.restart, sp.init) == (30, 1) and list(sp.u_l) == [0.0, 0.0, 0.0]
+    sp = lc.steady_params(3, u_r=(0.0, 0.4, 0.0), kn=1.0)
+    assert list(sp.u_r) == [0.0, 0.4, 0.0] and sp.kn == 1.0

@@ -1,0 +1,175 @@
+"""Pins of the oracle's steady 1-D problem (Sec. 5, Appendix B).
+
+Each check compares the oracle with something it does not compute itself:
+1. The upwind stencil on a field linear in x gives v1 times the slope in every
+   interior cell, whatever the side it looks to (sign, index and dx).
+2. The wall ghosts carry exactly zero discrete mass flux, and they converge to
+   the printed continuum-constant ghosts at the Euler-Maclaurin rate h_v^2 of
+   the half-range velocity sums (the reading of the wall densities).
+3. The transport term conserves mass and commutes with the reflection
+   x -> -x, v1 -> -v1 that swaps the walls (catches a swapped wall or a
+   density read from the wrong cell), and a wall Maxwellian is its steady
+   state.
+4. The modified Newton operator is the Frechet derivative of the residual at
+   a cellwise Maxwellian state (where the local Maxwellian linearization is
+   exact), up to the gap between the binary and fast discretizations; its
+   collision part keeps the five moments of each cell at zero.
+5. The solve keeps the discrete mass, drives the residual below the tolerance
+   with a monotone history, returns the global Maxwellian for equal walls,
+   and for a hot right wall gives a temperature rising and a density falling
+   towards it at nearly constant pressure."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fast_direct, projection, quadrature, steady
+from paper_2503_09580_amd import workloads as wl
+
+SPH = quadrature.hemisphere_product_rule(8, 16)
+
+
+def _problem(n, L, nx, theta_l=1.0, theta_r=1.5, kn=0.1, omega=0.74, **kw):
+    return steady.Problem(n, L, omega, nx, kn, theta_l, theta_r, sphere=SPH, **kw)
+
+
+def test_stencil_on_a_linear_field():
+    P = _problem(8, 4.0, 5)
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=(8, 8, 8))
+    b = rng.normal(size=(8, 8, 8))
+    f = np.stack([a + b * x for x in P.xc])
+    T = P.transport(f)
+    want = P.V[0] * b
+    for c in range(1, 4):
+        assert np.max(np.abs(T[c] - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_wall_ghosts_zero_flux():
+    P = _problem(8, 4.0, 3, theta_l=0.8, theta_r=1.7, u_l=(0, 0.2, 0), u_r=(0, -0.1, 0.3))
+    rng = np.random.default_rng(2)
+    f = rng.uniform(0.5, 1.5, size=(3, 8, 8, 8))
+    gl, gr = P.ghosts(f)
+    left = np.sum(P.vp * gl + P.vm * f[0])
+    right = np.sum(P.vp * f[-1] + P.vm * gr)
+    scale = np.sum(np.abs(P.V[0] * f[0]))
+    assert abs(left) <= 1e-14 * scale and abs(right) <= 1e-14 * scale
+
+
+def _printed_ghost(P, f0, theta):
+    """The left ghost with the printed continuum constants (Appendix B)."""
+    rho = -math.sqrt(2 * math.pi / theta) * P.hv ** 3 * np.sum(P.vm * f0)
+    d2 = sum(P.V[d] ** 2 for d in range(3))
+    return rho * (2 * math.pi * theta) ** -1.5 * np.exp(-d2 / (2 * theta))
+
+
+def test_wall_ghosts_tend_to_the_printed_constants():
+    gaps = []
+    for n in (16, 32, 64):
+        P = _problem(n, 8.0, 1, theta_l=1.0)
+        f0 = wl.maxwellian(n, 8.0, 1.0, (0.0, 0.0, 0.0), 1.3)
+        ours, _ = P.ghosts(f0[None])
+        printed = _printed_ghost(P, f0, 1.0)
+        gaps.append(np.max(np.abs(ours - printed)) / np.max(np.abs(printed)))
+    r1, r2 = gaps[0] / gaps[1], gaps[1] / gaps[2]
+    assert gaps[-1] < 1e-2, gaps
+    assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, (gaps, r1, r2)
+
+
+def test_transport_conserves_mass():
+    P = _problem(8, 4.0, 4)
+    f = np.random.default_rng(3).uniform(0.0, 1.0, size=(4, 8, 8, 8))
+    T = P.transport(f)
+    assert abs(np.sum(T)) <= 1e-13 * np.sum(np.abs(T))
+
+
+def test_transport_reflection_swaps_the_walls():
+    n, L, nx = 8, 10.0, 4
+    P = _problem(n, L, nx, theta_l=1.0, theta_r=1.5)
+    Q = _problem(n, L, nx, theta_l=1.5, theta_r=1.0)
+    f = np.random.default_rng(4).uniform(0.0, 1.0, size=(nx, n, n, n))
+    f[:, 0] = 0.0                       # v1 = -L has no mirror node on the grid
+
+    def reflect(x):
+        y = np.zeros_like(x)
+        y[:, 1:] = x[::-1, :0:-1]       # cell c -> nx-1-c, i1 -> n-i1
+        return y
+
+    a = Q.transport(reflect(f))[:, 1:]
+    b = reflect(P.transport(f))[:, 1:]
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_wall_maxwellian_is_transport_steady():
+    n, L, nx, th = 8, 10.0, 3, 1.2
+    P = _problem(n, L, nx, theta_l=th, theta_r=th)
+    f = np.stack([wl.maxwellian(n, L, 1.0, (0.0, 0.0, 0.0), th)] * nx)
+    T = P.transport(f)
+    assert np.max(np.abs(T)) <= 1e-12 * np.max(np.abs(P.V[0] * f)) / P.dx
+
+
+def test_binary_term_has_zero_mass_per_cell():
+    P = _problem(8, 4.0, 2)
+    f, _ = wl.slab_state(8, 4.0, 2)
+    q = P.q(f)
+    for c in range(2):
+        assert abs(np.sum(q[c])) <= 1e-13 * np.sum(np.abs(q[c]))
+
+
+def test_newton_operator_is_the_jacobian_at_maxwellian_states():
+    P = _problem(16, 5.0, 3, kn=1.0, omega=1.0)
+    par = np.array([[1.0, 0.05, 0.0, 0.0, 1.1], [0.9, -0.03, 0.02, 0.0, 1.25], [0.85, 0.0, 0.0, 0.04, 1.4]])
+    f = np.stack([fast_direct.maxwellian_fields(P.plan, p[0], p[1:4], p[4])[0] for p in par])
+    rng = np.random.default_rng(5)
+    g = f * (0.1 + 0.3 * rng.normal(size=f.shape))
+    eps = 1e-4
+    fd = (P.residual(f + eps * g) - P.residual(f - eps * g)) / (2 * eps)
+    mv = P.newton_operator(P.moments(f))(g.reshape(-1)).reshape(f.shape)
+    Tg = P.transport(g)
+    coll_fd, coll_mv = fd - Tg, mv - Tg
+    # binary vs fast discretization at n = 16, L = 5: a few per cent; a sign
+    # or factor error in either term is O(1)
+    assert np.linalg.norm(coll_fd - coll_mv) <= 0.1 * np.linalg.norm(coll_fd)
+    assert np.linalg.norm(fd - mv) <= 0.02 * np.linalg.norm(mv)
+
+
+def test_newton_operator_collision_part_keeps_moments():
+    P = _problem(8, 4.0, 2)
+    f, g = wl.slab_state(8, 4.0, 2)
+    params = P.moments(f)
+    y = P.lcons(g, params)
+    phis = projection.invariants(8, 4.0)
+    for c in range(2):
+        m = projection.moments(y[c], phis)
+        assert np.max(np.abs(m)) <= 1e-12 * np.sum(np.abs(y[c])) * 4.0 ** 2
+    A = P.newton_operator(params)(g.reshape(-1))
+    assert abs(np.sum(A)) <= 1e-12 * np.sum(np.abs(A))
+
+
+def test_solve_equal_walls_gives_the_global_maxwellian():
+    n, L, nx, th = 16, 5.0, 2, 1.0
+    P = _problem(n, L, nx, theta_l=th, theta_r=th, kn=1.0)
+    f, hist = P.solve(tol=1e-9, max_newton=10)
+    assert hist[-1] < 1e-9 and len(hist) <= 6, hist
+    assert abs(P.total_mass(f) - 1.0) <= 1e-13
+    mom = P.moments(f)
+    # the discrete Q(M, M) is not exactly zero at n = 16, L = 5: the steady
+    # state sits within that discretization level of the wall Maxwellian
+    assert np.max(np.abs(mom[:, 0] - 1.0)) < 2e-3
+    assert np.max(np.abs(mom[:, 1:4])) < 2e-3
+    assert np.max(np.abs(mom[:, 4] - th)) < 5e-3
+
+
+@pytest.mark.slow
+def test_solve_heat_transfer_profile():
+    P = _problem(16, 5.0, 3, theta_l=1.0, theta_r=1.5, kn=1.0)
+    f, hist = P.solve(tol=1e-8, max_newton=15)
+    assert hist[-1] < 1e-8
+    assert all(b < a for a, b in zip(hist, hist[1:])), hist
+    assert abs(P.total_mass(f) - 1.0) <= 1e-13
+    mom = P.moments(f)
+    rho, th = mom[:, 0], mom[:, 4]
+    assert np.all(np.diff(th) > 0) and np.all(np.diff(rho) < 0), mom
+    p = rho * th
+    assert np.max(np.abs(p - p.mean())) < 0.02 * p.mean()
+    assert 1.0 < th[0] and th[-1] < 1.5
