@@ -246,6 +246,76 @@ def bench_rk4(a, torch, lincoll, dev):
     print(json.dumps(rec))
 
 
+def bench_steady(a, torch, lincoll, dev):
+    """Newton solve wall-time of the steady 1-D heat-transfer problem (Sec. 5.2,
+    Fourier flow; scheme of Appendix B): 256 cells on [-0.5, 0.5], walls at
+    temperature 1 and 1.5, Kn = 0.1, mass 1, n = 32, box [-8,8)^3,
+    VHS omega = 0.74; residuals by quadcoll_apply (FP64), Newton operator with
+    applies in --dtype (default f32) inside sweep-preconditioned flexible
+    GMRES; Newton tolerance 1e-5, inner 1e-3 relative / 1e-7 absolute.  A step
+    is one whole solve from the initial guess of eq. (initial)."""
+    from paper_2503_09580_amd import workloads as wl
+    c = wl.CONFIGS["C4"]
+    n, L, om, nx = c["n"], c["L"], c["omega"], c["nx"]
+    dtype = a.dtype or "f32"
+    precond = a.precond
+    sp = lincoll.steady_params(nx, kn=c["kn"], theta_l=c["theta_l"], theta_r=c["theta_r"], mass=c["mass"],
+                               precond=precond)
+    stream = torch.cuda.Stream(device=dev)
+    steps = max(1, min(a.steps, 5))
+    with torch.cuda.stream(stream):
+        plan = lincoll.Plan(n, L, om, dtype)
+        if a.graph is not None:
+            plan.set_option("graph", a.graph)
+        f = torch.empty((nx, n, n, n), dtype=torch.float64, device=dev)
+        for _ in range(max(1, a.warmup)):
+            plan.steady_solve(sp, f)
+        stream.synchronize()
+        reps = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            reps.append(plan.steady_solve(sp, f))
+        stream.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        J = int(plan.info("J"))
+    rep = reps[-1]
+    evals = rep["newton_iters"] + 1
+    M = 64
+    q_ms = sum(r["ms_residual"] for r in reps) / steps
+    ach = quadcoll_flops_per_cell(n, J, M) * nx * evals / (q_ms / 1e3) / 1e12
+    rec = {"metric": "Newton solve wall-time (steady 1-D heat transfer, Table 8 case theta_R=1.5, Kn=0.1)",
+           "value": wall, "unit": "s", "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": wall * 1e3,
+           "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (closed-form initial guess)",
+           "config": {"workload": f"{nx} cells x n={n}^3 velocities, box [-{L:g},{L:g})^3, omega={om}, Kn={c['kn']}, "
+                                  f"walls theta 1/1.5, tol 1e-5", "precond": precond,
+                      "newton_iters": rep["newton_iters"], "inner_iters": rep["inner_iters"],
+                      "residual": rep["residual"], "res_history": rep["res_history"],
+                      "ms_residual": rep["ms_residual"], "ms_inner": rep["ms_inner"], "ms_total": rep["ms_total"],
+                      "converged": rep["converged"]},
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_VALU_TFLOPS, "traffic": None,
+                        "kernel": "quadcoll_apply inside the residuals (the dominant part of a solve)"}}
+    if not a.no_cpu:
+        from oracle import alg1, binary, fast_direct, quadrature
+        fh = f[:1].cpu().numpy()
+        oplan = fast_direct.make_plan(n, L, om)
+        sph = quadrature.hemisphere_product_rule(8, 16)
+        t0 = time.perf_counter()
+        binary.q_binary(oplan, sph, fh[0], fh[0], fix=1)
+        tq = time.perf_counter() - t0
+        p = np.array([[1.0, 0.0, 0.0, 0.0, 1.2]])
+        t0 = time.perf_counter()
+        alg1.apply_batch(oplan, fh, p)
+        tl = time.perf_counter() - t0
+        est = evals * nx * tq + rep["inner_iters"] * nx * tl
+        rec["cpu_baseline"] = {"value": est, "unit": "s", "cores": alg1.threads_used(), "kind": "oracle",
+                               "sample": f"one cell's binary Q ({tq:.2f} s) and one linearized apply ({tl:.2f} s) "
+                                         f"by the oracle, scaled by the solve's {evals} x {nx} residual cells and "
+                                         f"{rep['inner_iters']} x {nx} operator cells"}
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,8 +324,10 @@ def main():
     ap.add_argument("--dtype", default=None, help="f32 (default for apply), f64 (default for rk4), bf16x3")
     ap.add_argument("--path", default="auto")
     ap.add_argument("--config", default="C3")
-    ap.add_argument("--op", default="apply", choices=["apply", "quadcoll", "rk4"],
-                    help="apply: batched L[h] (default); quadcoll: binary Q(f,f); rk4: Table 5 time stepping")
+    ap.add_argument("--precond", default="sweep", choices=["sweep", "none"], help="steady: inner preconditioner")
+    ap.add_argument("--op", default="apply", choices=["apply", "quadcoll", "rk4", "steady"],
+                    help="apply: batched L[h] (default); quadcoll: binary Q(f,f); rk4: Table 5 time stepping; "
+                         "steady: Newton solve of the 256-cell heat-transfer problem")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -280,6 +352,8 @@ def main():
         return bench_quadcoll(a, torch, lincoll, dev)
     if a.op == "rk4":
         return bench_rk4(a, torch, lincoll, dev)
+    if a.op == "steady":
+        return bench_steady(a, torch, lincoll, dev)
     h, params, c = workload(a.config)
     n, L, om, B = c["n"], c["L"], c["omega"], h.shape[0]
     td = torch.float64 if a.dtype == "f64" else torch.float32
