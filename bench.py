@@ -263,11 +263,44 @@ def bench_steady(a, torch, lincoll, dev):
                                precond=precond)
     stream = torch.cuda.Stream(device=dev)
     steps = max(1, min(a.steps, 5))
+    extra = {}
     with torch.cuda.stream(stream):
         plan = lincoll.Plan(n, L, om, dtype)
         if a.graph is not None:
             plan.set_option("graph", a.graph)
         f = torch.empty((nx, n, n, n), dtype=torch.float64, device=dev)
+        if precond == "learned":
+            # training data from plain solves at wall temperatures spread over [1.1, 2.0],
+            # away from the timed case (1.5)
+            t0 = time.perf_counter()
+            thetas = np.array([1.1, 1.3, 1.7, 2.0])
+            rows = len(thetas) * 8 * nx
+            RX = torch.zeros((rows, 26), dtype=torch.float32, device=dev)
+            RT = torch.zeros((rows, 5), dtype=torch.float32, device=dev)
+            used = 0
+            for th in thetas:
+                rsp = lincoll.steady_params(nx, kn=c["kn"], theta_l=c["theta_l"], theta_r=float(th), mass=c["mass"],
+                                            inner_rtol=1e-8, inner_atol=0.0, rec_X=RX[used:], rec_T=RT[used:])
+                used += plan.steady_solve(rsp, f)["rec_rows"]
+            net = lincoll.MLP(seed=7)
+            loss = net.train(RX[:used].contiguous(), RT[:used].contiguous(), steps=3000, lr=2e-3)
+            stream.synchronize()
+            sp = lincoll.steady_params(nx, kn=c["kn"], theta_l=c["theta_l"], theta_r=c["theta_r"], mass=c["mass"],
+                                       precond="learned", mlp=net)
+            extra = {"train_rows": used, "train_loss": loss, "train_thetas": [round(float(t), 4) for t in thetas],
+                     "train_s": time.perf_counter() - t0}
+            # the plain FP64 solver (sweep preconditioner) on the same problem, timed alike
+            plan64 = lincoll.Plan(n, L, om, "f64")
+            sp64 = lincoll.steady_params(nx, kn=c["kn"], theta_l=c["theta_l"], theta_r=c["theta_r"], mass=c["mass"])
+            plan64.steady_solve(sp64, f)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rep64 = plan64.steady_solve(sp64, f)
+            stream.synchronize()
+            extra["plain_f64_s"] = (time.perf_counter() - t0) / steps
+            extra["plain_f64_inner_iters"] = rep64["inner_iters"]
+            extra["plain_f64_residual"] = rep64["residual"]
         for _ in range(max(1, a.warmup)):
             plan.steady_solve(sp, f)
         stream.synchronize()
@@ -292,7 +325,7 @@ def bench_steady(a, torch, lincoll, dev):
                       "newton_iters": rep["newton_iters"], "inner_iters": rep["inner_iters"],
                       "residual": rep["residual"], "res_history": rep["res_history"],
                       "ms_residual": rep["ms_residual"], "ms_inner": rep["ms_inner"], "ms_total": rep["ms_total"],
-                      "converged": rep["converged"]},
+                      "converged": rep["converged"], **extra},
            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                         "frac": ach / PEAK_VALU_TFLOPS, "traffic": None,
                         "kernel": "quadcoll_apply inside the residuals (the dominant part of a solve)"}}
@@ -324,7 +357,8 @@ def main():
     ap.add_argument("--dtype", default=None, help="f32 (default for apply), f64 (default for rk4), bf16x3")
     ap.add_argument("--path", default="auto")
     ap.add_argument("--config", default="C3")
-    ap.add_argument("--precond", default="sweep", choices=["sweep", "none"], help="steady: inner preconditioner")
+    ap.add_argument("--precond", default="sweep", choices=["sweep", "none", "learned"],
+                    help="steady: inner preconditioner (learned: trains the network first, untimed)")
     ap.add_argument("--op", default="apply", choices=["apply", "quadcoll", "rk4", "steady"],
                     help="apply: batched L[h] (default); quadcoll: binary Q(f,f); rk4: Table 5 time stepping; "
                          "steady: Newton solve of the 256-cell heat-transfer problem")

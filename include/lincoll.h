@@ -205,6 +205,10 @@ int lincoll_rk4(lincoll_plan_t plan, void* f, int batch, double dt, int steps);
  * the apply dtype of the Newton operator; these calls replace its Maxwellians
  * with the local ones of f and use its stream.  Work memory is allocated per
  * call and freed before return; every call synchronises the plan's stream. */
+/* Learned correction of the inner solves: a small FP32 network (see the
+ * lincoll_mlp_* functions below). */
+typedef struct lincoll_mlp_s* lincoll_mlp_t;
+
 typedef struct {
   int nx;                   /* cells, >= 1 (and <= the plan's max_batch if set) */
   double x_l, x_r;          /* slab ends, x_l < x_r (default -0.5, 0.5) */
@@ -220,13 +224,22 @@ typedef struct {
   int restart;              /* GMRES cycle length, 1..64 (default 30) */
   int init;                 /* 1: start from eq. (initial); 0: from f as passed (default 1) */
   int precond;              /* right preconditioner of the inner GMRES, lincoll_precond_t (default SWEEP) */
+  lincoll_mlp_t mlp;        /* network of LINCOLL_PRECOND_LEARNED (else unused; default NULL) */
+  float* rec_X;             /* optional device [rec_cap][LINCOLL_MLP_IN]: training features, one row per cell */
+  float* rec_T;             /* ... device [rec_cap][LINCOLL_MLP_OUT]: training targets (both NULL: no recording) */
+  int rec_cap;              /* rows available in rec_X / rec_T */
 } lincoll_steady_params_t;
 
 typedef enum {
   LINCOLL_PRECOND_NONE = 0,  /* plain GMRES */
-  LINCOLL_PRECOND_SWEEP = 1  /* one transport sweep z = (T + diag(nu)/Kn)^-1 y: the upwind recurrence of the
+  LINCOLL_PRECOND_SWEEP = 1, /* one transport sweep z = (T + diag(nu)/Kn)^-1 y: the upwind recurrence of the
                                 source iteration (Sec. 5.1) with nu(v) the loss collision frequency of each
-                                cell's L; left wall ghost from z, right ghost empty (a fixed linear map) */
+                                cell's L; left wall ghost from z, right ghost empty; then the total of z is
+                                removed along the current iterate, so corrections keep zero mass */
+  LINCOLL_PRECOND_LEARNED = 2 /* SWEEP inside GMRES, and each inner solve starts from a z + alpha Delta with
+                                 z = sweep(r), Delta the correction of mlp(features(z)) and (a, alpha)
+                                 minimising the start's residual (two extra operator applications, counted
+                                 as inner iterations): a nonlinear preconditioner applied to the residual */
 } lincoll_precond_t;
 
 typedef struct {
@@ -238,6 +251,7 @@ typedef struct {
   double res_history[65];   /* residual norm before step k, k = 0..min(newton_iters, 64) */
   int inner_history[64];    /* inner iterations of step k */
   double ms_total, ms_residual, ms_inner;   /* wall clock: whole solve, residuals, inner solves */
+  int rec_rows;             /* training rows written to rec_X / rec_T */
 } lincoll_steady_report_t;
 
 /* Fills *sp with the defaults above for nx cells. */
@@ -264,6 +278,56 @@ int lincoll_steady_newton_apply(lincoll_plan_t plan, const lincoll_steady_params
  * LINCOLL_OK also when not converged (see rep->converged). */
 int lincoll_steady_solve(lincoll_plan_t plan, const lincoll_steady_params_t* sp, double* f,
                          lincoll_steady_report_t* rep);
+
+/* With rec_X / rec_T set, every Newton step appends nx training rows after
+ * its inner solve: features of z = sweep(r) and targets m(g - z)/s, g the
+ * step's correction (solve the inner systems tightly for clean targets).
+ * Rows beyond rec_cap are not written. */
+
+/* ---- Learned correction of the inner solves ----------------------------
+ * Per cell c with local Maxwellian (rho, u, theta) the Hermite functions
+ *   psi_0 = 1, psi_d = (v_d - u_d)/sqrt(theta), psi_4 = (|v-u|^2/theta - 3)/sqrt 6
+ * (orthonormal under M/rho) give moments m_a(c) = h^3 sum z psi_a / rho.
+ * Features, 26 per cell, with s = sqrt(mean m^2) (1 if 0), ms = m/s and
+ * x_c = (c+1/2)/nx: ms (5), (sum_{c'<=c} ms - ms/2)/nx (5),
+ * (sum_{c'>=c} ms - ms/2)/nx (5), sum_{c'<=c} ms x_c'/nx (5),
+ * sum_{c'>=c} ms x_c'/nx (5), x_c.  The network Y = tanh(X W1 + b1) W2 + b2
+ * (26 -> 128 -> 5, FP32) predicts m(g - z)/s, and the correction is
+ * Delta_c = sum_a s Y_a(c) M_c psi_a.  Weights: one packed float array
+ * W1 [26][128], b1 [128], W2 [128][5], b2 [5] (row-major). */
+#define LINCOLL_MLP_IN 26
+#define LINCOLL_MLP_HIDDEN 128
+#define LINCOLL_MLP_OUT 5
+#define LINCOLL_MLP_WEIGHTS (26 * 128 + 128 + 128 * 5 + 5)
+
+/* Creates a network on the current device with Glorot-uniform weights from
+ * a seeded generator (splitmix64) and zero biases.  Synchronous. */
+int lincoll_mlp_create(unsigned long long seed, lincoll_mlp_t* out);
+void lincoll_mlp_destroy(lincoll_mlp_t mlp);
+int lincoll_mlp_set_stream(lincoll_mlp_t mlp, void* hip_stream);
+/* Copies the packed weights to (write = 0) or from (write = 1) the host array
+ * w of count = LINCOLL_MLP_WEIGHTS floats; writing resets the optimiser.
+ * Synchronous. */
+int lincoll_mlp_weights(lincoll_mlp_t mlp, float* w, long long count, int write);
+/* Y [rows][5] = network(X [rows][26]); device float arrays.  Asynchronous. */
+int lincoll_mlp_forward(lincoll_mlp_t mlp, const float* X, float* Y, int rows);
+/* loss = mean((Y - T)^2) over all rows x 5 entries (host, may be NULL) and
+ * its gradient with respect to the packed weights into grad (device
+ * [LINCOLL_MLP_WEIGHTS], may be NULL).  Synchronous. */
+int lincoll_mlp_loss_grad(lincoll_mlp_t mlp, const float* X, const float* T, int rows, float* grad, double* loss);
+/* steps full-batch Adam steps (beta 0.9, 0.999, eps 1e-8, step size lr) on
+ * the loss above; *loss (may be NULL) = the loss before the last step.
+ * Synchronous. */
+int lincoll_mlp_train(lincoll_mlp_t mlp, const float* X, const float* T, int rows, int steps, double lr,
+                      double* loss);
+/* X [nx][26] (device float) and *s (host) = features of the field z about
+ * the local Maxwellians of f (both device double [nx][n][n][n]).  Synchronous. */
+int lincoll_learned_features(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                             const double* z, float* X, double* s);
+/* out = Delta: sum_a s Y_a(c) M_c psi_a about the local Maxwellians of f
+ * (Y device float [nx][5], out device double).  Synchronous. */
+int lincoll_learned_correction(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                               const float* Y, double s, double* out);
 
 /* Releases everything the plan owns (waits for its stream first). */
 void lincoll_destroy(lincoll_plan_t plan);

@@ -26,6 +26,12 @@ projection   Orthogonal projection onto the complement of the collision
              invariants in the M^{-1}-weighted inner product.
 timestep     Classical RK4 for the spatially homogeneous linearized
              equation df/dt = L[f] (Sec. 4.2).
+steady       The steady 1-D problem with diffuse walls (Sec. 5, Appendix B):
+             upwind transport, residual with the binary operator, modified
+             Newton operator, Newton iteration with tight GMRES solves.
+learned      The fixed maps of the learned inner-solve correction (Hermite
+             moments, features, correction field) and its tanh network with
+             MSE gradient and Adam step.
 
 Readings of the paper that the oracle takes where the text is silent or
 inconsistent (each also implemented identically on the GPU side):
@@ -44,4 +50,12 @@ inconsistent (each also implemented identically on the GPU side):
       halving of the Nyquist entries).
   R9  cutoff: r = h/M kept where M/rho >= eps, r = 0 otherwise; the
       loss term uses the uncut h.
+  R17 diffuse walls: the wall density makes the discrete mass flux through
+      the wall exactly zero (ghost rho_W E_W, E_W = exp(-|v-u_W|^2/(2
+      theta_W)), rho_W from the outgoing half-range sum); the printed
+      constants are its continuum limit.  The right wall reads the last
+      cell (the printed formula names the first, a slip).
+  R18 total mass: Q with Q^_0 = 0 in the residual, P L P in the Newton
+      operator, and the initial guess and each iterate rescaled to the
+      discrete mass C.
 """

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["abi.cpp", "host_tables.cpp", "staged.hip", "setup.hip", "fused.hip", "mfma_dft.hip", "timestep.hip", "quadcoll.hip", "steady.hip",
-           "solver.cpp"]
+           "solver.cpp", "learn.hip", "mlp.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
 # packed FP32 instructions are kept out of every device code object

@@ -15,7 +15,8 @@
 // operator.  The phase exp(i a) factorises over the axes, so for one g-node
 // and one polar cosine mu_i the transform along z, G_+- = iDFT_z[F
 // exp(+-i alpha mu_i p_z)], serves all azimuths; per azimuth only the
-// in-plane transforms remain.
+// in-plane transforms remain, and one kernel runs the whole azimuth loop of a
+// plane pair with S accumulated in registers (k_qc_azim).
 //
 // Layouts: f and the result [cell][x][y][z]; every complex work volume is
 // [cell][plane][a][b] with the plane index the z (or k_z) axis.
@@ -111,13 +112,9 @@ __global__ void __launch_bounds__(128) k_qc_col(const double2* __restrict__ in, 
 // MODE 1: forward of S_j, plain (alias of 0, kept for clarity of the launches).
 // MODE 2: inverse after multiplying by the loss table Omega_u(|k|^2) (plane = kz).
 // MODE 3: inverse, plain.
-// MODE 4: inverse after multiplying by exp(sign i alpha (sx p1 + sy p2)); stores c.
-// MODE 5: as 4 with the conjugate phase, then S (+)= w c d (c read from cin).
 template <int NN, int MODE>
 __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in, double2* __restrict__ out,
-                                                  const double2* __restrict__ cin, const double* __restrict__ tab,
-                                                  double alpha, double sx, double sy, int sign, double w,
-                                                  int first, int nplanes) {
+                                                  const double* __restrict__ tab, int nplanes) {
   constexpr int NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
   constexpr bool INV = MODE >= 2;
   __shared__ double2 lds[PPB * NN * LD];
@@ -142,17 +139,6 @@ __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in,
         vi[k1] *= m;
       });
     }
-    if constexpr (MODE == 4 || MODE == 5) {
-      const double s = MODE == 4 ? sign : -sign;
-      const double pb = alpha * sy * sgn_idx<NN>(a);
-      static_for<0, NN>([&](auto k1) {
-        double sn, cs;
-        sincos(s * (alpha * sx * sgn_idx<NN>(k1) + pb), &sn, &cs);
-        const double r = vr[k1] * cs - vi[k1] * sn, i = vr[k1] * sn + vi[k1] * cs;
-        vr[k1] = r;
-        vi[k1] = i;
-      });
-    }
   } else {
     static_for<0, NN>([&](auto k1) { vr[k1] = 0.0; vi[k1] = 0.0; });
   }
@@ -175,18 +161,87 @@ __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in,
   });
   if (!active) return;
   double2* dst = out + (size_t)pid * NP + a;
-  if constexpr (MODE == 5) {
-    const double2* c = cin + (size_t)pid * NP + a;
-    static_for<0, NN>([&](auto k1) {
-      const double2 cv = c[(size_t)k1 * NN];
-      const double pr = cv.x * vr[k1] - cv.y * vi[k1], pi = cv.x * vi[k1] + cv.y * vr[k1];
-      double2 o{0.0, 0.0};
-      if (!first) o = dst[(size_t)k1 * NN];
-      dst[(size_t)k1 * NN] = double2{o.x + w * pr, o.y + w * pi};
-    });
-  } else {
-    static_for<0, NN>([&](auto k1) { dst[(size_t)k1 * NN] = double2{vr[k1], vi[k1]}; });
+  static_for<0, NN>([&](auto k1) { dst[(size_t)k1 * NN] = double2{vr[k1], vi[k1]}; });
+}
+
+// All azimuths of one (g-node, polar cosine) for pairs of planes (cell, z):
+//   S (+)= sum_m w Re(c_m d_m),  c_m, d_m = iDFT_xy[G+- exp(+-i alpha (sx_m p1 + sy_m p2))]
+// with sx_m, sy_m = sin(polar) (cos, sin)(2 pi m / nazim) and w the polar weight
+// over nazim.  G+- stay in L2 across the azimuth loop and S is written once,
+// so the HBM traffic of the loop is that of G+- and S alone.  Only Re S is
+// kept: S enters Q through Re iDFT[s_j DFT S] with s_j real and even in the
+// signed frequencies, which maps i Im S to a purely imaginary field.
+// Thread a of a plane owns column a for the first transform and row a for the
+// second; c is parked in LDS (own row) while d is transformed.
+template <int NN>
+__global__ void __launch_bounds__(64) k_qc_azim(const double2* __restrict__ Gp, const double2* __restrict__ Gm,
+                                                 double2* __restrict__ S, double alpha, double st, double w,
+                                                 int nazim, int first, int nplanes) {
+  constexpr int NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
+  __shared__ double2 Cb[PPB * NP];        // c, row x1 = a of thread a
+  __shared__ double2 Ub[PPB * NN * LD];   // transposes
+  __shared__ double2 E1[NN];              // exp(i alpha sx p1) for the current azimuth
+  const int lp = threadIdx.x / NN, a = threadIdx.x % NN;
+  const long pid = (long)blockIdx.x * PPB + lp;
+  const bool active = pid < nplanes;
+  double2* cb = Cb + lp * NP;
+  double2* ub = Ub + lp * NN * LD;
+  const double2* gp = Gp + (active ? pid : 0) * NP + a;
+  const double2* gm = Gm + (active ? pid : 0) * NP + a;
+  double sacc[NN];
+  static_for<0, NN>([&](auto x) { sacc[x] = 0.0; });
+  double vr[NN], vi[NN];
+  for (int m = 0; m < nazim; ++m) {
+    const double ph = 2.0 * M_PI * m / nazim;
+    const double sx = st * cos(ph), sy = st * sin(ph);
+    if (threadIdx.x < NN) {
+      double sn, cs;
+      sincos(alpha * sx * sgn_idx<NN>(threadIdx.x), &sn, &cs);
+      E1[threadIdx.x] = double2{cs, sn};
+    }
+    double s2, c2;
+    sincos(alpha * sy * sgn_idx<NN>(a), &s2, &c2);
+    __syncthreads();
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const double2* src = pass == 0 ? gp : gm;
+      const double sg = pass == 0 ? 1.0 : -1.0;   // c: exp(+i a.p), d: exp(-i a.p)
+      static_for<0, NN>([&](auto k1) {
+        const double2 v = src[(size_t)k1 * NN];
+        const double2 e = E1[k1];
+        const double er = e.x * c2 - e.y * s2, ei = sg * (e.x * s2 + e.y * c2);
+        vr[k1] = v.x * er - v.y * ei;
+        vi[k1] = v.x * ei + v.y * er;
+      });
+      fft<NN, true>(vr, vi);
+      static_for<0, NN>([&](auto k1) { ub[k1 * LD + a] = double2{vr[k1], vi[k1]}; });
+      __syncthreads();
+      static_for<0, NN>([&](auto k2) {
+        const double2 v = ub[a * LD + k2];
+        vr[k2] = v.x;
+        vi[k2] = v.y;
+      });
+      fft<NN, true>(vr, vi);
+      if (pass == 0) {
+        static_for<0, NN>([&](auto x2) { cb[a * NN + x2] = double2{vr[x2], vi[x2]}; });
+      } else {
+        static_for<0, NN>([&](auto x2) {
+          const double2 c = cb[a * NN + x2];
+          sacc[x2] += w * (c.x * vr[x2] - c.y * vi[x2]);
+        });
+      }
+      __syncthreads();   // ub (and E1 after the second pass) are reused
+    }
   }
+  // back to columns for coalesced stores: thread a writes S[x1][x2 = a]
+  static_for<0, NN>([&](auto x2) { ub[a * LD + x2] = double2{sacc[x2], 0.0}; });
+  __syncthreads();
+  if (!active) return;
+  double2* dst = S + pid * NP + a;
+  static_for<0, NN>([&](auto x1) {
+    const double v = ub[x1 * LD + a].x;
+    dst[(size_t)x1 * NN] = first ? double2{v, 0.0} : double2{dst[(size_t)x1 * NN].x + v, 0.0};
+  });
 }
 
 template <int NN>
@@ -198,9 +253,9 @@ hipError_t quadcoll_n(const QuadCtx& c) {
   hipStream_t s = c.stream;
   // F = DFT3[f]: along z, then in-plane
   k_qc_col<NN, 0><<<gc, 128, 0, s>>>(nullptr, Fk, c.f, nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 0, B);
-  k_qc_plane<NN, 0><<<gp, 64, 0, s>>>(Fk, Fk, nullptr, nullptr, 0, 0, 0, 0, 0, 0, nplanes);
+  k_qc_plane<NN, 0><<<gp, 64, 0, s>>>(Fk, Fk, nullptr, nplanes);
   // loss: V = Re iDFT_u[Omega_u F] (into the output buffer's shadow V)
-  k_qc_plane<NN, 2><<<gp, 64, 0, s>>>(Fk, C, nullptr, c.Om64, 0, 0, 0, 0, 0, 0, nplanes);
+  k_qc_plane<NN, 2><<<gp, 64, 0, s>>>(Fk, C, c.Om64, nplanes);
   k_qc_col<NN, 3><<<gc, 128, 0, s>>>(C, nullptr, nullptr, c.V, nullptr, nullptr, 0, 0, 0, 0, 0, 0, B);
   for (int j = 0; j < c.J; ++j) {
     const double alpha = M_PI * c.g[j] / (2.0 * c.L);
@@ -208,19 +263,14 @@ hipError_t quadcoll_n(const QuadCtx& c) {
       const double mu = c.mu[i], st = c.st[i];
       k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gp, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, +1, 0, B);
       k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gm, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, -1, 0, B);
-      for (int m = 0; m < c.nazim; ++m) {
-        const double phi = 2.0 * M_PI * m / c.nazim;
-        const double sx = st * cos(phi), sy = st * sin(phi), w = c.wpolar[i] / c.nazim;
-        k_qc_plane<NN, 4><<<gp, 64, 0, s>>>(Gp, C, nullptr, nullptr, alpha, sx, sy, +1, 0, 0, nplanes);
-        k_qc_plane<NN, 5><<<gp, 64, 0, s>>>(Gm, S, C, nullptr, alpha, sx, sy, +1, w, i == 0 && m == 0, nplanes);
-      }
+      k_qc_azim<NN><<<gp, 64, 0, s>>>(Gp, Gm, S, alpha, st, c.wpolar[i] / c.nazim, c.nazim, i == 0, nplanes);
     }
     // Qk (+)= W_j s_j DFT3[S_j]
-    k_qc_plane<NN, 1><<<gp, 64, 0, s>>>(S, S, nullptr, nullptr, 0, 0, 0, 0, 0, 0, nplanes);
+    k_qc_plane<NN, 1><<<gp, 64, 0, s>>>(S, S, nullptr, nplanes);
     k_qc_col<NN, 2><<<gc, 128, 0, s>>>(S, Qk, nullptr, nullptr, nullptr, c.Ws, c.Q, j, 0, 0, 0, j == 0, B);
   }
   // Q = 16 pi^2 / n^3 Re iDFT_u[Qk] - f V
-  k_qc_plane<NN, 3><<<gp, 64, 0, s>>>(Qk, Qk, nullptr, nullptr, 0, 0, 0, 0, 0, 0, nplanes);
+  k_qc_plane<NN, 3><<<gp, 64, 0, s>>>(Qk, Qk, nullptr, nplanes);
   k_qc_col<NN, 4><<<gc, 128, 0, s>>>(Qk, nullptr, c.f, c.out, c.V, nullptr, 0, 0, 0, 0, 0, 0, B);
   return hipGetLastError();
 }

@@ -14,6 +14,7 @@
 
 #include "../../include/lincoll.h"
 #include "internal.h"
+#include "learn.h"
 #include "steady.h"
 
 using namespace lincoll;
@@ -50,7 +51,11 @@ int check_params(const lincoll_steady_params_t* sp) {
   if (sp->max_newton < 0 || sp->max_inner < 1 || sp->restart < 1 || sp->restart > GMRES_MAXK - 1)
     return LINCOLL_EINVAL;
   if (sp->init != 0 && sp->init != 1) return LINCOLL_EINVAL;
-  if (sp->precond != LINCOLL_PRECOND_NONE && sp->precond != LINCOLL_PRECOND_SWEEP) return LINCOLL_EINVAL;
+  if (sp->precond != LINCOLL_PRECOND_NONE && sp->precond != LINCOLL_PRECOND_SWEEP &&
+      sp->precond != LINCOLL_PRECOND_LEARNED)
+    return LINCOLL_EINVAL;
+  if (sp->precond == LINCOLL_PRECOND_LEARNED && !sp->mlp) return LINCOLL_EINVAL;
+  if ((sp->rec_X == nullptr) != (sp->rec_T == nullptr) || sp->rec_cap < 0) return LINCOLL_EINVAL;
   return LINCOLL_OK;
 }
 
@@ -69,12 +74,18 @@ struct Solver {
   double L = 0.0, hv = 0.0, h3 = 0.0, dx = 0.0, wnorm = 0.0;   // wnorm = sqrt(dx h_v^3)
   WallGeom wg{};
   int project_before = 0;
+  const double* f_cur = nullptr;   // iterate whose local Maxwellians are set
+  double f_sum = 0.0;              // its plain sum (mass / (dx h^3))
   bool project_set = false;
   long matvecs = 0;
   std::vector<void*> owned;
   // small buffers
   double *d_sums = nullptr, *d_ysums = nullptr, *d_params = nullptr, *d_wall = nullptr;
   double *d_partial = nullptr, *d_red = nullptr, *d_y = nullptr;
+  // learned correction: moments, scale, features, network output
+  double *d_m5 = nullptr, *d_scale = nullptr;
+  float *d_X = nullptr, *d_Y = nullptr;
+  int rec_rows = 0;
   // fields of N values
   double* d_q = nullptr;   // Q(f, f)
   void* d_in = nullptr;    // apply input (plan dtype)
@@ -145,6 +156,10 @@ struct Solver {
     STCK(alloc(&d_partial, nb * GMRES_MAXK * sizeof(double)));
     STCK(alloc(&d_red, (GMRES_MAXK + 1) * sizeof(double)));
     STCK(alloc(&d_y, GMRES_MAXK * sizeof(double)));
+    STCK(alloc(&d_m5, (size_t)nx * 5 * sizeof(double)));
+    STCK(alloc(&d_scale, sizeof(double)));
+    STCK(alloc(&d_X, (size_t)nx * MLP_IN * sizeof(float)));
+    STCK(alloc(&d_Y, (size_t)nx * MLP_OUT * sizeof(float)));
     return LINCOLL_OK;
   }
 
@@ -175,12 +190,21 @@ struct Solver {
     return LINCOLL_OK;
   }
 
-  // Maxwellians of the plan <- local Maxwellians of f (checked on the host)
-  int set_local(const double* f) {
+  // d_params <- local Maxwellian parameters of f
+  int local_params(const double* f) {
     HIPCK(st_cell_sums(f, nx, n, L, d_sums, s));
     HIPCK(st_params(d_sums, nx, n, L, d_params, s));
+    return LINCOLL_OK;
+  }
+
+  // Maxwellians of the plan <- local Maxwellians of f (checked on the host)
+  int set_local(const double* f) {
+    STCK(local_params(f));
     std::vector<double> hp((size_t)nx * 5);
     STCK(host_copy(hp.data(), d_params, hp.size() * sizeof(double)));
+    f_cur = f;
+    f_sum = 0.0;
+    for (int c = 0; c < nx; ++c) f_sum += hp[(size_t)c * 5] / h3;
     for (int c = 0; c < nx; ++c) {
       const double* q = &hp[(size_t)c * 5];
       if (!finite_pos(q[0]) || !finite_pos(q[4]) || !std::isfinite(q[1]) || !std::isfinite(q[2]) ||
@@ -228,12 +252,79 @@ struct Solver {
     return LINCOLL_OK;
   }
 
+  // The Newton operator maps onto zero-mass fields and is singular along one
+  // direction of non-zero mass (the steady state's mass mode), so a
+  // zero-mass right-hand side has a unique zero-mass solution.  Keeping every
+  // preconditioned vector at zero mass (removing its total along the current
+  // iterate f) keeps the inner solution on it: the correction is then well
+  // defined (and learnable) and the Newton update preserves the mass.
+  int zero_mass(double* z) {
+    HIPCK(st_remove_mass(z, f_cur, f_sum, N, d_partial, d_red, s));
+    return LINCOLL_OK;
+  }
+
   // z = M^-1 v, the right preconditioner (z = v without one)
   int precondition(const double* v, double* z) {
-    if (sp.precond == LINCOLL_PRECOND_SWEEP)
-      HIPCK(st_sweep(v, z, plan_nu(pl), dtype != LINCOLL_F64, d_wall, wg, nx, n, L, dx, sp.kn, s));
-    else
+    if (sp.precond == LINCOLL_PRECOND_NONE) {
       HIPCK(st_axpby(z, 1.0, v, 0.0, nullptr, N, s));
+      return LINCOLL_OK;
+    }
+    HIPCK(st_sweep(v, z, plan_nu(pl), dtype != LINCOLL_F64, d_wall, wg, nx, n, L, dx, sp.kn, s));
+    return zero_mass(z);
+  }
+
+  // features of z (about d_params) into X, scale into d_scale
+  int features(const double* z, float* X) {
+    HIPCK(ln_hermite(z, nullptr, d_params, nx, n, L, d_m5, s));
+    HIPCK(ln_features(d_m5, nx, X, d_scale, s));
+    return LINCOLL_OK;
+  }
+
+  // Learned start of an inner solve: z = sweep(b), Delta = correction of
+  // mlp(features(z)); x0 = a z + alpha Delta with (a, alpha) minimising
+  // |b - A x0| (two operator applications), so the start is never worse in
+  // residual than zero or the sweep alone.  On return x0 holds the start and
+  // V[0] its residual b - A x0; Z[0] and V[1] are used as scratch.
+  int learned_start(const double* b, double* x0, double* V, double* Z) {
+    double *D = Z, *Az = V, *AD = V + N;
+    STCK(precondition(b, x0));
+    STCK(features(x0, d_X));
+    HIPCK(mlp_forward(d_X, mlp_device_weights(sp.mlp), nx, nullptr, d_Y, s));
+    HIPCK(ln_correction(d_Y, d_scale, d_params, nx, n, L, 0, D, s));
+    STCK(zero_mass(D));
+    STCK(matvec(x0, Az));
+    STCK(matvec(D, AD));
+    double g[4];
+    HIPCK(st_mdot(V, N, 2, AD, d_partial, d_red, s));       // <Az,AD>, <AD,AD>
+    STCK(host_copy(g, d_red, 2 * sizeof(double)));
+    HIPCK(st_mdot(V, N, 1, Az, d_partial, d_red, s));       // <Az,Az>
+    STCK(host_copy(g + 2, d_red, sizeof(double)));
+    double rb[2];
+    HIPCK(st_mdot(V, N, 2, b, d_partial, d_red, s));        // <Az,b>, <AD,b>
+    STCK(host_copy(rb, d_red, 2 * sizeof(double)));
+    const double a11 = g[2], a12 = g[0], a22 = g[1], det = a11 * a22 - a12 * a12;
+    double a = 0.0, al = 0.0;
+    if (det > 1e-14 * a11 * a22) {
+      a = (rb[0] * a22 - rb[1] * a12) / det;
+      al = (a11 * rb[1] - a12 * rb[0]) / det;
+    } else if (a11 > 0.0) {
+      a = rb[0] / a11;
+    }
+    if (!std::isfinite(a) || !std::isfinite(al)) a = al = 0.0;
+    HIPCK(st_axpby(x0, a, x0, al, D, N, s));
+    HIPCK(st_axpby(V, -a, V, 1.0, b, N, s));                // V0 = b - a Az
+    HIPCK(st_axpby(V, 1.0, V, -al, AD, N, s));              //      - alpha A Delta
+    return LINCOLL_OK;
+  }
+
+  // appends nx training rows: features of z = sweep(b), targets m(g - z)/s
+  int record(const double* b, const double* g, double* z) {
+    if (!sp.rec_X || rec_rows + nx > sp.rec_cap) return LINCOLL_OK;
+    STCK(precondition(b, z));
+    STCK(features(z, sp.rec_X + (size_t)rec_rows * MLP_IN));
+    HIPCK(ln_hermite(g, z, d_params, nx, n, L, d_m5, s));
+    HIPCK(ln_targets(d_m5, d_scale, nx, sp.rec_T + (size_t)rec_rows * MLP_OUT, s));
+    rec_rows += nx;
     return LINCOLL_OK;
   }
 
@@ -243,15 +334,30 @@ struct Solver {
   // Stops when the weighted residual <= max(inner_rtol |b|, inner_atol) or
   // after max_inner operator evaluations.  V: (restart + 1) vectors, Z:
   // restart vectors, tmp: one.
-  int gmres(const double* b, double bnorm, double* x, double* V, double* Z, double* tmp, int* iters) {
+  // With x0 set, x holds the starting guess on entry and V[0] its residual
+  // b - A x (the tolerance stays relative to |b|); start counts operator
+  // evaluations already spent on the start.
+  int gmres(const double* b, double bnorm, double* x, double* V, double* Z, double* tmp, int* iters, bool x0 = false,
+            long start = -1) {
     const int m = sp.restart;
     const double target = std::max(sp.inner_rtol * bnorm * wnorm, sp.inner_atol) / wnorm;   // plain norm
-    const long start = matvecs;
-    HIPCK(hipMemsetAsync(x, 0, (size_t)N * sizeof(double), s));
+    if (start < 0) start = matvecs;
     double beta = bnorm;
     *iters = 0;
-    if (!(beta > target)) return LINCOLL_OK;
-    HIPCK(st_axpby(V, 1.0 / beta, b, 0.0, nullptr, N, s));
+    if (x0) {
+      double bb = 0.0;
+      STCK(dot(V, V, &bb));
+      beta = std::sqrt(bb);
+      if (!(beta > target)) {
+        *iters = (int)(matvecs - start);
+        return LINCOLL_OK;
+      }
+      HIPCK(st_axpby(V, 1.0 / beta, V, 0.0, nullptr, N, s));
+    } else {
+      HIPCK(hipMemsetAsync(x, 0, (size_t)N * sizeof(double), s));
+      if (!(beta > target)) return LINCOLL_OK;
+      HIPCK(st_axpby(V, 1.0 / beta, b, 0.0, nullptr, N, s));
+    }
     std::vector<double> R((size_t)m * m, 0.0), cs(m), sn(m), g(m + 1), col(m + 2), y(m);
     for (;;) {
       std::fill(g.begin(), g.end(), 0.0);
@@ -344,7 +450,11 @@ struct Solver {
       if (k == sp.max_newton) break;
       t = clk::now();
       int its = 0;
-      if ((status = set_local(f)) || (status = gmres(r, res / wnorm, gcor, V, Z, tmp, &its))) break;
+      const bool learned = sp.precond == LINCOLL_PRECOND_LEARNED;
+      const long mv0 = matvecs;
+      if ((status = set_local(f)) || (learned && (status = learned_start(r, gcor, V, Z))) ||
+          (status = gmres(r, res / wnorm, gcor, V, Z, tmp, &its, learned, mv0)) || (status = record(r, gcor, tmp)))
+        break;
       rp.ms_inner += ms_since(t);
       if (k < 64) rp.inner_history[k] = its;
       rp.inner_iters += its;
@@ -361,6 +471,7 @@ struct Solver {
       if (constrain_mass(f, &m) == LINCOLL_OK) rp.mass = m;
     }
     rp.ms_total = ms_since(t0);
+    rp.rec_rows = rec_rows;
     if (rep) *rep = rp;
     return status;
   }
@@ -426,6 +537,32 @@ int lincoll_steady_newton_apply(lincoll_plan_t plan, const lincoll_steady_params
   STCK(S.set_local(f));
   STCK(S.matvec(g, out));
   lincoll_plan_t pl = plan;
+  HIPCK(hipStreamSynchronize(S.s));
+  return LINCOLL_OK;
+}
+
+int lincoll_learned_features(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                             const double* z, float* X, double* sc) {
+  if (!plan || !f || !z || !X) return LINCOLL_EINVAL;
+  Solver S;
+  STCK(S.init(plan, sp));
+  STCK(S.local_params(f));
+  STCK(S.features(z, X));
+  double v = 0.0;
+  STCK(S.host_copy(&v, S.d_scale, sizeof(double)));
+  if (sc) *sc = v;
+  return LINCOLL_OK;
+}
+
+int lincoll_learned_correction(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                               const float* Y, double sc, double* out) {
+  if (!plan || !f || !Y || !out || !std::isfinite(sc)) return LINCOLL_EINVAL;
+  Solver S;
+  STCK(S.init(plan, sp));
+  lincoll_plan_t pl = plan;
+  STCK(S.local_params(f));
+  HIPCK(hipMemcpyAsync(S.d_scale, &sc, sizeof(double), hipMemcpyHostToDevice, S.s));
+  HIPCK(ln_correction(Y, S.d_scale, S.d_params, S.nx, S.n, S.L, 0, out, S.s));
   HIPCK(hipStreamSynchronize(S.s));
   return LINCOLL_OK;
 }

@@ -39,6 +39,10 @@ hipError_t st_update(double* w, const double* V, long N, int k, const double* h,
 hipError_t st_combine(double* x, const double* V, long N, int k, const double* y, hipStream_t s);
 // out = a x + b y (y null: out = a x)
 hipError_t st_axpby(double* out, double a, const double* x, double b, const double* y, long N, hipStream_t s);
+// z -= (sum z / fsum) f, fsum = sum f (sets the total of z to zero along f);
+// partial, red: scratch as for st_mdot
+hipError_t st_remove_mass(double* z, const double* f, double fsum, long N, double* partial, double* red,
+                          hipStream_t s);
 hipError_t st_to_f32(const double* x, float* y, long N, hipStream_t s);
 
 }  // namespace lincoll

@@ -18,6 +18,8 @@ namespace {
 constexpr int TB = 256;          // threads per block
 constexpr int EPT = 8;           // elements per thread in the vector kernels
 constexpr int WAVES = TB / 64;
+constexpr int SWEEP_TB = 64;      // one wave per block: the sweep has only n^3/2 threads
+constexpr int SWEEP_BATCH = 16;   // cells of loads in flight per thread
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -156,25 +158,41 @@ __global__ void __launch_bounds__(TB) k_transport(const double* __restrict__ x, 
 // rho_L = -wall[0] / sum v1+ E_L, wall[0] = sum v1- z over the first cell as
 // left by the NEG pass.  A fixed linear map, used as a preconditioner.
 template <typename TN, bool NEG>
-__global__ void __launch_bounds__(TB) k_sweep(const double* __restrict__ y, double* __restrict__ z,
-                                              const TN* __restrict__ nu, const double* __restrict__ wall, WallGeom wg,
-                                              int n, int nx, double L, double hv, double dx, double kn) {
+__global__ void __launch_bounds__(SWEEP_TB) k_sweep(const double* __restrict__ y, double* __restrict__ z,
+                                                    const TN* __restrict__ nu, const double* __restrict__ wall,
+                                                    WallGeom wg, int n, int nx, double L, double hv, double dx,
+                                                    double kn) {
   const long n2 = (long)n * n, n3 = n2 * n;
   const long count = NEG ? (long)(n / 2 + 1) * n2 : (long)(n / 2 - 1) * n2;
-  const long t = (long)blockIdx.x * TB + threadIdx.x;
+  const long t = (long)blockIdx.x * SWEEP_TB + threadIdx.x;
   if (t >= count) return;
   const long e = (NEG ? 0 : (long)(n / 2 + 1) * n2) + t;
   const int i1 = (int)(e / n2), i2 = (int)((e / n) % n), i3 = (int)(e % n);
-  const double v1 = -L + i1 * hv, a = fabs(v1) / dx;
+  const double v1 = -L + i1 * hv, a = fabs(v1) / dx, ikn = 1.0 / kn;
   double prev = 0.0;
   if (!NEG) prev = -wall[0] / wg.flux_in[0] * wall_shape(v1, -L + i2 * hv, -L + i3 * hv, wg, 0);
-  for (int k = 0; k < nx; ++k) {
-    const long c = NEG ? nx - 1 - k : k;
-    const long i = c * n3 + e;
-    const double d = a + fmax((double)nu[i], 0.0) / kn;
-    const double v = d > 0.0 ? (y[i] + a * prev) / d : 0.0;
-    z[i] = v;
-    prev = v;
+  // the recurrence is serial in the cells; its loads are not, so they are
+  // issued SWEEP_BATCH cells ahead
+  for (int k0 = 0; k0 < nx; k0 += SWEEP_BATCH) {
+    double yv[SWEEP_BATCH], dv[SWEEP_BATCH];
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u) {
+      const int k = k0 + u;
+      if (k < nx) {
+        const long i = (NEG ? nx - 1 - k : k) * n3 + e;
+        yv[u] = y[i];
+        dv[u] = a + fmax((double)nu[i], 0.0) * ikn;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u) {
+      const int k = k0 + u;
+      if (k < nx) {
+        const double v = dv[u] > 0.0 ? (yv[u] + a * prev) / dv[u] : 0.0;
+        z[(NEG ? nx - 1 - k : k) * n3 + e] = v;
+        prev = v;
+      }
+    }
   }
 }
 
@@ -271,6 +289,29 @@ __global__ void __launch_bounds__(TB) k_combine(double* __restrict__ x, const do
   }
 }
 
+// partial[b][0] = block b's part of sum x
+__global__ void __launch_bounds__(TB) k_sum(const double* __restrict__ x, long N, double* __restrict__ partial) {
+  double v[1] = {0.0};
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const long i = vec_index(r);
+    if (i < N) v[0] += x[i];
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) partial[(long)blockIdx.x * GMRES_MAXK] = v[0];
+}
+
+// z -= (*sz / fmass) f
+__global__ void __launch_bounds__(TB) k_remove_mass(double* __restrict__ z, const double* __restrict__ f,
+                                                    const double* __restrict__ sz, double ifmass, long N) {
+  const double c = *sz * ifmass;
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const long i = vec_index(r);
+    if (i < N) z[i] -= c * f[i];
+  }
+}
+
 // out = a x + b y (y may be null: out = a x); out may alias x or y
 __global__ void __launch_bounds__(TB) k_axpby(double* out, double a, const double* x, double b, const double* y,
                                               long N) {
@@ -318,17 +359,18 @@ hipError_t st_sweep(const double* y, double* z, const void* nu, int nu_f32, doub
                     int n, double L, double dx, double kn, hipStream_t s) {
   const double hv = 2.0 * L / n;
   const long n2 = (long)n * n;
-  const unsigned bneg = (unsigned)(((n / 2 + 1) * n2 + TB - 1) / TB), bpos = (unsigned)(((n / 2 - 1) * n2 + TB - 1) / TB);
+  const unsigned bneg = (unsigned)(((n / 2 + 1) * n2 + SWEEP_TB - 1) / SWEEP_TB),
+                 bpos = (unsigned)(((n / 2 - 1) * n2 + SWEEP_TB - 1) / SWEEP_TB);
   if (nu_f32) {
     const float* q = static_cast<const float*>(nu);
-    k_sweep<float, true><<<bneg, TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<float, true><<<bneg, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
     k_wall_sums<<<1, TB, 0, s>>>(z, n, nx, L, hv, wall);
-    k_sweep<float, false><<<bpos, TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<float, false><<<bpos, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
   } else {
     const double* q = static_cast<const double*>(nu);
-    k_sweep<double, true><<<bneg, TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<double, true><<<bneg, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
     k_wall_sums<<<1, TB, 0, s>>>(z, n, nx, L, hv, wall);
-    k_sweep<double, false><<<bpos, TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<double, false><<<bpos, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
   }
   return hipGetLastError();
 }
@@ -376,6 +418,15 @@ hipError_t st_combine(double* x, const double* V, long N, int k, const double* y
 
 hipError_t st_axpby(double* out, double a, const double* x, double b, const double* y, long N, hipStream_t s) {
   k_axpby<<<vec_blocks(N), TB, 0, s>>>(out, a, x, b, y, N);
+  return hipGetLastError();
+}
+
+hipError_t st_remove_mass(double* z, const double* f, double fsum, long N, double* partial, double* red,
+                          hipStream_t s) {
+  const unsigned nb = vec_blocks(N);
+  k_sum<<<nb, TB, 0, s>>>(z, N, partial);
+  k_reduce_cols<<<1, TB, 0, s>>>(partial, (int)nb, red);
+  k_remove_mass<<<nb, TB, 0, s>>>(z, f, red, 1.0 / fsum, N);
   return hipGetLastError();
 }
 

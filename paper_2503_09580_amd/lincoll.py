@@ -19,13 +19,18 @@ PATHS = {"auto": 0, "staged": 1, "fused": 2}
 TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
 INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
         "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11, "L": 12, "project": 13}
-PRECONDS = {"none": 0, "sweep": 1}
+PRECONDS = {"none": 0, "sweep": 1, "learned": 2}
+MLP_IN, MLP_HIDDEN, MLP_OUT = 26, 128, 5
+MLP_WEIGHTS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2, "sphere_polar": 3, "sphere_azimuth": 4, "project": 5}
 SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
            "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
            "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",
            "lincoll_set_option", "lincoll_autotune", "lincoll_rk4", "lincoll_steady_default",
-           "lincoll_steady_residual", "lincoll_steady_newton_apply", "lincoll_steady_solve"]
+           "lincoll_steady_residual", "lincoll_steady_newton_apply", "lincoll_steady_solve",
+           "lincoll_mlp_create", "lincoll_mlp_destroy", "lincoll_mlp_set_stream", "lincoll_mlp_weights",
+           "lincoll_mlp_forward", "lincoll_mlp_loss_grad", "lincoll_mlp_train", "lincoll_learned_features",
+           "lincoll_learned_correction"]
 
 
 class LincollError(RuntimeError):
@@ -49,29 +54,41 @@ class SteadyParams(ctypes.Structure):
                 ("theta_r", ctypes.c_double), ("u_l", ctypes.c_double * 3), ("u_r", ctypes.c_double * 3),
                 ("tol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("inner_atol", ctypes.c_double),
                 ("max_newton", ctypes.c_int), ("max_inner", ctypes.c_int), ("restart", ctypes.c_int),
-                ("init", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("init", ctypes.c_int), ("precond", ctypes.c_int), ("mlp", ctypes.c_void_p),
+                ("rec_X", ctypes.c_void_p), ("rec_T", ctypes.c_void_p), ("rec_cap", ctypes.c_int)]
 
 
 class SteadyReport(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("converged", ctypes.c_int),
                 ("residual", ctypes.c_double), ("mass", ctypes.c_double),
                 ("res_history", ctypes.c_double * 65), ("inner_history", ctypes.c_int * 64),
-                ("ms_total", ctypes.c_double), ("ms_residual", ctypes.c_double), ("ms_inner", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_residual", ctypes.c_double), ("ms_inner", ctypes.c_double),
+                ("rec_rows", ctypes.c_int)]
 
     def as_dict(self):
         k = min(self.newton_iters, 64)
         return {"newton_iters": self.newton_iters, "inner_iters": self.inner_iters,
                 "converged": bool(self.converged), "residual": self.residual, "mass": self.mass,
                 "res_history": list(self.res_history[:k + 1]), "inner_history": list(self.inner_history[:k]),
-                "ms_total": self.ms_total, "ms_residual": self.ms_residual, "ms_inner": self.ms_inner}
+                "ms_total": self.ms_total, "ms_residual": self.ms_residual, "ms_inner": self.ms_inner,
+                "rec_rows": self.rec_rows}
 
 
 def steady_params(nx, **kw):
     """SteadyParams with the library defaults for nx cells, then kw
-    (u_l / u_r as 3-sequences)."""
+    (u_l / u_r as 3-sequences, precond as a name, mlp as an MLP, rec_X /
+    rec_T as float32 CUDA tensors [rows, 26] / [rows, 5], which the caller
+    keeps alive)."""
     sp = SteadyParams()
     _lib.lincoll_steady_default(ctypes.byref(sp), int(nx))
+    if "rec_X" in kw:
+        X, T = kw.pop("rec_X"), kw.pop("rec_T")
+        if X.shape[0] != T.shape[0] or X.shape[1:] != (MLP_IN,) or T.shape[1:] != (MLP_OUT,):
+            raise ValueError("rec_X [rows, 26] and rec_T [rows, 5] expected")
+        sp.rec_X, sp.rec_T, sp.rec_cap = X.data_ptr(), T.data_ptr(), X.shape[0]
     for k, v in kw.items():
+        if k == "mlp":
+            v = v._h.value if v is not None else None
         if k in ("u_l", "u_r"):
             v = (ctypes.c_double * 3)(*[float(a) for a in v])
         if k == "precond" and isinstance(v, str):
@@ -111,6 +128,15 @@ def _load():
         "lincoll_steady_residual": (i, [vp, P(SteadyParams), vp, vp, P(d)]),
         "lincoll_steady_newton_apply": (i, [vp, P(SteadyParams), vp, vp, vp]),
         "lincoll_steady_solve": (i, [vp, P(SteadyParams), vp, P(SteadyReport)]),
+        "lincoll_mlp_create": (i, [ctypes.c_ulonglong, P(vp)]),
+        "lincoll_mlp_destroy": (None, [vp]),
+        "lincoll_mlp_set_stream": (i, [vp, vp]),
+        "lincoll_mlp_weights": (i, [vp, P(ctypes.c_float), ctypes.c_longlong, i]),
+        "lincoll_mlp_forward": (i, [vp, vp, vp, i]),
+        "lincoll_mlp_loss_grad": (i, [vp, vp, vp, i, vp, P(d)]),
+        "lincoll_mlp_train": (i, [vp, vp, vp, i, i, d, P(d)]),
+        "lincoll_learned_features": (i, [vp, P(SteadyParams), vp, vp, vp, P(d)]),
+        "lincoll_learned_correction": (i, [vp, P(SteadyParams), vp, vp, d, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -296,7 +322,97 @@ class Plan:
                "lincoll_steady_solve")
         return rep.as_dict()
 
+    def learned_features(self, sp, f, z):
+        """(X float32 [nx, 26], s): features of z about the local Maxwellians of f."""
+        torch = self._torch
+        X = torch.empty((f.shape[0], MLP_IN), dtype=torch.float32, device=f.device)
+        v = ctypes.c_double()
+        self._sync_stream()
+        _check(_lib.lincoll_learned_features(self._h, ctypes.byref(sp), self._field(f, "f"), self._field(z, "z"),
+                                             ctypes.c_void_p(X.data_ptr()), ctypes.byref(v)), "lincoll_learned_features")
+        return X, v.value
+
+    def learned_correction(self, sp, f, Y, s):
+        """sum_a s Y_a M_c psi_a about the local Maxwellians of f."""
+        out = self._torch.empty_like(f)
+        if Y.dtype != self._torch.float32 or not Y.is_contiguous() or tuple(Y.shape) != (f.shape[0], MLP_OUT):
+            raise ValueError("Y must be a contiguous float32 [nx, 5] tensor")
+        self._sync_stream()
+        _check(_lib.lincoll_learned_correction(self._h, ctypes.byref(sp), self._field(f, "f"),
+                                               ctypes.c_void_p(Y.data_ptr()), float(s), self._field(out, "out")),
+               "lincoll_learned_correction")
+        return out
+
     def info(self, key):
         v = ctypes.c_double()
         _check(_lib.lincoll_get_info(self._h, INFO[key], ctypes.byref(v)), "lincoll_get_info")
+        return v.value
+
+
+class MLP:
+    """The learned correction's network (26 -> 128 tanh -> 5, FP32) on the
+    current GPU; arrays are float32 CUDA tensors."""
+
+    def __init__(self, seed=0):
+        import torch
+        self._torch = torch
+        self._h = ctypes.c_void_p()
+        _check(_lib.lincoll_mlp_create(int(seed), ctypes.byref(self._h)), "lincoll_mlp_create")
+
+    def close(self):
+        if self._h:
+            _lib.lincoll_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync(self):
+        _check(_lib.lincoll_mlp_set_stream(self._h, ctypes.c_void_p(self._torch.cuda.current_stream().cuda_stream)),
+               "lincoll_mlp_set_stream")
+
+    @staticmethod
+    def _f32(t, cols, name):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype.itemsize != 4 or t.dim() != 2 or t.shape[1] != cols:
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor [rows, {cols}]")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def get_weights(self):
+        w = np.empty(MLP_WEIGHTS, dtype=np.float32)
+        self._sync()
+        _check(_lib.lincoll_mlp_weights(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), MLP_WEIGHTS, 0),
+               "lincoll_mlp_weights")
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != MLP_WEIGHTS:
+            raise ValueError(f"{MLP_WEIGHTS} weights expected")
+        self._sync()
+        _check(_lib.lincoll_mlp_weights(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), MLP_WEIGHTS, 1),
+               "lincoll_mlp_weights")
+
+    def forward(self, X):
+        Y = self._torch.empty((X.shape[0], MLP_OUT), dtype=self._torch.float32, device=X.device)
+        self._sync()
+        _check(_lib.lincoll_mlp_forward(self._h, self._f32(X, MLP_IN, "X"), self._f32(Y, MLP_OUT, "Y"), X.shape[0]),
+               "lincoll_mlp_forward")
+        return Y
+
+    def loss_grad(self, X, T):
+        g = self._torch.empty(MLP_WEIGHTS, dtype=self._torch.float32, device=X.device)
+        v = ctypes.c_double()
+        self._sync()
+        _check(_lib.lincoll_mlp_loss_grad(self._h, self._f32(X, MLP_IN, "X"), self._f32(T, MLP_OUT, "T"), X.shape[0],
+                                          ctypes.c_void_p(g.data_ptr()), ctypes.byref(v)), "lincoll_mlp_loss_grad")
+        return v.value, g
+
+    def train(self, X, T, steps, lr=1e-3):
+        v = ctypes.c_double()
+        self._sync()
+        _check(_lib.lincoll_mlp_train(self._h, self._f32(X, MLP_IN, "X"), self._f32(T, MLP_OUT, "T"), X.shape[0],
+                                      int(steps), float(lr), ctypes.byref(v)), "lincoll_mlp_train")
         return v.value

@@ -1,0 +1,151 @@
+"""The learned correction of the steady solver's inner solves, through the C
+ABI, against the oracle (oracle/learned.py).
+
+1. Network: forward pass, loss and gradient (FP32 kernels against FP64
+   NumPy, 1e-5), one Adam step (1e-5 of the step).
+2. Features (FP32 outputs, 1e-6 of their scale) and the correction field
+   (FP64, 1e-12) about the local Maxwellians of a slab state.
+3. End to end on a 64-cell, n = 16 slab: training rows recorded from solves
+   at seeded wall temperatures, training lowers the loss, the network
+   predicts the macroscopic part of the held-out Newton corrections, and the
+   solve with the learned start converges to the same solution as the
+   sweep-only solve.  The inner-iteration counts of both are printed: at this
+   size the learned start saves about as many iterations as its two extra
+   operator applications cost (the inner solves are paced by kinetic, not
+   macroscopic, error)."""
+import numpy as np
+import pytest
+
+from oracle import learned as ol, steady
+from paper_2503_09580_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
+
+DEV = torch.device("cuda:0")
+
+
+def _weights(seed):
+    rng = np.random.default_rng(seed)
+    w = [rng.normal(0, 0.3, (ol.N_IN, ol.N_HID)), rng.normal(0, 0.1, ol.N_HID),
+         rng.normal(0, 0.3, (ol.N_HID, ol.N_OUT)), rng.normal(0, 0.1, ol.N_OUT)]
+    flat = ol.pack(w).astype(np.float32)
+    return flat, ol.unpack(flat.astype(np.float64))
+
+
+def _data(seed, rows):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 1, (rows, ol.N_IN)).astype(np.float32)
+    T = rng.normal(0, 0.5, (rows, ol.N_OUT)).astype(np.float32)
+    return X, T
+
+
+def _dev32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b)
+
+
+def test_forward_loss_and_gradient_match_oracle():
+    flat, w = _weights(1)
+    X, T = _data(2, 96)
+    net = lc.MLP(seed=0)
+    net.set_weights(flat)
+    assert np.array_equal(net.get_weights(), flat)
+    Y = net.forward(_dev32(X)).cpu().numpy()
+    Yr, _ = ol.forward(w, X.astype(np.float64))
+    assert rel(Y, Yr) <= 1e-5, rel(Y, Yr)
+    loss, g = net.loss_grad(_dev32(X), _dev32(T))
+    lr_, gr = ol.loss_grad(w, X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lr_) <= 1e-5 * lr_
+    assert rel(g.cpu().numpy(), ol.pack(gr)) <= 1e-5, rel(g.cpu().numpy(), ol.pack(gr))
+
+
+def test_adam_step_matches_oracle():
+    flat, w = _weights(3)
+    X, T = _data(4, 64)
+    net = lc.MLP(seed=0)
+    net.set_weights(flat)
+    net.train(_dev32(X), _dev32(T), steps=1, lr=1e-3)
+    got = net.get_weights().astype(np.float64)
+    _, g = ol.loss_grad(w, X.astype(np.float64), T.astype(np.float64))
+    m = [np.zeros_like(a) for a in w]
+    v = [np.zeros_like(a) for a in w]
+    ref = ol.pack(ol.adam_step([a.copy() for a in w], list(g), m, v, 1, 1e-3)[0])
+    step_ref = ref - flat.astype(np.float64)
+    big = np.abs(ol.pack(g)) > 1e-3            # sign-like first step where the gradient is not tiny
+    # FP32 weights: the stored result carries the rounding of w - step (2 ulp of |w|)
+    tol = 2 * np.spacing(np.abs(flat[big])).astype(np.float64) + 1e-5 * 1e-3
+    assert np.all(np.abs((got - flat)[big] - step_ref[big]) <= tol)
+
+
+def test_features_and_correction_match_oracle():
+    n, L, nx = 16, 5.0, 7
+    sp = lc.steady_params(nx)
+    f, g = wl.slab_state(n, L, nx, seed=900)
+    plan = lc.Plan(n, L, 0.74, "f64")
+    fd = torch.from_numpy(f).to(DEV)
+    X, s = plan.learned_features(sp, fd, torch.from_numpy(g).to(DEV))
+    P = steady.Problem(n, L, 0.74, nx, sp.kn, sp.theta_l, sp.theta_r)
+    params = P.moments(f)
+    Xr, sr = ol.features(ol.moments(g, params, n, L))
+    assert abs(s - sr) <= 1e-12 * sr
+    X = X.cpu().numpy()
+    assert np.max(np.abs(X - Xr)) <= 1e-6 * np.max(np.abs(Xr)), np.max(np.abs(X - Xr))
+    Y = np.random.default_rng(901).normal(0, 0.3, (nx, 5)).astype(np.float32)
+    d = plan.learned_correction(sp, fd, _dev32(Y), 0.37).cpu().numpy()
+    dr = ol.correction(Y.astype(np.float64), 0.37, params, n, L)
+    assert rel(d, dr) <= 1e-12, rel(d, dr)
+
+
+def _record(plan, nx, n, thetas, **kw):
+    rows = len(thetas) * 8 * nx
+    RX = torch.zeros((rows, ol.N_IN), dtype=torch.float32, device=DEV)
+    RT = torch.zeros((rows, ol.N_OUT), dtype=torch.float32, device=DEV)
+    used = 0
+    f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
+    for th in thetas:
+        sp = lc.steady_params(nx, theta_r=th, inner_rtol=1e-8, inner_atol=0.0, rec_X=RX[used:], rec_T=RT[used:], **kw)
+        rep = plan.steady_solve(sp, f)
+        assert rep["converged"], rep
+        assert rep["rec_rows"] == rep["newton_iters"] * nx
+        used += rep["rec_rows"]
+    return RX[:used].contiguous(), RT[:used].contiguous()
+
+
+def test_learned_start_end_to_end():
+    n, L, om, nx = 16, 6.0, 0.74, 64
+    plan = lc.Plan(n, L, om, "f32")
+    X, T = _record(plan, nx, n, (1.1, 1.3, 1.7, 2.0))
+    Xh, Th = _record(plan, nx, n, (1.5,))
+    net = lc.MLP(seed=7)
+    l0, _ = net.loss_grad(X, T)
+    l1 = net.train(X, T, steps=3000, lr=2e-3)
+    print("training loss", l0, "->", l1)
+    assert l1 < 1e-2 * l0
+    Y = net.forward(Xh).cpu().numpy()
+    Tn = Th.cpu().numpy()
+    for k in range(Tn.shape[0] // nx):
+        sl = slice(k * nx, (k + 1) * nx)
+        err = np.linalg.norm(Y[sl] - Tn[sl]) / np.linalg.norm(Tn[sl])
+        print("held-out Newton step", k, "relative error", err)
+        assert err < 0.3
+    res = {}
+    f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
+    for pc in ("sweep", "learned"):
+        sp = lc.steady_params(nx, theta_r=1.5, precond=pc, mlp=net if pc == "learned" else None)
+        rep = plan.steady_solve(sp, f)
+        res[pc] = (rep, f.cpu().numpy().copy())
+        print(pc, "inner iterations", rep["inner_iters"], rep["inner_history"], rep["res_history"])
+        assert rep["converged"] and abs(rep["mass"] - 1.0) < 1e-12, rep
+    (rs, fs), (rl, fl) = res["sweep"], res["learned"]
+    assert rl["newton_iters"] == rs["newton_iters"]
+    # both meet the Newton tolerance 1e-5 of the same discrete problem
+    assert np.max(np.abs(fs - fl)) <= 1e-3 * np.max(np.abs(fs))
