@@ -164,33 +164,31 @@ __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in,
   static_for<0, NN>([&](auto k1) { dst[(size_t)k1 * NN] = double2{vr[k1], vi[k1]}; });
 }
 
-// All azimuths of one (g-node, polar cosine) for pairs of planes (cell, z):
+// All azimuths of one (g-node, polar cosine) for one plane (cell, z) per
+// workgroup of 2 NN threads:
 //   S (+)= sum_m w Re(c_m d_m),  c_m, d_m = iDFT_xy[G+- exp(+-i alpha (sx_m p1 + sy_m p2))]
 // with sx_m, sy_m = sin(polar) (cos, sin)(2 pi m / nazim) and w the polar weight
 // over nazim.  G+- stay in L2 across the azimuth loop and S is written once,
 // so the HBM traffic of the loop is that of G+- and S alone.  Only Re S is
 // kept: S enters Q through Re iDFT[s_j DFT S] with s_j real and even in the
 // signed frequencies, which maps i Im S to a purely imaginary field.
-// Thread a of a plane owns column a for the first transform and row a for the
-// second; c is parked in LDS (own row) while d is transformed.
+// Lanes [0, NN) transform c and lanes [NN, 2 NN) transform d at the same time
+// (lane a: column a, then row a); the product exchanges half rows between
+// lane a and lane a + NN, so each lane accumulates NN/2 values of S.
 template <int NN>
-__global__ void __launch_bounds__(64) k_qc_azim(const double2* __restrict__ Gp, const double2* __restrict__ Gm,
-                                                 double2* __restrict__ S, double alpha, double st, double w,
-                                                 int nazim, int first, int nplanes) {
-  constexpr int NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
-  __shared__ double2 Cb[PPB * NP];        // c, row x1 = a of thread a
-  __shared__ double2 Ub[PPB * NN * LD];   // transposes
-  __shared__ double2 E1[NN];              // exp(i alpha sx p1) for the current azimuth
-  const int lp = threadIdx.x / NN, a = threadIdx.x % NN;
-  const long pid = (long)blockIdx.x * PPB + lp;
-  const bool active = pid < nplanes;
-  double2* cb = Cb + lp * NP;
-  double2* ub = Ub + lp * NN * LD;
-  const double2* gp = Gp + (active ? pid : 0) * NP + a;
-  const double2* gm = Gm + (active ? pid : 0) * NP + a;
-  double sacc[NN];
-  static_for<0, NN>([&](auto x) { sacc[x] = 0.0; });
-  double vr[NN], vi[NN];
+__global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ Gp, const double2* __restrict__ Gm,
+                                                     double2* __restrict__ S, double alpha, double st, double w,
+                                                     int nazim, int first) {
+  constexpr int NP = NN * NN, LD = NN + 1, H = NN / 2;
+  __shared__ double2 Ub[2][NN * LD];   // transposes of c and d
+  __shared__ double2 E1[NN];           // exp(i alpha sx p1) for the current azimuth
+  const int half = threadIdx.x / NN, a = threadIdx.x % NN;
+  const long pid = blockIdx.x;
+  double2* ub = Ub[half];
+  const double2* src = (half == 0 ? Gp : Gm) + pid * NP + a;
+  const double sg = half == 0 ? 1.0 : -1.0;   // c: exp(+i a.p), d: exp(-i a.p)
+  double sacc[H], vr[NN], vi[NN];
+  static_for<0, H>([&](auto x) { sacc[x] = 0.0; });
   for (int m = 0; m < nazim; ++m) {
     const double ph = 2.0 * M_PI * m / nazim;
     const double sx = st * cos(ph), sy = st * sin(ph);
@@ -202,44 +200,38 @@ __global__ void __launch_bounds__(64) k_qc_azim(const double2* __restrict__ Gp, 
     double s2, c2;
     sincos(alpha * sy * sgn_idx<NN>(a), &s2, &c2);
     __syncthreads();
-#pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-      const double2* src = pass == 0 ? gp : gm;
-      const double sg = pass == 0 ? 1.0 : -1.0;   // c: exp(+i a.p), d: exp(-i a.p)
-      static_for<0, NN>([&](auto k1) {
-        const double2 v = src[(size_t)k1 * NN];
-        const double2 e = E1[k1];
-        const double er = e.x * c2 - e.y * s2, ei = sg * (e.x * s2 + e.y * c2);
-        vr[k1] = v.x * er - v.y * ei;
-        vi[k1] = v.x * ei + v.y * er;
-      });
-      fft<NN, true>(vr, vi);
-      static_for<0, NN>([&](auto k1) { ub[k1 * LD + a] = double2{vr[k1], vi[k1]}; });
-      __syncthreads();
-      static_for<0, NN>([&](auto k2) {
-        const double2 v = ub[a * LD + k2];
-        vr[k2] = v.x;
-        vi[k2] = v.y;
-      });
-      fft<NN, true>(vr, vi);
-      if (pass == 0) {
-        static_for<0, NN>([&](auto x2) { cb[a * NN + x2] = double2{vr[x2], vi[x2]}; });
-      } else {
-        static_for<0, NN>([&](auto x2) {
-          const double2 c = cb[a * NN + x2];
-          sacc[x2] += w * (c.x * vr[x2] - c.y * vi[x2]);
-        });
-      }
-      __syncthreads();   // ub (and E1 after the second pass) are reused
-    }
+    static_for<0, NN>([&](auto k1) {
+      const double2 v = src[(size_t)k1 * NN];
+      const double2 e = E1[k1];
+      const double er = e.x * c2 - e.y * s2, ei = sg * (e.x * s2 + e.y * c2);
+      vr[k1] = v.x * er - v.y * ei;
+      vi[k1] = v.x * ei + v.y * er;
+    });
+    fft<NN, true>(vr, vi);
+    static_for<0, NN>([&](auto k1) { ub[k1 * LD + a] = double2{vr[k1], vi[k1]}; });
+    __syncthreads();
+    static_for<0, NN>([&](auto k2) {
+      const double2 v = ub[a * LD + k2];
+      vr[k2] = v.x;
+      vi[k2] = v.y;
+    });
+    fft<NN, true>(vr, vi);
+    // lane a (c) takes x2 < H, lane a + NN (d) takes x2 >= H
+    static_for<0, H>([&](auto k) {
+      const double sr = half == 0 ? vr[H + k] : vr[k], si = half == 0 ? vi[H + k] : vi[k];
+      const double rr = __shfl_xor(sr, NN, 2 * NN), ri = __shfl_xor(si, NN, 2 * NN);
+      const double mr = half == 0 ? vr[k] : vr[H + k], mi = half == 0 ? vi[k] : vi[H + k];
+      sacc[k] += w * (mr * rr - mi * ri);
+    });
+    __syncthreads();   // ub and E1 are rewritten next azimuth
   }
-  // back to columns for coalesced stores: thread a writes S[x1][x2 = a]
-  static_for<0, NN>([&](auto x2) { ub[a * LD + x2] = double2{sacc[x2], 0.0}; });
+  // S[x1 = a][x2 = half H + k] -> LDS, then column-wise coalesced stores
+  static_for<0, H>([&](auto k) { Ub[0][a * LD + half * H + k] = double2{sacc[k], 0.0}; });
   __syncthreads();
-  if (!active) return;
   double2* dst = S + pid * NP + a;
-  static_for<0, NN>([&](auto x1) {
-    const double v = ub[x1 * LD + a].x;
+  static_for<0, H>([&](auto r) {
+    const int x1 = half * H + r;
+    const double v = Ub[0][x1 * LD + a].x;
     dst[(size_t)x1 * NN] = first ? double2{v, 0.0} : double2{dst[(size_t)x1 * NN].x + v, 0.0};
   });
 }
@@ -263,7 +255,7 @@ hipError_t quadcoll_n(const QuadCtx& c) {
       const double mu = c.mu[i], st = c.st[i];
       k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gp, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, +1, 0, B);
       k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gm, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, -1, 0, B);
-      k_qc_azim<NN><<<gp, 64, 0, s>>>(Gp, Gm, S, alpha, st, c.wpolar[i] / c.nazim, c.nazim, i == 0, nplanes);
+      k_qc_azim<NN><<<nplanes, 2 * NN, 0, s>>>(Gp, Gm, S, alpha, st, c.wpolar[i] / c.nazim, c.nazim, i == 0);
     }
     // Qk (+)= W_j s_j DFT3[S_j]
     k_qc_plane<NN, 1><<<gp, 64, 0, s>>>(S, S, nullptr, nplanes);
