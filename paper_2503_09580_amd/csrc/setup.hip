@@ -218,21 +218,26 @@ hipError_t setup_cells(const SetupCtx& c) {
 
 // ------------------------------------------------------------ projection
 // y = x - M sum_a phi_a (A^-1 m[x])_a per cell; moments reduced in FP64.
+constexpr int PROJ_TB = 512;
+
+// One block per cell: the five moments of x (FP64 sums in a fixed tree), the
+// coefficients A^-1 m, then y = x - M sum_a coef_a phi_a.  n is a power of
+// two, so velocity indices come from shifts of the flat index.
 template <typename T>
-__global__ void __launch_bounds__(256) k_project(const T* __restrict__ x, T* __restrict__ y, int n, double L,
-                                                  const double* __restrict__ fac64,
-                                                  const double* __restrict__ pref64, const double* __restrict__ Ainv,
-                                                  int Bc) {
-  __shared__ double red[5][256];
+__global__ void __launch_bounds__(PROJ_TB) k_project(const T* __restrict__ x, T* __restrict__ y, int n, int lgn,
+                                                     double L, const double* __restrict__ fac64,
+                                                     const double* __restrict__ pref64,
+                                                     const double* __restrict__ Ainv, int Bc) {
+  __shared__ double red[5][PROJ_TB];
   __shared__ double coef[5];
   const int cell = blockIdx.x, cc = Bc > 1 ? cell : 0;
-  const long n3 = (long)n * n * n;
+  const int n3 = n << (2 * lgn), msk = n - 1;
   const T* xc = x + (size_t)cell * n3;
   T* yc = y + (size_t)cell * n3;
   const double hv = 2.0 * L / n;
   double m[5] = {0, 0, 0, 0, 0};
-  for (long i = threadIdx.x; i < n3; i += blockDim.x) {
-    const int ix = (int)(i / (n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+  for (int i = threadIdx.x; i < n3; i += PROJ_TB) {
+    const int ix = i >> (2 * lgn), iy = (i >> lgn) & msk, iz = i & msk;
     const double v1 = -L + ix * hv, v2 = -L + iy * hv, v3 = -L + iz * hv;
     const double xv = (double)xc[i];
     m[0] += xv;
@@ -243,7 +248,7 @@ __global__ void __launch_bounds__(256) k_project(const T* __restrict__ x, T* __r
   }
   for (int a = 0; a < 5; ++a) red[a][threadIdx.x] = m[a];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = PROJ_TB / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s)
       for (int a = 0; a < 5; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + s];
     __syncthreads();
@@ -256,8 +261,8 @@ __global__ void __launch_bounds__(256) k_project(const T* __restrict__ x, T* __r
   __syncthreads();
   const double* f = fac64 + (size_t)cc * 6 * n;
   const double pm = pref64[2 * cc];
-  for (long i = threadIdx.x; i < n3; i += blockDim.x) {
-    const int ix = (int)(i / (n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+  for (int i = threadIdx.x; i < n3; i += PROJ_TB) {
+    const int ix = i >> (2 * lgn), iy = (i >> lgn) & msk, iz = i & msk;
     const double v1 = -L + ix * hv, v2 = -L + iy * hv, v3 = -L + iz * hv;
     const double M = pm * f[ix] * f[n + iy] * f[2 * n + iz];
     const double corr = coef[0] + coef[1] * v1 + coef[2] * v2 + coef[3] * v3 + coef[4] * (v1 * v1 + v2 * v2 + v3 * v3);
@@ -266,12 +271,15 @@ __global__ void __launch_bounds__(256) k_project(const T* __restrict__ x, T* __r
 }
 
 hipError_t project_cells(const ProjectCtx& c) {
+  int lgn = 0;
+  while ((1 << lgn) < c.n) ++lgn;
+  if ((1 << lgn) != c.n) return hipErrorInvalidValue;
   if (c.dtype == 0)
-    k_project<double><<<c.batch, 256, 0, c.stream>>>(static_cast<const double*>(c.x), static_cast<double*>(c.y), c.n,
-                                                      c.L, c.fac64, c.pref64, c.Ainv, c.Bc);
+    k_project<double><<<c.batch, PROJ_TB, 0, c.stream>>>(static_cast<const double*>(c.x), static_cast<double*>(c.y),
+                                                          c.n, lgn, c.L, c.fac64, c.pref64, c.Ainv, c.Bc);
   else
-    k_project<float><<<c.batch, 256, 0, c.stream>>>(static_cast<const float*>(c.x), static_cast<float*>(c.y), c.n,
-                                                     c.L, c.fac64, c.pref64, c.Ainv, c.Bc);
+    k_project<float><<<c.batch, PROJ_TB, 0, c.stream>>>(static_cast<const float*>(c.x), static_cast<float*>(c.y), c.n,
+                                                         lgn, c.L, c.fac64, c.pref64, c.Ainv, c.Bc);
   return hipGetLastError();
 }
 
