@@ -269,6 +269,13 @@ int lincoll_steady_residual(lincoll_plan_t plan, const lincoll_steady_params_t* 
 int lincoll_steady_newton_apply(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
                                 const double* g, double* out);
 
+/* z = M^-1 y, the inner solver's preconditioner sp->precond (NONE: z = y;
+ * SWEEP and LEARNED: the zero-mass transport sweep) about the local
+ * Maxwellians of f; the plan's Maxwellians are set to those of f.  y and z
+ * must not overlap.  Synchronous. */
+int lincoll_steady_precondition(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                                const double* y, double* z);
+
 /* Modified Newton iteration (Sec. 5.1): f <- f - g with A g = r(f) solved by
  * restarted flexible GMRES from g = 0 (right preconditioner sp->precond,
  * classical Gram-Schmidt, FP64 vectors, the plan's apply dtype inside A) to

@@ -115,6 +115,35 @@ class Problem:
         return np.stack([self.mass / (self.x_r - self.x_l) * (2 * math.pi * t) ** -1.5 * np.exp(-d2 / (2 * t))
                          for t in th])
 
+    # ---- the inner solve's preconditioner ----------------------------------------
+    def collision_frequency(self, params_c):
+        """nu(v) = iDFT[Omega DFT[M]] (eq. (20)): the loss frequency of L about M."""
+        M = fast_direct.maxwellian_fields(self.plan, params_c[0], params_c[1:4], params_c[4])[0]
+        return grid.idft3(self.plan.Omega * grid.dft3(M)).real
+
+    def sweep(self, y, f):
+        """One source-iteration sweep (Sec. 5.1) as a preconditioner about the
+        local Maxwellians of f: z solves
+            v1 (z_c - z_{c-1})/dx + nu+_c z_c/Kn = y_c   (v1 > 0)
+            v1 (z_{c+1} - z_c)/dx + nu+_c z_c/Kn = y_c   (v1 <= 0)
+        with nu+ = max(nu, 0), an empty ghost right of the last cell and the
+        left wall ghost rho_L E_L taken from z's own first cell; then the total
+        of z is removed along f: z <- z - (sum z / sum f) f."""
+        params = self.moments(f)
+        nu = np.stack([np.maximum(self.collision_frequency(p), 0.0) for p in params])
+        a = np.abs(self.V[0]) / self.dx
+        neg, pos = self.V[0] <= 0, self.V[0] > 0
+        z = np.zeros_like(y)
+        prev = np.zeros_like(y[0])
+        for c in range(self.nx - 1, -1, -1):
+            z[c] = np.where(neg, (y[c] + a * prev) / (a + nu[c] / self.kn), 0.0)
+            prev = z[c]
+        prev, _ = self.ghosts(z)
+        for c in range(self.nx):
+            z[c] = np.where(pos, (y[c] + a * prev) / (a + nu[c] / self.kn), z[c])
+            prev = z[c]
+        return z - np.sum(z) / np.sum(f) * f
+
     # ---- modified Newton -----------------------------------------------------
     def newton_matrix(self, params):
         """Dense matrix of g -> T[g] - L_j[g_j]/Kn (columns by unit vectors)."""

@@ -541,6 +541,19 @@ int lincoll_steady_newton_apply(lincoll_plan_t plan, const lincoll_steady_params
   return LINCOLL_OK;
 }
 
+int lincoll_steady_precondition(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
+                                const double* y, double* z) {
+  if (!plan || !f || !y || !z) return LINCOLL_EINVAL;
+  Solver S;
+  STCK(S.init(plan, sp));
+  if (overlap(y, z, (size_t)S.N * sizeof(double))) return LINCOLL_EINVAL;
+  STCK(S.set_local(f));
+  STCK(S.precondition(y, z));
+  lincoll_plan_t pl = plan;
+  HIPCK(hipStreamSynchronize(S.s));
+  return LINCOLL_OK;
+}
+
 int lincoll_learned_features(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
                              const double* z, float* X, double* sc) {
   if (!plan || !f || !z || !X) return LINCOLL_EINVAL;

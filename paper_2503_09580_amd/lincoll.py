@@ -28,6 +28,7 @@ SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll
            "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",
            "lincoll_set_option", "lincoll_autotune", "lincoll_rk4", "lincoll_steady_default",
            "lincoll_steady_residual", "lincoll_steady_newton_apply", "lincoll_steady_solve",
+           "lincoll_steady_precondition",
            "lincoll_mlp_create", "lincoll_mlp_destroy", "lincoll_mlp_set_stream", "lincoll_mlp_weights",
            "lincoll_mlp_forward", "lincoll_mlp_loss_grad", "lincoll_mlp_train", "lincoll_learned_features",
            "lincoll_learned_correction"]
@@ -128,6 +129,7 @@ def _load():
         "lincoll_steady_residual": (i, [vp, P(SteadyParams), vp, vp, P(d)]),
         "lincoll_steady_newton_apply": (i, [vp, P(SteadyParams), vp, vp, vp]),
         "lincoll_steady_solve": (i, [vp, P(SteadyParams), vp, P(SteadyReport)]),
+        "lincoll_steady_precondition": (i, [vp, P(SteadyParams), vp, vp, vp]),
         "lincoll_mlp_create": (i, [ctypes.c_ulonglong, P(vp)]),
         "lincoll_mlp_destroy": (None, [vp]),
         "lincoll_mlp_set_stream": (i, [vp, vp]),
@@ -313,6 +315,15 @@ class Plan:
         _check(_lib.lincoll_steady_newton_apply(self._h, ctypes.byref(sp), self._field(f, "f"), self._field(g, "g"),
                                                 self._field(out, "out")), "lincoll_steady_newton_apply")
         return out
+
+    def steady_precondition(self, sp, f, y, z=None):
+        """z = the inner solver's preconditioner applied to y about the local Maxwellians of f."""
+        if z is None:
+            z = self._torch.empty_like(y)
+        self._sync_stream()
+        _check(_lib.lincoll_steady_precondition(self._h, ctypes.byref(sp), self._field(f, "f"), self._field(y, "y"),
+                                                self._field(z, "z")), "lincoll_steady_precondition")
+        return z
 
     def steady_solve(self, sp, f):
         """Modified Newton solve in place on f; returns the report as a dict."""

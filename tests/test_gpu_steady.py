@@ -5,7 +5,9 @@
    walls; at the full 256-cell, n = 32 size on a sampled cell, whose
    residual the oracle evaluates from that cell and its two neighbours.
 2. Modified Newton operator T[g] - P L P g / Kn about the local Maxwellians:
-   FP64 1e-12 and FP32 1e-5 of |T g| + |P L P g|/Kn.
+   FP64 1e-12 and FP32 1e-5 of |T g| + |P L P g|/Kn; the inner solver's
+   sweep preconditioner: FP64 1e-12, FP32 plans (float collision frequency)
+   1e-6.
 3. Solve: converged GPU solutions in FP64 and FP32 applies against the
    oracle's converged solution (stored moments and sampled values); the mass
    constraint; the full C4 problem (256 cells, n = 32, FP32 applies) converges
@@ -72,6 +74,20 @@ def test_newton_operator_matches_oracle(dtype, bar):
     ref = P.newton_operator(params)(g.reshape(-1)).reshape(g.shape)
     scale = np.linalg.norm(P.transport(g)) + np.linalg.norm(P.lcons(g, params)) / sp.kn
     assert np.linalg.norm(out - ref) <= bar * scale, np.linalg.norm(out - ref) / scale
+
+
+@pytest.mark.parametrize("dtype,bar", [("f64", 1e-12), ("f32", 1e-6)])
+def test_sweep_preconditioner_matches_oracle(dtype, bar):
+    n, L, om, nx = 16, 5.0, 0.74, 6
+    sp = lc.steady_params(nx, kn=0.3)
+    f, y = wl.slab_state(n, L, nx, seed=730)
+    plan = lc.Plan(n, L, om, dtype)
+    z = plan.steady_precondition(sp, dev(f), dev(y)).cpu().numpy()
+    ref = oracle_problem(n, L, om, sp).sweep(y, f)
+    # FP32 plans hold the collision frequency in float
+    assert np.linalg.norm(z - ref) <= bar * np.linalg.norm(ref), np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    none = plan.steady_precondition(lc.steady_params(nx, precond="none"), dev(f), dev(y)).cpu().numpy()
+    assert np.array_equal(none, y)
 
 
 def _golden():

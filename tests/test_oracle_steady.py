@@ -14,7 +14,10 @@ Each check compares the oracle with something it does not compute itself:
    a cellwise Maxwellian state (where the local Maxwellian linearization is
    exact), up to the gap between the binary and fast discretizations; its
    collision part keeps the five moments of each cell at zero.
-5. The solve keeps the discrete mass, drives the residual below the tolerance
+5. The preconditioner's sweep solves the upwind transport system with
+   nu/Kn on the diagonal (checked in operator form after undoing its mass
+   removal).
+6. The solve keeps the discrete mass, drives the residual below the tolerance
    with a monotone history, returns the global Maxwellian for equal walls,
    and for a hot right wall gives a temperature rising and a density falling
    towards it at nearly constant pressure."""
@@ -106,6 +109,27 @@ def test_wall_maxwellian_is_transport_steady():
     f = np.stack([wl.maxwellian(n, L, 1.0, (0.0, 0.0, 0.0), th)] * nx)
     T = P.transport(f)
     assert np.max(np.abs(T)) <= 1e-12 * np.max(np.abs(P.V[0] * f)) / P.dx
+
+
+def test_sweep_solves_its_transport_system():
+    """The sweep's recurrences against the operator form: before the mass
+    removal, v1+ (z_c - z_{c-1})/dx + v1- (z_{c+1} - z_c)/dx + nu+ z/Kn = y with
+    the left wall ghost from z and nothing right of the last cell."""
+    P = _problem(8, 4.0, 4, kn=0.3)
+    f, y = wl.slab_state(8, 4.0, 4, seed=11)
+    z = P.sweep(y, f)
+    assert abs(np.sum(z)) <= 1e-13 * np.sum(np.abs(z))
+    # undo the mass removal along f: z0 = z + c f solves the system for the c that the residual fixes
+    params = P.moments(f)
+    nu = np.stack([np.maximum(P.collision_frequency(p), 0.0) for p in params])
+
+    def op(x):
+        gl, _ = P.ghosts(x)
+        ext = np.concatenate([gl[None], x, np.zeros_like(x[:1])], axis=0)
+        return (P.vp * (ext[1:-1] - ext[:-2]) + P.vm * (ext[2:] - ext[1:-1])) / P.dx + nu * x / P.kn
+    r0, rf = y - op(z), op(f)
+    c = np.sum(r0 * rf) / np.sum(rf * rf)
+    assert np.linalg.norm(r0 - c * rf) <= 1e-12 * np.linalg.norm(y)
 
 
 def test_binary_term_has_zero_mass_per_cell():
