@@ -260,7 +260,7 @@ def bench_steady(a, torch, lincoll, dev):
     dtype = a.dtype or "f32"
     precond = a.precond
     sp = lincoll.steady_params(nx, kn=c["kn"], theta_l=c["theta_l"], theta_r=c["theta_r"], mass=c["mass"],
-                               precond=precond)
+                               precond=precond, inner=a.inner)
     stream = torch.cuda.Stream(device=dev)
     steps = max(1, min(a.steps, 5))
     extra = {}
@@ -321,7 +321,7 @@ def bench_steady(a, torch, lincoll, dev):
            "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": dtype,
            "data": "synthetic (closed-form initial guess)",
            "config": {"workload": f"{nx} cells x n={n}^3 velocities, box [-{L:g},{L:g})^3, omega={om}, Kn={c['kn']}, "
-                                  f"walls theta 1/1.5, tol 1e-5", "precond": precond,
+                                  f"walls theta 1/1.5, tol 1e-5", "precond": precond, "inner": a.inner,
                       "newton_iters": rep["newton_iters"], "inner_iters": rep["inner_iters"],
                       "residual": rep["residual"], "res_history": rep["res_history"],
                       "ms_residual": rep["ms_residual"], "ms_inner": rep["ms_inner"], "ms_total": rep["ms_total"],
@@ -357,6 +357,7 @@ def main():
     ap.add_argument("--dtype", default=None, help="f32 (default for apply), f64 (default for rk4), bf16x3")
     ap.add_argument("--path", default="auto")
     ap.add_argument("--config", default="C3")
+    ap.add_argument("--inner", default="gmres", choices=["gmres", "source"], help="steady: inner solver")
     ap.add_argument("--precond", default="sweep", choices=["sweep", "none", "learned"],
                     help="steady: inner preconditioner (learned: trains the network first, untimed)")
     ap.add_argument("--op", default="apply", choices=["apply", "quadcoll", "rk4", "steady"],

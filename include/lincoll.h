@@ -224,11 +224,19 @@ typedef struct {
   int restart;              /* GMRES cycle length, 1..64 (default 30) */
   int init;                 /* 1: start from eq. (initial); 0: from f as passed (default 1) */
   int precond;              /* right preconditioner of the inner GMRES, lincoll_precond_t (default SWEEP) */
+  int inner;                /* inner solver, lincoll_inner_t (default GMRES) */
   lincoll_mlp_t mlp;        /* network of LINCOLL_PRECOND_LEARNED (else unused; default NULL) */
   float* rec_X;             /* optional device [rec_cap][LINCOLL_MLP_IN]: training features, one row per cell */
   float* rec_T;             /* ... device [rec_cap][LINCOLL_MLP_OUT]: training targets (both NULL: no recording) */
   int rec_cap;              /* rows available in rec_X / rec_T */
 } lincoll_steady_params_t;
+
+typedef enum {
+  LINCOLL_INNER_GMRES = 0,   /* restarted flexible GMRES with sp->precond */
+  LINCOLL_INNER_SOURCE = 1   /* source iteration (Sec. 5.1, eq. (source_iteration)): g <- g + M^-1 (r - A g)
+                                from g = 0 with M^-1 the zero-mass sweep, i.e. (T + nu/Kn) g' =
+                                (P L P + nu) g / Kn + r; one operator application per iteration */
+} lincoll_inner_t;
 
 typedef enum {
   LINCOLL_PRECOND_NONE = 0,  /* plain GMRES */

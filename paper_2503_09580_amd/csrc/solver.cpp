@@ -56,6 +56,7 @@ int check_params(const lincoll_steady_params_t* sp) {
     return LINCOLL_EINVAL;
   if (sp->precond == LINCOLL_PRECOND_LEARNED && !sp->mlp) return LINCOLL_EINVAL;
   if ((sp->rec_X == nullptr) != (sp->rec_T == nullptr) || sp->rec_cap < 0) return LINCOLL_EINVAL;
+  if (sp->inner != LINCOLL_INNER_GMRES && sp->inner != LINCOLL_INNER_SOURCE) return LINCOLL_EINVAL;
   return LINCOLL_OK;
 }
 
@@ -334,6 +335,31 @@ struct Solver {
   // Stops when the weighted residual <= max(inner_rtol |b|, inner_atol) or
   // after max_inner operator evaluations.  V: (restart + 1) vectors, Z:
   // restart vectors, tmp: one.
+  // Source iteration (Sec. 5.1): x <- x + M^-1 (b - A x) from x = 0, M^-1 the
+  // zero-mass sweep; stops like gmres.  w, z: scratch vectors.
+  int source_iteration(const double* b, double bnorm, double* x, double* w, double* z, int* iters) {
+    const double target = std::max(sp.inner_rtol * bnorm * wnorm, sp.inner_atol) / wnorm;   // plain norm
+    const long start = matvecs;
+    *iters = 0;
+    HIPCK(hipMemsetAsync(x, 0, (size_t)N * sizeof(double), s));
+    if (!(bnorm > target)) return LINCOLL_OK;
+    HIPCK(st_axpby(w, 1.0, b, 0.0, nullptr, N, s));            // w = b - A x with x = 0
+    for (;;) {
+      HIPCK(st_sweep(w, z, plan_nu(pl), dtype != LINCOLL_F64, d_wall, wg, nx, n, L, dx, sp.kn, s));
+      STCK(zero_mass(z));
+      HIPCK(st_axpby(x, 1.0, x, 1.0, z, N, s));
+      STCK(matvec(x, w));
+      HIPCK(st_axpby(w, 1.0, b, -1.0, w, N, s));
+      double rr = 0.0;
+      STCK(dot(w, w, &rr));
+      const double res = std::sqrt(rr);
+      if (!std::isfinite(res)) break;
+      if (res <= target || matvecs - start >= sp.max_inner) break;
+    }
+    *iters = (int)(matvecs - start);
+    return LINCOLL_OK;
+  }
+
   // With x0 set, x holds the starting guess on entry and V[0] its residual
   // b - A x (the tolerance stays relative to |b|); start counts operator
   // evaluations already spent on the start.
@@ -450,11 +476,16 @@ struct Solver {
       if (k == sp.max_newton) break;
       t = clk::now();
       int its = 0;
-      const bool learned = sp.precond == LINCOLL_PRECOND_LEARNED;
+      const bool learned = sp.inner == LINCOLL_INNER_GMRES && sp.precond == LINCOLL_PRECOND_LEARNED;
       const long mv0 = matvecs;
-      if ((status = set_local(f)) || (learned && (status = learned_start(r, gcor, V, Z))) ||
-          (status = gmres(r, res / wnorm, gcor, V, Z, tmp, &its, learned, mv0)) || (status = record(r, gcor, tmp)))
+      if ((status = set_local(f))) break;
+      if (sp.inner == LINCOLL_INNER_SOURCE) {
+        if ((status = source_iteration(r, res / wnorm, gcor, V, V + N, &its))) break;
+      } else if ((learned && (status = learned_start(r, gcor, V, Z))) ||
+                 (status = gmres(r, res / wnorm, gcor, V, Z, tmp, &its, learned, mv0))) {
         break;
+      }
+      if ((status = record(r, gcor, tmp))) break;
       rp.ms_inner += ms_since(t);
       if (k < 64) rp.inner_history[k] = its;
       rp.inner_iters += its;
@@ -510,6 +541,7 @@ void lincoll_steady_default(lincoll_steady_params_t* sp, int nx) {
   sp->restart = 30;
   sp->init = 1;
   sp->precond = LINCOLL_PRECOND_SWEEP;
+  sp->inner = LINCOLL_INNER_GMRES;
 }
 
 int lincoll_steady_residual(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f, double* r,

@@ -20,6 +20,7 @@ TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
 INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
         "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11, "L": 12, "project": 13}
 PRECONDS = {"none": 0, "sweep": 1, "learned": 2}
+INNERS = {"gmres": 0, "source": 1}
 MLP_IN, MLP_HIDDEN, MLP_OUT = 26, 128, 5
 MLP_WEIGHTS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2, "sphere_polar": 3, "sphere_azimuth": 4, "project": 5}
@@ -55,7 +56,7 @@ class SteadyParams(ctypes.Structure):
                 ("theta_r", ctypes.c_double), ("u_l", ctypes.c_double * 3), ("u_r", ctypes.c_double * 3),
                 ("tol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("inner_atol", ctypes.c_double),
                 ("max_newton", ctypes.c_int), ("max_inner", ctypes.c_int), ("restart", ctypes.c_int),
-                ("init", ctypes.c_int), ("precond", ctypes.c_int), ("mlp", ctypes.c_void_p),
+                ("init", ctypes.c_int), ("precond", ctypes.c_int), ("inner", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("rec_X", ctypes.c_void_p), ("rec_T", ctypes.c_void_p), ("rec_cap", ctypes.c_int)]
 
 
@@ -94,6 +95,8 @@ def steady_params(nx, **kw):
             v = (ctypes.c_double * 3)(*[float(a) for a in v])
         if k == "precond" and isinstance(v, str):
             v = PRECONDS[v]
+        if k == "inner" and isinstance(v, str):
+            v = INNERS[v]
         setattr(sp, k, v)
     return sp
 

@@ -8,8 +8,10 @@
    FP64 1e-12 and FP32 1e-5 of |T g| + |P L P g|/Kn; the inner solver's
    sweep preconditioner: FP64 1e-12, FP32 plans (float collision frequency)
    1e-6.
-3. Solve: converged GPU solutions in FP64 and FP32 applies against the
-   oracle's converged solution (stored moments and sampled values); the mass
+3. Solve: converged GPU solutions in FP64 and FP32 applies, with GMRES
+   (sweep or no preconditioner) or the paper's source iteration as the inner
+   solver, against the oracle's converged solution (stored moments and
+   sampled values); the mass
    constraint; the full C4 problem (256 cells, n = 32, FP32 applies) converges
    in as many Newton steps as the paper's Table 8 entry for this case.
 4. An inadmissible state is reported as LINCOLL_EDIVERGED before any apply."""
@@ -106,16 +108,17 @@ def _golden():
     return cfg, np.array(mom), samples
 
 
-@pytest.mark.parametrize("dtype,precond", [("f64", "sweep"), ("f32", "sweep"), ("f64", "none")])
-def test_solve_matches_oracle_solution(dtype, precond):
+@pytest.mark.parametrize("dtype,precond,inner", [("f64", "sweep", "gmres"), ("f32", "sweep", "gmres"),
+                                                 ("f64", "none", "gmres"), ("f64", "sweep", "source")])
+def test_solve_matches_oracle_solution(dtype, precond, inner):
     cfg, mom_ref, samples = _golden()
     n, L, om, nx = int(cfg["n"]), cfg["L"], cfg["omega"], int(cfg["nx"])
     sp = lc.steady_params(nx, kn=cfg["kn"], theta_l=cfg["theta_l"], theta_r=cfg["theta_r"], mass=cfg["mass"],
-                          tol=1e-10, inner_atol=1e-13, max_newton=40, precond=precond)
+                          tol=1e-10, inner_atol=1e-13, max_newton=40, precond=precond, inner=inner)
     plan = lc.Plan(n, L, om, dtype)
     f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
     rep = plan.steady_solve(sp, f)
-    print(dtype, precond, rep)
+    print(dtype, precond, inner, rep)
     assert rep["converged"], rep
     assert abs(rep["mass"] - cfg["mass"]) <= 1e-12
     hist = rep["res_history"]
