@@ -18,8 +18,8 @@ namespace {
 constexpr int TB = 256;          // threads per block
 constexpr int EPT = 8;           // elements per thread in the vector kernels
 constexpr int WAVES = TB / 64;
-constexpr int SWEEP_TB = 64;      // one wave per block: the sweep has only n^3/2 threads
-constexpr int SWEEP_BATCH = 16;   // cells of loads in flight per thread
+constexpr int SWEEP_VEL = 32;      // velocities per sweep block
+constexpr int SWEEP_CHUNKS = 8;    // cell chunks per velocity (one thread each)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -152,47 +152,69 @@ __global__ void __launch_bounds__(TB) k_transport(const double* __restrict__ x, 
 // frequency of each cell's linearized operator: per velocity a first-order
 // recurrence along x in the upwind direction (the fast sweeping of the source
 // iteration, Sec. 5.1):
-//   z_c = (y_c + |v1|/dx z_prev) / (|v1|/dx + nu_c/Kn).
+//   z_c = (y_c + |v1|/dx z_prev) / (|v1|/dx + nu_c/Kn) = alpha_c z_prev + beta_c.
 // NEG (v1 <= 0) runs from the right wall leftwards with an empty (zero) ghost;
 // the POS pass (v1 > 0) runs rightwards from the left ghost rho_L E_L with
 // rho_L = -wall[0] / sum v1+ E_L, wall[0] = sum v1- z over the first cell as
 // left by the NEG pass.  A fixed linear map, used as a preconditioner.
+//
+// The recurrence is linear, so each velocity's cells are cut into
+// SWEEP_CHUNKS chunks run by different threads: each chunk first composes its
+// map z_out = A z_in + B from a zero start, one thread per velocity chains the
+// chunk maps from the ghost, and each chunk then reruns its cells from its
+// exact carry-in.  A block holds SWEEP_VEL velocities x SWEEP_CHUNKS chunks.
 template <typename TN, bool NEG>
-__global__ void __launch_bounds__(SWEEP_TB) k_sweep(const double* __restrict__ y, double* __restrict__ z,
-                                                    const TN* __restrict__ nu, const double* __restrict__ wall,
-                                                    WallGeom wg, int n, int nx, double L, double hv, double dx,
-                                                    double kn) {
+__global__ void __launch_bounds__(SWEEP_VEL * SWEEP_CHUNKS) k_sweep(const double* __restrict__ y,
+                                                                    double* __restrict__ z,
+                                                                    const TN* __restrict__ nu,
+                                                                    const double* __restrict__ wall, WallGeom wg,
+                                                                    int n, int nx, double L, double hv, double dx,
+                                                                    double kn) {
+  __shared__ double cA[SWEEP_CHUNKS][SWEEP_VEL], cB[SWEEP_CHUNKS][SWEEP_VEL];
   const long n2 = (long)n * n, n3 = n2 * n;
   const long count = NEG ? (long)(n / 2 + 1) * n2 : (long)(n / 2 - 1) * n2;
-  const long t = (long)blockIdx.x * SWEEP_TB + threadIdx.x;
-  if (t >= count) return;
-  const long e = (NEG ? 0 : (long)(n / 2 + 1) * n2) + t;
+  const int lv = threadIdx.x % SWEEP_VEL, ch = threadIdx.x / SWEEP_VEL;
+  const long t = (long)blockIdx.x * SWEEP_VEL + lv;
+  const bool live = t < count;
+  const long e = (NEG ? 0 : (long)(n / 2 + 1) * n2) + (live ? t : 0);
   const int i1 = (int)(e / n2), i2 = (int)((e / n) % n), i3 = (int)(e % n);
   const double v1 = -L + i1 * hv, a = fabs(v1) / dx, ikn = 1.0 / kn;
-  double prev = 0.0;
-  if (!NEG) prev = -wall[0] / wg.flux_in[0] * wall_shape(v1, -L + i2 * hv, -L + i3 * hv, wg, 0);
-  // the recurrence is serial in the cells; its loads are not, so they are
-  // issued SWEEP_BATCH cells ahead
-  for (int k0 = 0; k0 < nx; k0 += SWEEP_BATCH) {
-    double yv[SWEEP_BATCH], dv[SWEEP_BATCH];
-#pragma unroll
-    for (int u = 0; u < SWEEP_BATCH; ++u) {
-      const int k = k0 + u;
-      if (k < nx) {
-        const long i = (NEG ? nx - 1 - k : k) * n3 + e;
-        yv[u] = y[i];
-        dv[u] = a + fmax((double)nu[i], 0.0) * ikn;
-      }
+  const int per = (nx + SWEEP_CHUNKS - 1) / SWEEP_CHUNKS;
+  const int k0 = ch * per, k1 = min(nx, k0 + per);   // steps k of this chunk (k = 0 at the inflow wall)
+  auto cell = [&](int k) { return (long)(NEG ? nx - 1 - k : k) * n3 + e; };
+  // 1. the chunk's map from a zero carry-in
+  double A = 1.0, B = 0.0;
+  if (live)
+    for (int k = k0; k < k1; ++k) {
+      const long i = cell(k);
+      const double d = a + fmax((double)nu[i], 0.0) * ikn;
+      const double al = d > 0.0 ? a / d : 0.0, be = d > 0.0 ? y[i] / d : 0.0;
+      A *= al;
+      B = al * B + be;
     }
-#pragma unroll
-    for (int u = 0; u < SWEEP_BATCH; ++u) {
-      const int k = k0 + u;
-      if (k < nx) {
-        const double v = dv[u] > 0.0 ? (yv[u] + a * prev) / dv[u] : 0.0;
-        z[(NEG ? nx - 1 - k : k) * n3 + e] = v;
-        prev = v;
-      }
+  cA[ch][lv] = A;
+  cB[ch][lv] = B;
+  __syncthreads();
+  // 2. chain the chunks from the ghost
+  if (ch == 0) {
+    double carry = 0.0;
+    if (!NEG && live) carry = -wall[0] / wg.flux_in[0] * wall_shape(v1, -L + i2 * hv, -L + i3 * hv, wg, 0);
+    for (int c = 0; c < SWEEP_CHUNKS; ++c) {
+      const double in = carry;
+      carry = cA[c][lv] * in + cB[c][lv];
+      cA[c][lv] = in;   // becomes chunk c's carry-in
     }
+  }
+  __syncthreads();
+  // 3. rerun the chunk from its carry-in
+  if (!live) return;
+  double prev = cA[ch][lv];
+  for (int k = k0; k < k1; ++k) {
+    const long i = cell(k);
+    const double d = a + fmax((double)nu[i], 0.0) * ikn;
+    const double v = d > 0.0 ? (y[i] + a * prev) / d : 0.0;
+    z[i] = v;
+    prev = v;
   }
 }
 
@@ -359,18 +381,19 @@ hipError_t st_sweep(const double* y, double* z, const void* nu, int nu_f32, doub
                     int n, double L, double dx, double kn, hipStream_t s) {
   const double hv = 2.0 * L / n;
   const long n2 = (long)n * n;
-  const unsigned bneg = (unsigned)(((n / 2 + 1) * n2 + SWEEP_TB - 1) / SWEEP_TB),
-                 bpos = (unsigned)(((n / 2 - 1) * n2 + SWEEP_TB - 1) / SWEEP_TB);
+  const unsigned bneg = (unsigned)(((n / 2 + 1) * n2 + SWEEP_VEL - 1) / SWEEP_VEL),
+                 bpos = (unsigned)(((n / 2 - 1) * n2 + SWEEP_VEL - 1) / SWEEP_VEL);
+  constexpr int TBS = SWEEP_VEL * SWEEP_CHUNKS;
   if (nu_f32) {
     const float* q = static_cast<const float*>(nu);
-    k_sweep<float, true><<<bneg, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<float, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
     k_wall_sums<<<1, TB, 0, s>>>(z, n, nx, L, hv, wall);
-    k_sweep<float, false><<<bpos, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<float, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
   } else {
     const double* q = static_cast<const double*>(nu);
-    k_sweep<double, true><<<bneg, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<double, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
     k_wall_sums<<<1, TB, 0, s>>>(z, n, nx, L, hv, wall);
-    k_sweep<double, false><<<bpos, SWEEP_TB, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<double, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
   }
   return hipGetLastError();
 }
