@@ -38,8 +38,9 @@ __device__ __forceinline__ int fold_q(int k) { return k <= NN / 2 ? k : NN - k; 
 // ---- column transforms along the plane axis --------------------------------
 // MODE 0: forward transform of the real f along z (columns contiguous in f),
 //         out[plane = kz][e].
-// MODE 1: inverse along kz of F exp(sign i alpha mu p_z), scaled by 1/n^3,
-//         out[plane = z][e] (G+- for one g-node and one polar cosine).
+// MODE 1: inverse along kz of F exp(+i alpha mu p_z) and of F exp(-i alpha mu p_z),
+//         scaled by 1/n^3, into cout and cout2 [plane = z][e] (G+ and G- for one
+//         g-node and one polar cosine; the second read of F comes from L2).
 // MODE 2: forward along z of S_j (in-plane already transformed); adds
 //         W_j s_j(|k|) * result into Qk[plane = kz][e] (stores at the first node).
 // MODE 3: inverse along kz; out real part to res[cell][e][z] (physical).
@@ -47,15 +48,34 @@ __device__ __forceinline__ int fold_q(int k) { return k <= NN / 2 ? k : NN - k; 
 //         16 pi^2 / n^3 Re(q) - f * V   (V from MODE 3).
 template <int NN, int MODE>
 __global__ void __launch_bounds__(128) k_qc_col(const double2* __restrict__ in, double2* __restrict__ cout,
-                                                 const double* __restrict__ f, double* __restrict__ res,
-                                                 const double* __restrict__ V, const double* __restrict__ Ws,
-                                                 int Q, int j, double alpha, double mu, int sign, int first,
-                                                 int batch) {
+                                                 double2* __restrict__ cout2, const double* __restrict__ f,
+                                                 double* __restrict__ res, const double* __restrict__ V,
+                                                 const double* __restrict__ Ws, int Q, int j, double alpha,
+                                                 double mu, int first, int batch) {
   constexpr int NP = NN * NN;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long)batch * NP) return;
   const int cell = (int)(gid / NP), e = (int)(gid % NP);
   double vr[NN], vi[NN];
+  if constexpr (MODE == 1) {
+    const double2* src = in + (size_t)cell * NN * NP + e;
+    constexpr double s3 = 1.0 / ((double)NN * NN * NN);
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const double sign = pass == 0 ? 1.0 : -1.0;
+      static_for<0, NN>([&](auto p) {
+        const double2 v = src[(size_t)p * NP];
+        double sn, cs;
+        sincos(sign * alpha * mu * sgn_idx<NN>(p), &sn, &cs);
+        vr[p] = (v.x * cs - v.y * sn) * s3;
+        vi[p] = (v.x * sn + v.y * cs) * s3;
+      });
+      fft<NN, true>(vr, vi);
+      double2* dst = (pass == 0 ? cout : cout2) + (size_t)cell * NN * NP + e;
+      static_for<0, NN>([&](auto p) { dst[(size_t)p * NP] = double2{vr[p], vi[p]}; });
+    }
+    return;
+  }
   if constexpr (MODE == 0) {
     const double* src = f + ((size_t)cell * NP + e) * NN;
     static_for<0, NN>([&](auto z) {
@@ -70,19 +90,9 @@ __global__ void __launch_bounds__(128) k_qc_col(const double2* __restrict__ in, 
       vi[p] = v.y;
     });
   }
-  if constexpr (MODE == 1) {
-    constexpr double s3 = 1.0 / ((double)NN * NN * NN);
-    static_for<0, NN>([&](auto p) {
-      double sn, cs;
-      sincos(sign * alpha * mu * sgn_idx<NN>(p), &sn, &cs);
-      const double r = vr[p] * cs - vi[p] * sn, i = vr[p] * sn + vi[p] * cs;
-      vr[p] = r * s3;
-      vi[p] = i * s3;
-    });
-  }
-  constexpr bool INV = MODE == 1 || MODE == 3 || MODE == 4;
+  constexpr bool INV = MODE == 3 || MODE == 4;
   fft<NN, INV>(vr, vi);
-  if constexpr (MODE == 0 || MODE == 1) {
+  if constexpr (MODE == 0) {
     double2* dst = cout + (size_t)cell * NN * NP + e;
     static_for<0, NN>([&](auto p) { dst[(size_t)p * NP] = double2{vr[p], vi[p]}; });
   } else if constexpr (MODE == 2) {
@@ -244,26 +254,25 @@ hipError_t quadcoll_n(const QuadCtx& c) {
   double2 *Fk = c.Fk, *Gp = c.Gp, *Gm = c.Gm, *C = c.C, *S = c.S, *Qk = c.Qk;
   hipStream_t s = c.stream;
   // F = DFT3[f]: along z, then in-plane
-  k_qc_col<NN, 0><<<gc, 128, 0, s>>>(nullptr, Fk, c.f, nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 0, B);
+  k_qc_col<NN, 0><<<gc, 128, 0, s>>>(nullptr, Fk, nullptr, c.f, nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, B);
   k_qc_plane<NN, 0><<<gp, 64, 0, s>>>(Fk, Fk, nullptr, nplanes);
   // loss: V = Re iDFT_u[Omega_u F] (into the output buffer's shadow V)
   k_qc_plane<NN, 2><<<gp, 64, 0, s>>>(Fk, C, c.Om64, nplanes);
-  k_qc_col<NN, 3><<<gc, 128, 0, s>>>(C, nullptr, nullptr, c.V, nullptr, nullptr, 0, 0, 0, 0, 0, 0, B);
+  k_qc_col<NN, 3><<<gc, 128, 0, s>>>(C, nullptr, nullptr, nullptr, c.V, nullptr, nullptr, 0, 0, 0, 0, 0, B);
   for (int j = 0; j < c.J; ++j) {
     const double alpha = M_PI * c.g[j] / (2.0 * c.L);
     for (int i = 0; i < c.npolar; ++i) {
       const double mu = c.mu[i], st = c.st[i];
-      k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gp, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, +1, 0, B);
-      k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gm, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, -1, 0, B);
+      k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gp, Gm, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, 0, B);
       k_qc_azim<NN><<<nplanes, 2 * NN, 0, s>>>(Gp, Gm, S, alpha, st, c.wpolar[i] / c.nazim, c.nazim, i == 0);
     }
     // Qk (+)= W_j s_j DFT3[S_j]
     k_qc_plane<NN, 1><<<gp, 64, 0, s>>>(S, S, nullptr, nplanes);
-    k_qc_col<NN, 2><<<gc, 128, 0, s>>>(S, Qk, nullptr, nullptr, nullptr, c.Ws, c.Q, j, 0, 0, 0, j == 0, B);
+    k_qc_col<NN, 2><<<gc, 128, 0, s>>>(S, Qk, nullptr, nullptr, nullptr, nullptr, c.Ws, c.Q, j, 0, 0, j == 0, B);
   }
   // Q = 16 pi^2 / n^3 Re iDFT_u[Qk] - f V
   k_qc_plane<NN, 3><<<gp, 64, 0, s>>>(Qk, Qk, nullptr, nplanes);
-  k_qc_col<NN, 4><<<gc, 128, 0, s>>>(Qk, nullptr, c.f, c.out, c.V, nullptr, 0, 0, 0, 0, 0, 0, B);
+  k_qc_col<NN, 4><<<gc, 128, 0, s>>>(Qk, nullptr, nullptr, c.f, c.out, c.V, nullptr, 0, 0, 0, 0, 0, B);
   return hipGetLastError();
 }
 
