@@ -218,7 +218,7 @@ typedef struct {
   double u_l[3], u_r[3];    /* wall velocities (default 0) */
   double tol;               /* Newton stops when the residual norm < tol (default 1e-5) */
   double inner_rtol;        /* inner stop: residual <= inner_rtol * |r| ... (default 1e-3) */
-  double inner_atol;        /* ... or <= inner_atol (default 1e-7) (Sec. 5.2) */
+  double inner_atol;        /* ... or <= min(inner_atol, tol / 100) (default 1e-7) (Sec. 5.2) */
   int max_newton;           /* Newton steps, >= 0 (default 30) */
   int max_inner;            /* inner iterations per Newton step, >= 1 (default 2000) */
   int restart;              /* GMRES cycle length, 1..64 (default 30) */

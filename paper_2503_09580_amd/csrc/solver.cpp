@@ -264,6 +264,10 @@ struct Solver {
     return LINCOLL_OK;
   }
 
+  // Absolute inner stop, never above 1 % of the Newton tolerance (an inner
+  // solve stopped above the outer tolerance would stall the iteration there).
+  double inner_atol() const { return std::min(sp.inner_atol, 0.01 * sp.tol); }
+
   // z = M^-1 v, the right preconditioner (z = v without one)
   int precondition(const double* v, double* z) {
     if (sp.precond == LINCOLL_PRECOND_NONE) {
@@ -338,7 +342,7 @@ struct Solver {
   // Source iteration (Sec. 5.1): x <- x + M^-1 (b - A x) from x = 0, M^-1 the
   // zero-mass sweep; stops like gmres.  w, z: scratch vectors.
   int source_iteration(const double* b, double bnorm, double* x, double* w, double* z, int* iters) {
-    const double target = std::max(sp.inner_rtol * bnorm * wnorm, sp.inner_atol) / wnorm;   // plain norm
+    const double target = std::max(sp.inner_rtol * bnorm * wnorm, inner_atol()) / wnorm;   // plain norm
     const long start = matvecs;
     *iters = 0;
     HIPCK(hipMemsetAsync(x, 0, (size_t)N * sizeof(double), s));
@@ -366,7 +370,7 @@ struct Solver {
   int gmres(const double* b, double bnorm, double* x, double* V, double* Z, double* tmp, int* iters, bool x0 = false,
             long start = -1) {
     const int m = sp.restart;
-    const double target = std::max(sp.inner_rtol * bnorm * wnorm, sp.inner_atol) / wnorm;   // plain norm
+    const double target = std::max(sp.inner_rtol * bnorm * wnorm, inner_atol()) / wnorm;   // plain norm
     if (start < 0) start = matvecs;
     double beta = bnorm;
     *iters = 0;

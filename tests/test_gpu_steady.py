@@ -135,6 +135,24 @@ def test_solve_matches_oracle_solution(dtype, precond, inner):
     assert P.norm(P.residual(fh)) < 2e-10
 
 
+def test_solve_with_graph_replay_matches_eager():
+    """The Newton operator applies through a recorded graph when the plan's
+    graph option is on; the iterates must not change."""
+    cfg, _, _ = _golden()
+    n, L, om, nx = int(cfg["n"]), cfg["L"], cfg["omega"], int(cfg["nx"])
+    sp = lc.steady_params(nx, kn=cfg["kn"], theta_l=cfg["theta_l"], theta_r=cfg["theta_r"], tol=1e-8, inner_atol=1e-11)
+    out = []
+    for graph in (0, 1):
+        plan = lc.Plan(n, L, om, "f32")
+        plan.set_option("graph", graph)
+        f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
+        rep = plan.steady_solve(sp, f)
+        assert rep["converged"] and plan.info("graph") == graph
+        out.append((rep, f.cpu().numpy()))
+    assert out[0][0]["res_history"] == out[1][0]["res_history"]
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_c4_solve_converges_like_the_paper():
     c = wl.CONFIGS["C4"]
     n, L, om, nx = c["n"], c["L"], c["omega"], c["nx"]
