@@ -14,7 +14,8 @@
    sampled values); the mass
    constraint; the full C4 problem (256 cells, n = 32, FP32 applies) converges
    in as many Newton steps as the paper's Table 8 entry for this case.
-4. An inadmissible state is reported as LINCOLL_EDIVERGED before any apply."""
+4. The paper's Newton counts (Tables 6 and 8) at Kn = 1 and 10.
+5. An inadmissible state is reported as LINCOLL_EDIVERGED before any apply."""
 import os
 
 import numpy as np
@@ -176,6 +177,29 @@ def test_c4_solve_converges_like_the_paper():
     got = r[j].cpu().numpy()
     scale = np.linalg.norm(P.transport(fj)[1]) + np.linalg.norm(P.q(fj[1:2])[0]) / sp.kn
     assert np.linalg.norm(got - ref) <= 1e-12 * scale, np.linalg.norm(got - ref) / scale
+
+
+@pytest.mark.parametrize("kind,kn,par,count", [
+    ("fourier", 1.0, 1.5, 3), ("fourier", 1.0, 3.0, 4), ("fourier", 10.0, 2.0, 2), ("fourier", 10.0, 2.5, 3),
+    ("couette", 1.0, 0.3, 2), ("couette", 1.0, 0.5, 3), ("couette", 10.0, 0.5, 2),
+])
+def test_newton_counts_of_the_paper(kind, kn, par, count):
+    """Newton steps to a residual below 1e-5 for the paper's slab runs (Sec. 5.2:
+    200 cells, n = 32, x in [-0.5, 0.5], mass 1, Maxwell molecules, R = 3.5
+    (4 above theta_R = 2), L = (3 + sqrt 2) R / 4): Table 8 (Fourier flow,
+    theta_L = 1) and Table 6 (Couette flow, walls at -+u_W, theta = 1) at
+    Kn = 1 and 10."""
+    import math
+    nx, n = 200, 32
+    R = 4.0 if kind == "fourier" and par > 2.0 else 3.5
+    plan = lc.Plan(n, (3 + math.sqrt(2)) * R / 4, 1.0, "f32", R=R)
+    if kind == "fourier":
+        sp = lc.steady_params(nx, kn=kn, theta_l=1.0, theta_r=par)
+    else:
+        sp = lc.steady_params(nx, kn=kn, theta_l=1.0, theta_r=1.0, u_l=(0, -par, 0), u_r=(0, par, 0))
+    f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
+    rep = plan.steady_solve(sp, f)
+    assert rep["converged"] and rep["newton_iters"] == count, rep["res_history"]
 
 
 def test_inadmissible_state_is_reported():
