@@ -106,7 +106,7 @@ int lincoll_mlp_create(unsigned long long seed, lincoll_mlp_t* out) {
 
 void lincoll_mlp_destroy(lincoll_mlp_t m) {
   if (!m) return;
-  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  (void)hipStreamSynchronize(m->stream);
   free_buffers(m);
   void* ps[] = {m->d_w, m->d_m, m->d_v, m->d_g};
   for (void* p : ps)

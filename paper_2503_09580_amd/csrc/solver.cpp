@@ -93,7 +93,7 @@ struct Solver {
   void* d_o = nullptr;     // apply output (plan dtype)
 
   ~Solver() {
-    if (s) (void)hipStreamSynchronize(s);
+    if (pl) (void)hipStreamSynchronize(s);   // also the null stream: work may still read these buffers
     for (void* p : owned) (void)hipFree(p);
     if (project_set) (void)lincoll_set_option(pl, LINCOLL_OPT_PROJECT, project_before);
   }

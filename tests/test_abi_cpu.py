@@ -75,6 +75,18 @@ def test_null_handles_rejected():
     assert lib.lincoll_steady_residual(nullp, ctypes.byref(sp), nullp, nullp, None) == lc.EINVAL
     assert lib.lincoll_steady_newton_apply(nullp, ctypes.byref(sp), nullp, nullp, nullp) == lc.EINVAL
     assert lib.lincoll_steady_solve(nullp, ctypes.byref(sp), nullp, ctypes.byref(rep)) == lc.EINVAL
+    assert lib.lincoll_steady_precondition(nullp, ctypes.byref(sp), nullp, nullp, nullp) == lc.EINVAL
+    assert lib.lincoll_learned_features(nullp, ctypes.byref(sp), nullp, nullp, nullp, None) == lc.EINVAL
+    assert lib.lincoll_learned_correction(nullp, ctypes.byref(sp), nullp, nullp, 1.0, nullp) == lc.EINVAL
+    # the network: null handles and arguments are rejected before any device call
+    assert lib.lincoll_mlp_create(1, None) == lc.EINVAL
+    assert lib.lincoll_mlp_set_stream(nullp, nullp) == lc.EINVAL
+    w = (ctypes.c_float * lc.MLP_WEIGHTS)()
+    assert lib.lincoll_mlp_weights(nullp, w, lc.MLP_WEIGHTS, 0) == lc.EINVAL
+    assert lib.lincoll_mlp_forward(nullp, nullp, nullp, 1) == lc.EINVAL
+    assert lib.lincoll_mlp_loss_grad(nullp, nullp, nullp, 1, nullp, None) == lc.EINVAL
+    assert lib.lincoll_mlp_train(nullp, nullp, nullp, 1, 1, 1e-3, None) == lc.EINVAL
+    lib.lincoll_mlp_destroy(nullp)
     lib.lincoll_destroy(nullp)
 
 
@@ -106,6 +118,14 @@ def test_plan_tables_rejects_small_buffer():
     out = (ctypes.c_double * 2)()
     assert lib.lincoll_plan_tables(ctypes.byref(p), 0, out, 2) == lc.EINVAL
     assert lib.lincoll_plan_tables(ctypes.byref(p), 99, None, 0) == lc.EINVAL
+
+
+def test_mlp_constants_match_header():
+    import re
+    hdr = open(os.path.join(ROOT, "include", "lincoll.h")).read()
+    vals = {k: int(v) for k, v in re.findall(r"#define LINCOLL_MLP_(IN|HIDDEN|OUT) (\d+)", hdr)}
+    assert (vals["IN"], vals["HIDDEN"], vals["OUT"]) == (lc.MLP_IN, lc.MLP_HIDDEN, lc.MLP_OUT)
+    assert lc.MLP_WEIGHTS == 26 * 128 + 128 + 128 * 5 + 5
 
 
 def test_steady_defaults():
