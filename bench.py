@@ -349,6 +349,55 @@ def bench_steady(a, torch, lincoll, dev):
     print(json.dumps(rec))
 
 
+# Table 7: Couette-flow solve times (total, s) on an 11th-gen Intel Core i7
+# with 8 threads; 200 cells, n = 32, Maxwell molecules, FP64.
+PAPER_TABLE7 = {0.1: {0.1: 174.8, 1.0: 127.1, 10.0: 121.6}, 0.2: {0.1: 242.3, 1.0: 134.0, 10.0: 124.7},
+                0.3: {0.1: 254.9, 1.0: 136.5, 10.0: 134.9}, 0.4: {0.1: 254.9, 1.0: 180.9, 10.0: 136.7},
+                0.5: {0.1: 256.5, 1.0: 199.6, 10.0: 153.1}}
+
+
+def bench_couette(a, torch, lincoll, dev):
+    """The paper's Couette flow (Sec. 5.2; walls at -+u_W, theta = 1): 200
+    cells on [-0.5, 0.5], n = 32, Maxwell molecules, R = 3.5 and
+    L = (3 + sqrt 2) R / 4, mass 1, Newton tolerance 1e-5, inner 1e-3 / 1e-7.
+    A step is one whole solve from the initial guess of eq. (initial)."""
+    kn, uw = a.kn, a.uw
+    nx, n, R = 200, 32, 3.5
+    L = (3.0 + math.sqrt(2.0)) * R / 4.0
+    dtype = a.dtype or "f32"
+    sp = lincoll.steady_params(nx, kn=kn, theta_l=1.0, theta_r=1.0, u_l=(0.0, -uw, 0.0), u_r=(0.0, uw, 0.0))
+    stream = torch.cuda.Stream(device=dev)
+    steps = max(1, min(a.steps, 5))
+    with torch.cuda.stream(stream):
+        plan = lincoll.Plan(n, L, 1.0, dtype, R=R)
+        f = torch.empty((nx, n, n, n), dtype=torch.float64, device=dev)
+        for _ in range(max(1, a.warmup)):
+            plan.steady_solve(sp, f)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rep = plan.steady_solve(sp, f)
+        stream.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        J = int(plan.info("J"))
+    paper = PAPER_TABLE7.get(round(uw, 1), {}).get(kn)
+    ach = quadcoll_flops_per_cell(n, J, 64) * nx * (rep["newton_iters"] + 1) / (rep["ms_residual"] / 1e3) / 1e12
+    rec = {"metric": "Newton solve wall-time (Couette flow, Table 7 workload)", "value": wall, "unit": "s",
+           "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": wall * 1e3, "higher_is_better": False,
+           "scaling": "strong", "vs_baseline": wall / paper if paper else None,
+           "vs_baseline_note": "value / the paper's Table 7 total on an 8-thread Intel Core i7, FP64 (other hardware)"
+           if paper else None,
+           "dtype": dtype, "data": "synthetic (closed-form initial guess)",
+           "config": {"workload": f"Couette u_W={uw}, Kn={kn}: {nx} cells x n={n}^3, R={R}, L={L:.4f}, Maxwell molecules",
+                      "newton_iters": rep["newton_iters"], "inner_iters": rep["inner_iters"],
+                      "residual": rep["residual"], "converged": rep["converged"], "paper_s": paper,
+                      "ms_residual": rep["ms_residual"], "ms_inner": rep["ms_inner"]},
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_VALU_TFLOPS, "traffic": None,
+                        "kernel": "quadcoll_apply inside the residuals (the dominant part of a solve)"}}
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,11 +407,14 @@ def main():
     ap.add_argument("--path", default="auto")
     ap.add_argument("--config", default="C3")
     ap.add_argument("--inner", default="gmres", choices=["gmres", "source"], help="steady: inner solver")
+    ap.add_argument("--kn", type=float, default=1.0, help="couette: Knudsen number")
+    ap.add_argument("--uw", type=float, default=0.5, help="couette: wall speed")
     ap.add_argument("--precond", default="sweep", choices=["sweep", "none", "learned"],
                     help="steady: inner preconditioner (learned: trains the network first, untimed)")
-    ap.add_argument("--op", default="apply", choices=["apply", "quadcoll", "rk4", "steady"],
+    ap.add_argument("--op", default="apply", choices=["apply", "quadcoll", "rk4", "steady", "couette"],
                     help="apply: batched L[h] (default); quadcoll: binary Q(f,f); rk4: Table 5 time stepping; "
-                         "steady: Newton solve of the 256-cell heat-transfer problem")
+                         "steady: Newton solve of the 256-cell heat-transfer problem; couette: the paper's "
+                         "Table 7 workload (--kn, --uw)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -389,6 +441,8 @@ def main():
         return bench_rk4(a, torch, lincoll, dev)
     if a.op == "steady":
         return bench_steady(a, torch, lincoll, dev)
+    if a.op == "couette":
+        return bench_couette(a, torch, lincoll, dev)
     h, params, c = workload(a.config)
     n, L, om, B = c["n"], c["L"], c["omega"], h.shape[0]
     td = torch.float64 if a.dtype == "f64" else torch.float32
