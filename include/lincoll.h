@@ -225,6 +225,8 @@ typedef struct {
   int init;                 /* 1: start from eq. (initial); 0: from f as passed (default 1) */
   int precond;              /* right preconditioner of the inner GMRES, lincoll_precond_t (default SWEEP) */
   int inner;                /* inner solver, lincoll_inner_t (default GMRES) */
+  int backtrack;            /* 1 (default): a Newton step that does not lower the residual is halved, at most
+                               three times (f = f_prev - lambda g, lambda = 1/2, 1/4, 1/8); 0: full steps */
   lincoll_mlp_t mlp;        /* network of LINCOLL_PRECOND_LEARNED (else unused; default NULL) */
   float* rec_X;             /* optional device [rec_cap][LINCOLL_MLP_IN]: training features, one row per cell */
   float* rec_T;             /* ... device [rec_cap][LINCOLL_MLP_OUT]: training targets (both NULL: no recording) */
@@ -260,6 +262,7 @@ typedef struct {
   int inner_history[64];    /* inner iterations of step k */
   double ms_total, ms_residual, ms_inner;   /* wall clock: whole solve, residuals, inner solves */
   int rec_rows;             /* training rows written to rec_X / rec_T */
+  int backtracks;           /* step halvings taken (each costs one residual evaluation) */
 } lincoll_steady_report_t;
 
 /* Fills *sp with the defaults above for nx cells. */

@@ -57,6 +57,7 @@ int check_params(const lincoll_steady_params_t* sp) {
   if (sp->precond == LINCOLL_PRECOND_LEARNED && !sp->mlp) return LINCOLL_EINVAL;
   if ((sp->rec_X == nullptr) != (sp->rec_T == nullptr) || sp->rec_cap < 0) return LINCOLL_EINVAL;
   if (sp->inner != LINCOLL_INNER_GMRES && sp->inner != LINCOLL_INNER_SOURCE) return LINCOLL_EINVAL;
+  if (sp->backtrack != 0 && sp->backtrack != 1) return LINCOLL_EINVAL;
   return LINCOLL_OK;
 }
 
@@ -462,22 +463,38 @@ struct Solver {
     STCK(alloc(&Z, (size_t)sp.restart * N * sizeof(double)));
     if (sp.init) HIPCK(st_initial(f, nx, n, L, sp.x_l, sp.x_r, sp.theta_l, sp.theta_r, sp.mass, s));
     int status = constrain(f, nullptr);
-    for (int k = 0; status == LINCOLL_OK; ++k) {
+    double res_prev = 0.0, lambda = 1.0;
+    for (int k = 0; status == LINCOLL_OK;) {
       clk::time_point t = clk::now();
       double res = 0.0;
       if ((status = residual(f, r, &res))) break;
       rp.ms_residual += ms_since(t);
-      if (k <= 64) rp.res_history[k] = res;
-      rp.residual = res;
       if (!std::isfinite(res)) {
         status = LINCOLL_EDIVERGED;
         break;
       }
+      // backtracking: a step that did not lower the residual is halved
+      // (f = f_prev - lambda g), at most three times
+      if (sp.backtrack && k > 0 && !(res < res_prev) && !(res < sp.tol) && lambda > 0.125) {
+        lambda *= 0.5;
+        if (hipError_t e = st_axpby(f, 1.0, f, lambda, gcor, N, s)) {
+          plan_note_hip(pl, e);
+          status = LINCOLL_EHIP;
+          break;
+        }
+        ++rp.backtracks;
+        status = constrain(f, nullptr);
+        continue;
+      }
+      if (k <= 64) rp.res_history[k] = res;
+      rp.residual = res;
       if (res < sp.tol) {
         rp.converged = 1;
         break;
       }
       if (k == sp.max_newton) break;
+      res_prev = res;
+      lambda = 1.0;
       t = clk::now();
       int its = 0;
       const bool learned = sp.inner == LINCOLL_INNER_GMRES && sp.precond == LINCOLL_PRECOND_LEARNED;
@@ -493,7 +510,7 @@ struct Solver {
       rp.ms_inner += ms_since(t);
       if (k < 64) rp.inner_history[k] = its;
       rp.inner_iters += its;
-      rp.newton_iters = k + 1;
+      rp.newton_iters = ++k;
       if (hipError_t e = st_axpby(f, 1.0, f, -1.0, gcor, N, s)) {
         plan_note_hip(pl, e);
         status = LINCOLL_EHIP;
@@ -546,6 +563,7 @@ void lincoll_steady_default(lincoll_steady_params_t* sp, int nx) {
   sp->init = 1;
   sp->precond = LINCOLL_PRECOND_SWEEP;
   sp->inner = LINCOLL_INNER_GMRES;
+  sp->backtrack = 1;
 }
 
 int lincoll_steady_residual(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f, double* r,

@@ -56,7 +56,8 @@ class SteadyParams(ctypes.Structure):
                 ("theta_r", ctypes.c_double), ("u_l", ctypes.c_double * 3), ("u_r", ctypes.c_double * 3),
                 ("tol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("inner_atol", ctypes.c_double),
                 ("max_newton", ctypes.c_int), ("max_inner", ctypes.c_int), ("restart", ctypes.c_int),
-                ("init", ctypes.c_int), ("precond", ctypes.c_int), ("inner", ctypes.c_int), ("mlp", ctypes.c_void_p),
+                ("init", ctypes.c_int), ("precond", ctypes.c_int), ("inner", ctypes.c_int),
+                ("backtrack", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("rec_X", ctypes.c_void_p), ("rec_T", ctypes.c_void_p), ("rec_cap", ctypes.c_int)]
 
 
@@ -65,7 +66,7 @@ class SteadyReport(ctypes.Structure):
                 ("residual", ctypes.c_double), ("mass", ctypes.c_double),
                 ("res_history", ctypes.c_double * 65), ("inner_history", ctypes.c_int * 64),
                 ("ms_total", ctypes.c_double), ("ms_residual", ctypes.c_double), ("ms_inner", ctypes.c_double),
-                ("rec_rows", ctypes.c_int)]
+                ("rec_rows", ctypes.c_int), ("backtracks", ctypes.c_int)]
 
     def as_dict(self):
         k = min(self.newton_iters, 64)
@@ -73,7 +74,7 @@ class SteadyReport(ctypes.Structure):
                 "converged": bool(self.converged), "residual": self.residual, "mass": self.mass,
                 "res_history": list(self.res_history[:k + 1]), "inner_history": list(self.inner_history[:k]),
                 "ms_total": self.ms_total, "ms_residual": self.ms_residual, "ms_inner": self.ms_inner,
-                "rec_rows": self.rec_rows}
+                "rec_rows": self.rec_rows, "backtracks": self.backtracks}
 
 
 def steady_params(nx, **kw):

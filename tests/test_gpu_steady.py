@@ -14,7 +14,8 @@
    sampled values); the mass
    constraint; the full C4 problem (256 cells, n = 32, FP32 applies) converges
    in as many Newton steps as the paper's Table 8 entry for this case.
-4. The paper's Newton counts (Tables 6 and 8) at Kn = 1 and 10.
+4. The paper's Newton counts (Tables 6 and 8) at Kn = 1 and 10; step
+   halving rescues the one stalling VHS Couette case.
 5. An inadmissible state is reported as LINCOLL_EDIVERGED before any apply."""
 import os
 
@@ -200,6 +201,22 @@ def test_newton_counts_of_the_paper(kind, kn, par, count):
     f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
     rep = plan.steady_solve(sp, f)
     assert rep["converged"] and rep["newton_iters"] == count, rep["res_history"]
+
+
+def test_backtracking_rescues_the_stalling_couette_case():
+    """VHS omega = 0.72, Kn = 0.1, u_W = 0.5 (the paper's Couette setup): full
+    modified Newton steps stall near 3e-3 and then grow; halving the steps
+    that do not lower the residual restores convergence."""
+    import math
+    nx, n, R = 200, 32, 3.5
+    plan = lc.Plan(n, (3 + math.sqrt(2)) * R / 4, 0.72, "f32", R=R)
+    f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
+    kw = dict(kn=0.1, theta_l=1.0, theta_r=1.0, u_l=(0, -0.5, 0), u_r=(0, 0.5, 0), max_newton=12)
+    full = plan.steady_solve(lc.steady_params(nx, backtrack=0, **kw), f)
+    assert not full["converged"] and full["backtracks"] == 0
+    damped = plan.steady_solve(lc.steady_params(nx, **kw), f)
+    assert damped["converged"] and damped["backtracks"] >= 1, damped["res_history"]
+    assert abs(damped["mass"] - 1.0) < 1e-12
 
 
 def test_inadmissible_state_is_reported():
