@@ -16,7 +16,10 @@
    in as many Newton steps as the paper's Table 8 entry for this case.
 4. The paper's Newton counts (Tables 6 and 8) at Kn = 1 and 10; step
    halving rescues the one stalling VHS Couette case.
-5. An inadmissible state is reported as LINCOLL_EDIVERGED before any apply."""
+5. Checkpoint and resume: a solve resumed from a state saved after one step
+   ends where the uninterrupted one ends.
+6. An inadmissible or non-finite state is reported as LINCOLL_EDIVERGED
+   before any apply."""
 import os
 
 import numpy as np
@@ -219,6 +222,26 @@ def test_backtracking_rescues_the_stalling_couette_case():
     assert abs(damped["mass"] - 1.0) < 1e-12
 
 
+def test_checkpoint_and_resume(tmp_path):
+    """A solve stopped after one Newton step, saved to disk and resumed from
+    the saved state (init = 0) ends where the uninterrupted solve ends."""
+    cfg, _, _ = _golden()
+    n, L, om, nx = int(cfg["n"]), cfg["L"], cfg["omega"], int(cfg["nx"])
+    kw = dict(kn=cfg["kn"], theta_l=cfg["theta_l"], theta_r=cfg["theta_r"], tol=1e-9, inner_atol=1e-12)
+    plan = lc.Plan(n, L, om, "f64")
+    f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
+    full = plan.steady_solve(lc.steady_params(nx, **kw), f)
+    f_full = f.cpu().numpy()
+    first = plan.steady_solve(lc.steady_params(nx, max_newton=1, **kw), f)
+    assert first["newton_iters"] == 1 and not first["converged"]
+    np.save(tmp_path / "state.npy", f.cpu().numpy())
+    g = torch.from_numpy(np.load(tmp_path / "state.npy")).to(DEV)
+    rest = plan.steady_solve(lc.steady_params(nx, init=0, **kw), g)
+    assert rest["converged"] and rest["newton_iters"] == full["newton_iters"] - 1
+    assert np.allclose(rest["res_history"], full["res_history"][1:], rtol=1e-9, atol=0)
+    assert np.max(np.abs(g.cpu().numpy() - f_full)) <= 1e-12 * np.max(np.abs(f_full))
+
+
 def test_inadmissible_state_is_reported():
     n, L, nx = 8, 4.0, 2
     sp = lc.steady_params(nx)
@@ -226,6 +249,11 @@ def test_inadmissible_state_is_reported():
     plan = lc.Plan(n, L, 0.74, "f64")
     with pytest.raises(lc.LincollError) as ei:
         plan.steady_newton_apply(sp, dev(-f), dev(g))
+    assert ei.value.status == lc.EDIVERGED
+    nan_f = f.copy()
+    nan_f[1, 3, 4, 5] = np.nan
+    with pytest.raises(lc.LincollError) as ei:
+        plan.steady_solve(lc.steady_params(nx, init=0), dev(nan_f))
     assert ei.value.status == lc.EDIVERGED
     bad = lc.steady_params(nx, kn=-1.0)
     with pytest.raises(lc.LincollError) as ei:
