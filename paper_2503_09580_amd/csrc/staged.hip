@@ -339,7 +339,11 @@ static hipError_t apply_n(const ApplyCtx& c) {
   k_z_fwd<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(static_cast<const TS*>(c.h), R, H, fac, pref, c.mask, c.Bc, B);
   k_plane<double, double, TS, T, NN, false, 0, 0><<<gp, 64, 0, c.stream>>>(R, R, nullptr, nullptr, c.J, 0, c.Bc,
                                                                            nplanes, 1);
-  k_plane<TS, TS, TS, T, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
+  // Transforms of h-derived data and of the products with M^h (the loss
+  // spectrum, the gain node passes, the final inverses) compute in the storage
+  // precision; only the r-derived passes keep T.
+  using TF = TS;
+  k_plane<TS, TS, TS, TF, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
   for (int j = 0; j < c.J; ++j) {
     k_plane<double, double, TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc,
                                                                             nplanes, 1);
@@ -352,12 +356,12 @@ static hipError_t apply_n(const ApplyCtx& c) {
         continue;
       }
     }
-    k_plane<TS, TS, TS, T, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(Wq, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes,
-                                                                     j == 0);
+    k_plane<TS, TS, TS, TF, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(Wq, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes,
+                                                                      j == 0);
   }
-  k_plane<TS, TS, TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc, nplanes,
-                                                                  1);
-  k_plane<TS, TS, TS, T, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
+  k_plane<TS, TS, TS, TF, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc, nplanes,
+                                                                   1);
+  k_plane<TS, TS, TS, TF, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
   k_z_inv<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(Lp, H, static_cast<const TS*>(c.h), static_cast<const TS*>(c.nu),
                                                  static_cast<TS*>(c.out), fac, pref, c.Bc, B, W);
   return hipGetLastError();
