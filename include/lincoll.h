@@ -49,7 +49,7 @@ typedef enum {
   LINCOLL_F64 = 0,   /* every step in double */
   LINCOLL_F32 = 1,   /* transforms and mode products in float; setup, mask and projection in double */
   LINCOLL_BF16X3 = 2 /* as F32, with the two in-plane forward DFT stages of the gain loop as split-bfloat16
-                        (hi + lo, three products, FP32 accumulation) matrix-core GEMMs; staged path, n = 32 */
+                        (hi + lo, three products, FP32 accumulation) matrix-core GEMMs; staged path, n = 32, 64 */
 } lincoll_dtype_t;
 
 typedef enum {

@@ -112,9 +112,9 @@ hipError_t project_cells(const ProjectCtx& c);
 bool staged_supported(int n, int dtype);
 bool fused_supported(int n, int dtype);
 hipError_t fused_apply(const ApplyCtx& c);
-// BF16x3 matrix-core forward plane transform of the gain loop (n = 32):
-// out = (first ? 0 : out) + Phi_j * DFT2(in) over the planes [nplanes][32][32].
-hipError_t plane_fwd_bf16x3(const float2* in, float2* out, const float* table, int j, int nplanes, int first,
+// BF16x3 matrix-core forward plane transform of the gain loop (n = 32, 64):
+// out = (first ? 0 : out) + Phi_j * DFT2(in) over the planes [nplanes][n][n].
+hipError_t plane_fwd_bf16x3(int n, const float2* in, float2* out, const float* table, int j, int nplanes, int first,
                             int cus, hipStream_t s);
 // RK4 stage combinations (double arithmetic on the dtype's storage)
 hipError_t rk_stage(int dtype, const void* f, const void* k, void* acc, void* tmp, long count, double a, double b,

@@ -243,15 +243,26 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, type
                                                int j, int Bc, int nplanes, int first) {
   using CI = typename V2<TI>::t;
   using C = typename V2<TO>::t;
-  using CT = typename V2<T>::t;     // the transpose in LDS keeps compute precision
   constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
-  __shared__ CT lds[PPB * NN * LD];
+  // The transposes go through LDS in compute precision, one component at a
+  // time: half the footprint of a complex tile, so that LDS does not limit the
+  // blocks per CU below what the registers allow (at n = 64 a complex double
+  // tile would leave two single-wave blocks per CU).
+  __shared__ T lds[PPB * NN * LD];
   const int lp = threadIdx.x / NN, a = threadIdx.x % NN;
   const long pid = (long)blockIdx.x * PPB + lp;
   const bool active = pid < nplanes;
   const int cell = (int)(pid / P), kz = (int)(pid % P);
   const int cc = Bc > 1 ? cell : 0;
-  CT* sm = lds + lp * NN * LD;
+  T* sm = lds + lp * NN * LD;
+  // (k1, a) -> (a, k2) when FWD, (a, k2) -> (k1, a) otherwise; w is one
+  // component of this lane's pencil
+  auto transpose = [&](T(&w)[NN], bool fwd) {
+    static_for<0, NN>([&](auto k) { sm[fwd ? k * LD + a : a * LD + k] = w[k]; });
+    __syncthreads();
+    static_for<0, NN>([&](auto k) { w[k] = sm[fwd ? a * LD + k : k * LD + a]; });
+    __syncthreads();
+  };
   T vr[NN], vi[NN];
   // column a of the plane: element [k1][a], k1 = 0..NN-1
   if (active) {
@@ -273,22 +284,11 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, type
     static_for<0, NN>([&](auto k1) { vr[k1] = T(0); vi[k1] = T(0); });
   }
   fft<NN, INV>(vr, vi);                    // along the first in-plane axis
-  static_for<0, NN>([&](auto k1) { sm[k1 * LD + a] = CT{vr[k1], vi[k1]}; });
-  __syncthreads();
-  static_for<0, NN>([&](auto k2) {
-    const CT v = sm[a * LD + k2];
-    vr[k2] = v.x;
-    vi[k2] = v.y;
-  });
+  transpose(vr, true);
+  transpose(vi, true);
   fft<NN, INV>(vr, vi);                    // along the second in-plane axis
-  __syncthreads();
-  static_for<0, NN>([&](auto k2) { sm[a * LD + k2] = CT{vr[k2], vi[k2]}; });
-  __syncthreads();
-  static_for<0, NN>([&](auto k1) {
-    const CT v = sm[k1 * LD + a];
-    vr[k1] = v.x;
-    vi[k1] = v.y;
-  });
+  transpose(vr, false);
+  transpose(vi, false);
   if (!active) return;
   C* dst = out + (size_t)pid * NP + a;
   if constexpr (POST >= 1) {
@@ -348,10 +348,10 @@ static hipError_t apply_n(const ApplyCtx& c) {
     k_plane<double, double, TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc,
                                                                             nplanes, 1);
     k_z_mid<TS, T, NN><<<gz2, 128, 0, c.stream>>>(W, Wq, fac, pref, c.Bc, B);
-    if constexpr (std::is_same<TS, float>::value && NN == 32) {
+    if constexpr (std::is_same<TS, float>::value && (NN == 32 || NN == 64)) {
       if (c.dtype == 2) {   // BF16x3: the forward in-plane DFT stages on the matrix cores
-        hipError_t e = plane_fwd_bf16x3(reinterpret_cast<const float2*>(Wq), reinterpret_cast<float2*>(Lp), Phi, j,
-                                        nplanes, j == 0, c.cus, c.stream);
+        hipError_t e = plane_fwd_bf16x3(NN, reinterpret_cast<const float2*>(Wq), reinterpret_cast<float2*>(Lp), Phi,
+                                        j, nplanes, j == 0, c.cus, c.stream);
         if (e) return e;
         continue;
       }
@@ -368,7 +368,7 @@ static hipError_t apply_n(const ApplyCtx& c) {
 }
 
 bool staged_supported(int n, int dtype) {
-  if (dtype == 2) return n == 32;   // BF16x3 matrix-core stage exists for n = 32
+  if (dtype == 2) return n == 32 || n == 64;   // the BF16x3 matrix-core stage exists for these
   return n == 8 || n == 16 || n == 32 || n == 64;
 }
 

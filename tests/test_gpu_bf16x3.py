@@ -1,5 +1,5 @@
-"""BF16x3 variant (matrix-core forward DFT stages of the gain loop) against
-the FP64 oracle and against the FP32 path on the same GPU.
+"""BF16x3 variant (matrix-core forward DFT stages of the gain loop, n = 32
+and 64) against the FP64 oracle and against the FP64 path on the same GPU.
 
 Bar: a bfloat16 hi + lo pair carries 16 significant bits, so each split
 operand is represented to within 2^-17 relative; the three-product form
@@ -64,10 +64,43 @@ def test_bf16x3_full_c3_batch_against_gpu_fp64():
     assert float(d.max()) <= BAR, float(d.max())
 
 
-def test_bf16x3_supported_only_at_n32():
-    p = lc.make_params(16, 8.0, 0.74, "bf16x3")
+def test_bf16x3_n64_c5_cells_against_oracle():
+    """n = 64 (box [-10, 10)^3): the four-wave matrix-core plane transform."""
+    cells = [0, 300, 511]
+    h, params = wl.c5(cells=cells)
+    hin = h.astype(np.float32).astype(np.float64)
+    got = run("bf16x3", hin, params, n=64, L=10.0)
+    ref = alg1.apply_batch(fd.make_plan(64, 10.0, 0.74), hin, params)
+    errs = [rel(got[b], ref[b]) for b in range(len(cells))]
+    assert max(errs) <= BAR, errs
+
+
+def test_bf16x3_n64_full_c5_batch_against_gpu_fp64():
+    h, params = wl.c5()
+    hin = h.astype(np.float32).astype(np.float64)
+    got = torch.from_numpy(run("bf16x3", hin, params, n=64, L=10.0))
+    ref = torch.from_numpy(run("f64", hin, params, n=64, L=10.0))
+    d = (got - ref).reshape(len(h), -1).norm(dim=1) / ref.reshape(len(h), -1).norm(dim=1)
+    assert float(d.max()) <= BAR, float(d.max())
+
+
+def test_bf16x3_n64_ragged_batch():
+    """A batch whose plane count (7 cells x 33 planes) is not a multiple of
+    the grid, with per-cell Maxwellians."""
+    h, params = mixed_inputs(64, 10.0, 7, seed=1310)
+    hin = h.astype(np.float32).astype(np.float64)
+    got = run("bf16x3", hin, params, n=64, L=10.0)
+    ref = run("f64", hin, params, n=64, L=10.0)
+    for b in range(7):
+        assert rel(got[b], ref[b]) <= BAR
+
+
+def test_bf16x3_supported_at_n32_and_n64_only():
     import ctypes
-    h = ctypes.c_void_p()
-    assert lc.library().lincoll_plan_ex(ctypes.byref(p), ctypes.byref(h)) == lc.EINVAL
-    plan = lc.Plan(32, 8.0, 0.74, "bf16x3")
-    assert plan.info("path") == 1            # staged path (the fused kernel has no BF16x3 stage)
+    for n in (8, 16):
+        p = lc.make_params(n, 8.0, 0.74, "bf16x3")
+        h = ctypes.c_void_p()
+        assert lc.library().lincoll_plan_ex(ctypes.byref(p), ctypes.byref(h)) == lc.EINVAL
+    for n, L in ((32, 8.0), (64, 10.0)):
+        plan = lc.Plan(n, L, 0.74, "bf16x3")
+        assert plan.info("path") == 1        # staged path (the fused kernel has no BF16x3 stage)
