@@ -183,57 +183,100 @@ __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in,
 // kept: S enters Q through Re iDFT[s_j DFT S] with s_j real and even in the
 // signed frequencies, which maps i Im S to a purely imaginary field.
 // Lanes [0, NN) transform c and lanes [NN, 2 NN) transform d at the same time
-// (lane a: column a, then row a); the product exchanges half rows between
-// lane a and lane a + NN, so each lane accumulates NN/2 values of S.
+// (lane a: column a, then row a).
+// Azimuths m and nazim - m have the same sx and opposite sy.  The factor
+// exp(+-i alpha sy p2) is constant along the first transform axis, so the
+// first-axis transform of G+- exp(+-i alpha sx p1) is done once for the pair
+// (through LDS) and the sy phase is applied after the transpose, once per
+// azimuth: nazim/2 + 1 first-axis transforms instead of nazim.
+// The product pairs lane a (c) with lane a + NN (d).  At NN = 32 these are the
+// two halves of the wave, and v_permlane32_swap of registers x2 and x2 + 16
+// leaves c[x2] d[x2] in the low half and c[x2 + 16] d[x2 + 16] in the high
+// half: a VALU exchange, with identical code in both halves.  Below NN = 32
+// the exchange is a shuffle, and the d lanes multiply their second-axis input
+// by (-1)^p2, which shifts their output by NN/2 along x2, so that every lane
+// keeps registers [0, NN/2) and sends [NN/2, NN) to its partner.  Either way
+// lane a accumulates S[a][x2 < NN/2] and lane a + NN S[a][x2 >= NN/2].
+__device__ __forceinline__ void swap_wave_halves(double& x, double& y) {
+  // lanes 32..63 of x <-> lanes 0..31 of y
+  const unsigned long long xb = __builtin_bit_cast(unsigned long long, x);
+  const unsigned long long yb = __builtin_bit_cast(unsigned long long, y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+  y = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+
 template <int NN>
 __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ Gp, const double2* __restrict__ Gm,
                                                      double2* __restrict__ S, double alpha, double st, double w,
                                                      int nazim, int first) {
   constexpr int NP = NN * NN, LD = NN + 1, H = NN / 2;
-  __shared__ double2 Ub[2][NN * LD];   // transposes of c and d
-  __shared__ double2 E1[NN];           // exp(i alpha sx p1) for the current azimuth
+  constexpr bool SWAP = NN == 32;      // c and d on the two halves of one wave
+  __shared__ double2 Ub[2][NN * LD];   // first-axis transforms of c and d, transposed
+  __shared__ double2 E[2][NN];         // exp(i alpha sx p1), exp(i alpha sy p2) of the current pair
   const int half = threadIdx.x / NN, a = threadIdx.x % NN;
   const long pid = blockIdx.x;
   double2* ub = Ub[half];
   const double2* src = (half == 0 ? Gp : Gm) + pid * NP + a;
-  const double sg = half == 0 ? 1.0 : -1.0;   // c: exp(+i a.p), d: exp(-i a.p)
+  const double sg = half == 0 ? 1.0 : -1.0;        // c: exp(+i a.p), d: exp(-i a.p)
+  const double dsign = SWAP || half == 0 ? 1.0 : -1.0;   // shuffle form, d: (-1)^p2 on the odd p2
   double sacc[H], vr[NN], vi[NN];
   static_for<0, H>([&](auto x) { sacc[x] = 0.0; });
-  for (int m = 0; m < nazim; ++m) {
+  for (int m = 0; 2 * m <= nazim; ++m) {
+    const bool pair = m > 0 && 2 * m < nazim;      // azimuth nazim - m shares sx
     const double ph = 2.0 * M_PI * m / nazim;
-    const double sx = st * cos(ph), sy = st * sin(ph);
-    if (threadIdx.x < NN) {
+    {
+      // lanes [0, NN): the sx phase of p1 = lane; lanes [NN, 2 NN): the sy phase of p2 = lane - NN
+      const double sc = half == 0 ? st * cos(ph) : st * sin(ph);
       double sn, cs;
-      sincos(alpha * sx * sgn_idx<NN>(threadIdx.x), &sn, &cs);
-      E1[threadIdx.x] = double2{cs, sn};
+      sincos(alpha * sc * sgn_idx<NN>(a), &sn, &cs);
+      E[half][a] = double2{cs, sn};
     }
-    double s2, c2;
-    sincos(alpha * sy * sgn_idx<NN>(a), &s2, &c2);
     __syncthreads();
     static_for<0, NN>([&](auto k1) {
       const double2 v = src[(size_t)k1 * NN];
-      const double2 e = E1[k1];
-      const double er = e.x * c2 - e.y * s2, ei = sg * (e.x * s2 + e.y * c2);
-      vr[k1] = v.x * er - v.y * ei;
-      vi[k1] = v.x * ei + v.y * er;
+      const double2 e = E[0][k1];
+      const double ei = sg * e.y;
+      vr[k1] = v.x * e.x - v.y * ei;
+      vi[k1] = v.x * ei + v.y * e.x;
     });
     fft<NN, true>(vr, vi);
     static_for<0, NN>([&](auto k1) { ub[k1 * LD + a] = double2{vr[k1], vi[k1]}; });
     __syncthreads();
-    static_for<0, NN>([&](auto k2) {
-      const double2 v = ub[a * LD + k2];
-      vr[k2] = v.x;
-      vi[k2] = v.y;
-    });
-    fft<NN, true>(vr, vi);
-    // lane a (c) takes x2 < H, lane a + NN (d) takes x2 >= H
-    static_for<0, H>([&](auto k) {
-      const double sr = half == 0 ? vr[H + k] : vr[k], si = half == 0 ? vi[H + k] : vi[k];
-      const double rr = __shfl_xor(sr, NN, 2 * NN), ri = __shfl_xor(si, NN, 2 * NN);
-      const double mr = half == 0 ? vr[k] : vr[H + k], mi = half == 0 ? vi[k] : vi[H + k];
-      sacc[k] += w * (mr * rr - mi * ri);
-    });
-    __syncthreads();   // ub and E1 are rewritten next azimuth
+#pragma unroll 1
+    for (int t = 0; t < (pair ? 2 : 1); ++t) {
+      // read the row and the phases again for the second azimuth rather than
+      // keeping 2 NN complex values live across the loop
+      asm volatile("" ::: "memory");
+      const double si = t == 0 ? sg : -sg;         // sign of the sy phase: azimuth m, then nazim - m
+      static_for<0, NN>([&](auto k2) {
+        const double2 v = ub[a * LD + k2];
+        const double2 e = E[1][k2];
+        double er = e.x, ei = si * e.y;
+        if constexpr (k2 % 2 == 1) {
+          er *= dsign;
+          ei *= dsign;
+        }
+        vr[k2] = v.x * er - v.y * ei;
+        vi[k2] = v.x * ei + v.y * er;
+      });
+      fft<NN, true>(vr, vi);
+      if constexpr (SWAP) {
+        static_for<0, H>([&](auto k) {
+          double xr = vr[k], yr = vr[H + k], xi = vi[k], yi = vi[H + k];
+          swap_wave_halves(xr, yr);
+          swap_wave_halves(xi, yi);
+          sacc[k] += w * (xr * yr - xi * yi);
+        });
+      } else {
+        static_for<0, H>([&](auto k) {
+          const double rr = __shfl_xor(vr[H + k], NN, 2 * NN), ri = __shfl_xor(vi[H + k], NN, 2 * NN);
+          sacc[k] += w * (vr[k] * rr - vi[k] * ri);
+        });
+      }
+    }
+    __syncthreads();   // ub and E are rewritten for the next pair
   }
   // S[x1 = a][x2 = half H + k] -> LDS, then column-wise coalesced stores
   static_for<0, H>([&](auto k) { Ub[0][a * LD + half * H + k] = double2{sacc[k], 0.0}; });
