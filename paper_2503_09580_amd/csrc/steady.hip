@@ -85,18 +85,33 @@ __global__ void k_params(const double* __restrict__ sums, int nx, double h3, dou
 
 // wall[0] = sum v1- x over the first cell, wall[1] = sum v1+ x over the last
 // (a launch of one block computes wall[0] only).
-__global__ void __launch_bounds__(TB) k_wall_sums(const double* __restrict__ x, int n, int nx, double L, double hv,
-                                                  double* __restrict__ wall) {
-  const long n3 = (long)n * n * n;
+// Only the velocities towards the wall contribute: the planes v1 < 0
+// (i1 < n/2) at the left wall and v1 > 0 (i1 > n/2) at the right.  A single
+// wide block per wall (the sum sits between the two sweeps, on the critical
+// path) reads them plane by plane.
+constexpr int TBW = 1024;
+__global__ void __launch_bounds__(TBW) k_wall_sums(const double* __restrict__ x, int n, int nx, double L, double hv,
+                                                   double* __restrict__ wall) {
+  const int n2 = n * n;
+  const long n3 = (long)n2 * n;
   const bool left = blockIdx.x == 0;
   const double* c = x + (left ? 0 : (long)(nx - 1) * n3);
-  double v[1] = {0.0};
-  for (long e = threadIdx.x; e < n3; e += TB) {
-    const double v1 = -L + (int)(e / ((long)n * n)) * hv;
-    if (left ? v1 < 0.0 : v1 > 0.0) v[0] += v1 * c[e];
+  const int i1a = left ? 0 : n / 2 + 1, i1b = left ? n / 2 : n;
+  double v = 0.0;
+  for (int i1 = i1a; i1 < i1b; ++i1) {
+    const double v1 = -L + i1 * hv;
+    const double* p = c + (long)i1 * n2;
+    for (int r = threadIdx.x; r < n2; r += TBW) v += v1 * p[r];
   }
-  block_sum<1>(v);
-  if (threadIdx.x == 0) wall[blockIdx.x] = v[0];
+  __shared__ double sm[TBW / 64];
+  v = wave_sum(v);
+  if (threadIdx.x % 64 == 0) sm[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < TBW / 64; ++w) t += sm[w];
+    wall[blockIdx.x] = t;
+  }
 }
 
 __device__ __forceinline__ double wall_shape(double v1, double v2, double v3, const WallGeom& w, int side) {
@@ -373,7 +388,7 @@ hipError_t st_params(const double* sums, int nx, int n, double L, double* params
 }
 
 hipError_t st_wall_sums(const double* x, int nx, int n, double L, double* wall, hipStream_t s) {
-  k_wall_sums<<<2, TB, 0, s>>>(x, n, nx, L, 2.0 * L / n, wall);
+  k_wall_sums<<<2, TBW, 0, s>>>(x, n, nx, L, 2.0 * L / n, wall);
   return hipGetLastError();
 }
 
@@ -387,12 +402,12 @@ hipError_t st_sweep(const double* y, double* z, const void* nu, int nu_f32, doub
   if (nu_f32) {
     const float* q = static_cast<const float*>(nu);
     k_sweep<float, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
-    k_wall_sums<<<1, TB, 0, s>>>(z, n, nx, L, hv, wall);
+    k_wall_sums<<<1, TBW, 0, s>>>(z, n, nx, L, hv, wall);
     k_sweep<float, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
   } else {
     const double* q = static_cast<const double*>(nu);
     k_sweep<double, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
-    k_wall_sums<<<1, TB, 0, s>>>(z, n, nx, L, hv, wall);
+    k_wall_sums<<<1, TBW, 0, s>>>(z, n, nx, L, hv, wall);
     k_sweep<double, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
   }
   return hipGetLastError();
