@@ -31,7 +31,13 @@ def gpu_q(n, L, om, f, polar=8, azim=16):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("n,L,om,polar,azim", [(8, 4.0, 1.0, 8, 16), (16, 8.0, 0.74, 8, 16), (16, 8.0, 0.5, 6, 10)])
+# The kernel shares the first-axis transform between azimuths m and
+# n_azim - m: odd counts (one unpaired azimuth), one and two azimuths (no
+# pairs) and n = 32 (where the c/d exchange is a wave-half swap) are covered.
+@pytest.mark.parametrize("n,L,om,polar,azim", [
+    (8, 4.0, 1.0, 8, 16), (16, 8.0, 0.74, 8, 16), (16, 8.0, 0.5, 6, 10),
+    (8, 4.0, 1.0, 6, 7), (16, 8.0, 0.74, 4, 1), (16, 8.0, 0.74, 4, 2), (16, 8.0, 0.74, 4, 9),
+    (32, 8.0, 0.74, 4, 5), (32, 8.0, 0.74, 4, 6)])
 def test_quadcoll_matches_binary_oracle(n, L, om, polar, azim):
     h, params = mixed_inputs(n, L, 3, seed=1600 + n + polar)
     f = h + np.stack([wl.maxwellian(n, L, q[0], q[1:4], q[4]) for q in params])
