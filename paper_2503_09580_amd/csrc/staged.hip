@@ -106,8 +106,8 @@ __global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, double2
 // inverse and forward transforms): per pair of columns (x, y) and
 // (x, y + n/2), inverse real transform along z, multiply by M^h, forward
 // real transform, in place on W.
-template <typename TS, typename T, int NN>
-__global__ void __launch_bounds__(128) k_z_mid(const double2* __restrict__ W, typename V2<TS>::t* __restrict__ Wq,
+template <typename TS, typename T, int NN, typename TW>
+__global__ void __launch_bounds__(128) k_z_mid(const typename V2<TW>::t* __restrict__ W, typename V2<TS>::t* __restrict__ Wq,
                                                 const TS* __restrict__ fac, const TS* __restrict__ pref, int Bc,
                                                 int batch) {
   using C = typename V2<TS>::t;
@@ -124,8 +124,8 @@ __global__ void __launch_bounds__(128) k_z_mid(const double2* __restrict__ W, ty
   const size_t b2 = b1 + NN / 2;
   T Ar[P], Ai[P], Br[P], Bi[P];
   static_for<0, P>([&](auto k) {
-    const double2 a = W[b1 + (size_t)k * NP];
-    const double2 b = W[b2 + (size_t)k * NP];
+    const auto a = W[b1 + (size_t)k * NP];
+    const auto b = W[b2 + (size_t)k * NP];
     Ar[k] = T(a.x); Ai[k] = T(a.y); Br[k] = T(b.x); Bi[k] = T(b.y);
   });
   T zr[NN], zi[NN];
@@ -325,10 +325,17 @@ static hipError_t apply_n(const ApplyCtx& c) {
   const TS* Kh = static_cast<const TS*>(c.Kh);
   const TS* Phi = static_cast<const TS*>(c.Phi);
   const TS* Om = static_cast<const TS*>(c.Om);
-  // r-derived spectra (R, and W before the product with M^h) are kept in
-  // double for every dtype; H, W after the product and L+ use TS.
+  // r-derived spectra are transformed in double for every dtype; R is stored
+  // in double, W as below; H, W after the product and L+ use TS.
   double2* R = static_cast<double2*>(c.R);
   double2* W = static_cast<double2*>(c.W);
+  // W between the in-plane and z passes of a node is stored in the storage
+  // precision up to n = 32 (FP32 staged C3: 20.8 -> 17.2 ms at an unchanged
+  // error); at n = 64 the float copy measured slower (41.4 -> 44.0 ms), so it
+  // stays double there.
+  using TW = std::conditional_t<NN == 64, double, TS>;
+  using CW = typename V2<TW>::t;
+  CW* WS = static_cast<CW*>(c.W);
   Cx* H = static_cast<Cx*>(c.H);
   Cx* Wq = static_cast<Cx*>(c.Wq);
   Cx* Lp = static_cast<Cx*>(c.Lp);
@@ -345,9 +352,9 @@ static hipError_t apply_n(const ApplyCtx& c) {
   using TF = TS;
   k_plane<TS, TS, TS, TF, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
   for (int j = 0; j < c.J; ++j) {
-    k_plane<double, double, TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, W, Kh, nullptr, c.J, j, c.Bc,
-                                                                            nplanes, 1);
-    k_z_mid<TS, T, NN><<<gz2, 128, 0, c.stream>>>(W, Wq, fac, pref, c.Bc, B);
+    k_plane<double, TW, TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, WS, Kh, nullptr, c.J, j, c.Bc,
+                                                                        nplanes, 1);
+    k_z_mid<TS, T, NN, TW><<<gz2, 128, 0, c.stream>>>(WS, Wq, fac, pref, c.Bc, B);
     if constexpr (std::is_same<TS, float>::value && (NN == 32 || NN == 64)) {
       if (c.dtype == 2) {   // BF16x3: the forward in-plane DFT stages on the matrix cores
         hipError_t e = plane_fwd_bf16x3(NN, reinterpret_cast<const float2*>(Wq), reinterpret_cast<float2*>(Lp), Phi,
