@@ -240,6 +240,31 @@ def test_abi_errors_on_device():
     assert plan.info("maxw_batch") == 3
 
 
+def test_empty_and_oversized_batches_are_rejected():
+    """An empty batch is an argument error (LINCOLL_EINVAL) for apply,
+    project and quadcoll, through the C ABI with valid pointers and through
+    the binding with a zero-length tensor; so is a batch above the plan's
+    max_batch.  The output is left untouched."""
+    import ctypes
+    n, L, om = 8, 4.0, 1.0
+    lib = lc.library()
+    plan = lc.Plan(n, L, om, "f64", max_batch=2)
+    plan.set_maxwellians(torch.tensor([[1, 0, 0, 0, 1.0]], dtype=torch.float64, device=DEV))
+    x = torch.ones((3, n, n, n), dtype=torch.float64, device=DEV)
+    y = torch.full_like(x, 7.0)
+    px, py = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    for fn in (lib.lincoll_apply, lib.lincoll_project, lib.quadcoll_apply):
+        assert fn(plan._h, px, py, 0) == lc.EINVAL
+        assert fn(plan._h, px, py, -1) == lc.EINVAL
+    assert lib.lincoll_apply(plan._h, px, py, 3) == lc.EINVAL        # above max_batch
+    assert lib.lincoll_apply(plan._h, px, py, 2) == lc.OK
+    torch.cuda.synchronize()
+    assert torch.all(y[2] == 7.0)
+    with pytest.raises(lc.LincollError) as err:
+        plan.apply(torch.empty((0, n, n, n), dtype=torch.float64, device=DEV))
+    assert err.value.status == lc.EINVAL
+
+
 @pytest.mark.parametrize("n,L", [(16, 8.0), (32, 8.0)])
 def test_fp32_fused_and_staged_match_oracle(n, L):
     """Both FP32 paths (the fused per-cell kernel and the staged kernels)
