@@ -59,7 +59,7 @@ typedef enum {
 } lincoll_path_t;
 
 typedef struct {
-  int n;            /* points per velocity axis (the paper's 2N): 8, 16, 32 (F64) or 8..64 (F32) */
+  int n;            /* points per velocity axis (the paper's 2N): 8, 16, 32 or 64 (BF16X3: 32, 64) */
   double L;         /* half-width of the periodic velocity box, > 0 */
   double omega;     /* VHS viscosity index, 1/2 <= omega <= 1 (eq. (4)) */
   double C;         /* kernel constant of B(g) = C g^(2(1-omega)); default 1/(4 pi) (eq. (26)) */
@@ -95,7 +95,9 @@ int lincoll_set_maxwellians(lincoll_plan_t plan, const double* params, int batch
 
 /* out[b] = L[h[b]] about Maxwellian b (or the broadcast one) for b < batch
  * (eq. (20) + eq. (23), Algorithm 1).  h and out must not overlap.
- * batch must equal the Maxwellian batch or the Maxwellian batch must be 1. */
+ * batch >= 1 and, when the plan sets max_batch, batch <= max_batch (else
+ * LINCOLL_EINVAL, nothing enqueued); batch must equal the Maxwellian batch or
+ * the Maxwellian batch must be 1 (else LINCOLL_ENOTREADY). */
 int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
 
 /* y[b] = P x[b]: removes the collision-invariant part in the inner product
