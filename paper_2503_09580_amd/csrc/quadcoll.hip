@@ -214,12 +214,14 @@ __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ 
   constexpr int NP = NN * NN, LD = NN + 1, H = NN / 2;
   constexpr bool SWAP = NN == 32;      // c and d on the two halves of one wave
   __shared__ double2 Ub[2][NN * LD];   // first-axis transforms of c and d, transposed
-  __shared__ double2 E[2][NN];         // exp(i alpha sx p1), exp(i alpha sy p2) of the current pair
+  // exp(i alpha sx p1) and its conjugate, exp(i alpha sy p2) and its
+  // conjugate, for the current pair: each lane picks a table instead of
+  // multiplying by a sign
+  __shared__ double2 E[4][NN];
   const int half = threadIdx.x / NN, a = threadIdx.x % NN;
   const long pid = blockIdx.x;
   double2* ub = Ub[half];
   const double2* src = (half == 0 ? Gp : Gm) + pid * NP + a;
-  const double sg = half == 0 ? 1.0 : -1.0;        // c: exp(+i a.p), d: exp(-i a.p)
   const double dsign = SWAP || half == 0 ? 1.0 : -1.0;   // shuffle form, d: (-1)^p2 on the odd p2
   double sacc[H], vr[NN], vi[NN];
   static_for<0, H>([&](auto x) { sacc[x] = 0.0; });
@@ -231,15 +233,16 @@ __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ 
       const double sc = half == 0 ? st * cos(ph) : st * sin(ph);
       double sn, cs;
       sincos(alpha * sc * sgn_idx<NN>(a), &sn, &cs);
-      E[half][a] = double2{cs, sn};
+      E[2 * half][a] = double2{cs, sn};
+      E[2 * half + 1][a] = double2{cs, -sn};
     }
     __syncthreads();
+    const double2* e1 = E[half];   // c: exp(+i alpha sx p1), d: its conjugate
     static_for<0, NN>([&](auto k1) {
       const double2 v = src[(size_t)k1 * NN];
-      const double2 e = E[0][k1];
-      const double ei = sg * e.y;
-      vr[k1] = v.x * e.x - v.y * ei;
-      vi[k1] = v.x * ei + v.y * e.x;
+      const double2 e = e1[k1];
+      vr[k1] = v.x * e.x - v.y * e.y;
+      vi[k1] = v.x * e.y + v.y * e.x;
     });
     fft<NN, true>(vr, vi);
     static_for<0, NN>([&](auto k1) { ub[k1 * LD + a] = double2{vr[k1], vi[k1]}; });
@@ -249,12 +252,13 @@ __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ 
       // read the row and the phases again for the second azimuth rather than
       // keeping 2 NN complex values live across the loop
       asm volatile("" ::: "memory");
-      const double si = t == 0 ? sg : -sg;         // sign of the sy phase: azimuth m, then nazim - m
+      // the sy phase: c exp(+i ..) at azimuth m and exp(-i ..) at nazim - m, d the reverse
+      const double2* e2 = E[2 + (half ^ t)];
       static_for<0, NN>([&](auto k2) {
         const double2 v = ub[a * LD + k2];
-        const double2 e = E[1][k2];
-        double er = e.x, ei = si * e.y;
-        if constexpr (k2 % 2 == 1) {
+        const double2 e = e2[k2];
+        double er = e.x, ei = e.y;
+        if constexpr (!SWAP && k2 % 2 == 1) {
           er *= dsign;
           ei *= dsign;
         }
@@ -267,19 +271,22 @@ __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ 
           double xr = vr[k], yr = vr[H + k], xi = vi[k], yi = vi[H + k];
           swap_wave_halves(xr, yr);
           swap_wave_halves(xi, yi);
-          sacc[k] += w * (xr * yr - xi * yi);
+          sacc[k] = fma(xr, yr, sacc[k]);
+          sacc[k] = fma(-xi, yi, sacc[k]);
         });
       } else {
         static_for<0, H>([&](auto k) {
           const double rr = __shfl_xor(vr[H + k], NN, 2 * NN), ri = __shfl_xor(vi[H + k], NN, 2 * NN);
-          sacc[k] += w * (vr[k] * rr - vi[k] * ri);
+          sacc[k] = fma(vr[k], rr, sacc[k]);
+          sacc[k] = fma(-vi[k], ri, sacc[k]);
         });
       }
     }
     __syncthreads();   // ub and E are rewritten for the next pair
   }
-  // S[x1 = a][x2 = half H + k] -> LDS, then column-wise coalesced stores
-  static_for<0, H>([&](auto k) { Ub[0][a * LD + half * H + k] = double2{sacc[k], 0.0}; });
+  // S[x1 = a][x2 = half H + k] (times the weight, constant over the loop) ->
+  // LDS, then column-wise coalesced stores
+  static_for<0, H>([&](auto k) { Ub[0][a * LD + half * H + k] = double2{w * sacc[k], 0.0}; });
   __syncthreads();
   double2* dst = S + pid * NP + a;
   static_for<0, H>([&](auto r) {
