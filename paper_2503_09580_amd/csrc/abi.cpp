@@ -80,6 +80,8 @@ struct lincoll_plan_s {
   double* d_Ws = nullptr;
   double* d_qV = nullptr;
   double2 *d_qF = nullptr, *d_qGp = nullptr, *d_qGm = nullptr, *d_qC = nullptr, *d_qS = nullptr, *d_qQ = nullptr;
+  double2* d_qPh = nullptr;   // azimuth phase tables of the hemisphere rule
+  long cap_qph = 0;           // complex values held by d_qPh
 };
 
 namespace {
@@ -639,6 +641,11 @@ int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
       return hip_fail(pl, e);
     pl->cap_qc = batch;
   }
+  const long nph = quadcoll_phase_count(n, (int)mu.size(), pl->sphere_azim);
+  if (nph > pl->cap_qph) {
+    if ((e = dalloc(pl, &pl->d_qPh, (size_t)nph * sizeof(double2)))) return hip_fail(pl, e);
+    pl->cap_qph = nph;
+  }
   std::vector<double> st(mu.size());
   for (size_t i = 0; i < mu.size(); ++i) st[i] = std::sqrt(1.0 - mu[i] * mu[i]);
   QuadCtx c;
@@ -665,6 +672,7 @@ int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
   c.wpolar = wmu.data();
   c.npolar = (int)mu.size();
   c.nazim = pl->sphere_azim;
+  c.phase = pl->d_qPh;
   if ((e = quadcoll_apply_fp64(c))) return hip_fail(pl, e);
   return LINCOLL_OK;
 }
@@ -788,7 +796,7 @@ void lincoll_destroy(lincoll_plan_t pl) {
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
                   pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin,
                   pl->d_rk_k, pl->d_rk_tmp, pl->d_rk_acc, pl->d_Ws, pl->d_qV, pl->d_qF, pl->d_qGp,
-                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ};
+                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ, pl->d_qPh};
   for (void* p : ptrs) dfree(p);
   delete pl;
 }

@@ -102,7 +102,10 @@ struct QuadCtx {
   const double* st = nullptr;    // host [npolar] sqrt(1 - mu^2)
   const double* wpolar = nullptr;   // host [npolar] polar weights
   int npolar = 0, nazim = 0;
+  double2* phase = nullptr;      // [npolar][nazim/2+1][4][n] phase tables of one g-node (quadcoll_phase_count)
 };
+// complex values of the phase tables of QuadCtx::phase
+inline long quadcoll_phase_count(int n, int npolar, int nazim) { return (long)npolar * (nazim / 2 + 1) * 4 * n; }
 bool quadcoll_supported(int n);
 hipError_t quadcoll_apply_fp64(const QuadCtx& c);
 

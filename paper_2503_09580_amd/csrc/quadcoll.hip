@@ -197,6 +197,29 @@ __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in,
 // by (-1)^p2, which shifts their output by NN/2 along x2, so that every lane
 // keeps registers [0, NN/2) and sends [NN/2, NN) to its partner.  Either way
 // lane a accumulates S[a][x2 < NN/2] and lane a + NN S[a][x2 >= NN/2].
+// Phase tables of one g-node for k_qc_azim, one block of 2 NN threads per
+// (polar cosine i, azimuth pair m): exp(i alpha sx p1) and its conjugate
+// (lanes [0, NN), p1 = lane) and exp(i alpha sy p2) and its conjugate
+// (lanes [NN, 2 NN), p2 = lane - NN), with (sx, sy) = sin(polar) (cos, sin)
+// of azimuth m.  Layout [i][m][4][NN].
+struct PolarSines {
+  double v[32];
+};
+
+template <int NN>
+__global__ void __launch_bounds__(2 * NN) k_qc_phases(double2* __restrict__ tab, double alpha, PolarSines st,
+                                                       int nazim, int npair) {
+  const int i = blockIdx.x / npair, m = blockIdx.x % npair;
+  const int half = threadIdx.x / NN, a = threadIdx.x % NN;
+  const double ph = 2.0 * M_PI * m / nazim;
+  const double sc = half == 0 ? st.v[i] * cos(ph) : st.v[i] * sin(ph);
+  double sn, cs;
+  sincos(alpha * sc * sgn_idx<NN>(a), &sn, &cs);
+  double2* t = tab + (size_t)blockIdx.x * 4 * NN;
+  t[2 * half * NN + a] = double2{cs, sn};
+  t[(2 * half + 1) * NN + a] = double2{cs, -sn};
+}
+
 __device__ __forceinline__ void swap_wave_halves(double& x, double& y) {
   // lanes 32..63 of x <-> lanes 0..31 of y
   const unsigned long long xb = __builtin_bit_cast(unsigned long long, x);
@@ -209,14 +232,14 @@ __device__ __forceinline__ void swap_wave_halves(double& x, double& y) {
 
 template <int NN>
 __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ Gp, const double2* __restrict__ Gm,
-                                                     double2* __restrict__ S, double alpha, double st, double w,
-                                                     int nazim, int first) {
+                                                     double2* __restrict__ S, const double2* __restrict__ tab,
+                                                     double w, int nazim, int first) {
   constexpr int NP = NN * NN, LD = NN + 1, H = NN / 2;
   constexpr bool SWAP = NN == 32;      // c and d on the two halves of one wave
   __shared__ double2 Ub[2][NN * LD];   // first-axis transforms of c and d, transposed
   // exp(i alpha sx p1) and its conjugate, exp(i alpha sy p2) and its
-  // conjugate, for the current pair: each lane picks a table instead of
-  // multiplying by a sign
+  // conjugate, for the current pair (from the k_qc_phases tables): each lane
+  // picks a table instead of multiplying by a sign
   __shared__ double2 E[4][NN];
   const int half = threadIdx.x / NN, a = threadIdx.x % NN;
   const long pid = blockIdx.x;
@@ -225,16 +248,18 @@ __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ 
   const double dsign = SWAP || half == 0 ? 1.0 : -1.0;   // shuffle form, d: (-1)^p2 on the odd p2
   double sacc[H], vr[NN], vi[NN];
   static_for<0, H>([&](auto x) { sacc[x] = 0.0; });
+  // the 4 NN table entries of a pair, two per lane; the next pair's are
+  // loaded while the current one is processed
+  double2* Ef = &E[0][0];
+  const int npair = nazim / 2 + 1;
+  double2 t0 = tab[threadIdx.x], t1 = tab[threadIdx.x + 2 * NN];
   for (int m = 0; 2 * m <= nazim; ++m) {
     const bool pair = m > 0 && 2 * m < nazim;      // azimuth nazim - m shares sx
-    const double ph = 2.0 * M_PI * m / nazim;
-    {
-      // lanes [0, NN): the sx phase of p1 = lane; lanes [NN, 2 NN): the sy phase of p2 = lane - NN
-      const double sc = half == 0 ? st * cos(ph) : st * sin(ph);
-      double sn, cs;
-      sincos(alpha * sc * sgn_idx<NN>(a), &sn, &cs);
-      E[2 * half][a] = double2{cs, sn};
-      E[2 * half + 1][a] = double2{cs, -sn};
+    Ef[threadIdx.x] = t0;
+    Ef[threadIdx.x + 2 * NN] = t1;
+    if (m + 1 < npair) {
+      t0 = tab[(size_t)(m + 1) * 4 * NN + threadIdx.x];
+      t1 = tab[(size_t)(m + 1) * 4 * NN + threadIdx.x + 2 * NN];
     }
     __syncthreads();
     const double2* e1 = E[half];   // c: exp(+i alpha sx p1), d: its conjugate
@@ -309,12 +334,18 @@ hipError_t quadcoll_n(const QuadCtx& c) {
   // loss: V = Re iDFT_u[Omega_u F] (into the output buffer's shadow V)
   k_qc_plane<NN, 2><<<gp, 64, 0, s>>>(Fk, C, c.Om64, nplanes);
   k_qc_col<NN, 3><<<gc, 128, 0, s>>>(C, nullptr, nullptr, nullptr, c.V, nullptr, nullptr, 0, 0, 0, 0, 0, B);
+  if (c.npolar < 1 || c.npolar > 32 || c.nazim < 1 || !c.phase) return hipErrorInvalidValue;
+  const int npair = c.nazim / 2 + 1;
+  PolarSines sines{};
+  for (int i = 0; i < c.npolar; ++i) sines.v[i] = c.st[i];
   for (int j = 0; j < c.J; ++j) {
     const double alpha = M_PI * c.g[j] / (2.0 * c.L);
+    k_qc_phases<NN><<<c.npolar * npair, 2 * NN, 0, s>>>(c.phase, alpha, sines, c.nazim, npair);
     for (int i = 0; i < c.npolar; ++i) {
-      const double mu = c.mu[i], st = c.st[i];
+      const double mu = c.mu[i];
       k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gp, Gm, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, 0, B);
-      k_qc_azim<NN><<<nplanes, 2 * NN, 0, s>>>(Gp, Gm, S, alpha, st, c.wpolar[i] / c.nazim, c.nazim, i == 0);
+      k_qc_azim<NN><<<nplanes, 2 * NN, 0, s>>>(Gp, Gm, S, c.phase + (size_t)i * npair * 4 * NN,
+                                                 c.wpolar[i] / c.nazim, c.nazim, i == 0);
     }
     // Qk (+)= W_j s_j DFT3[S_j]
     k_qc_plane<NN, 1><<<gp, 64, 0, s>>>(S, S, nullptr, nplanes);
