@@ -22,6 +22,8 @@
 // [cell][plane][a][b] with the plane index the z (or k_z) axis.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "fft.h"
 #include "internal.h"
 
@@ -46,12 +48,19 @@ __device__ __forceinline__ int fold_q(int k) { return k <= NN / 2 ? k : NN - k; 
 // MODE 3: inverse along kz; out real part to res[cell][e][z] (physical).
 // MODE 4: inverse along kz; final combine into out[cell][e][z]:
 //         16 pi^2 / n^3 Re(q) - f * V   (V from MODE 3).
+// exp(i alpha mu p_z) for the MODE 1 pass, p_z = signed index of the plane:
+// the same for every column, so it travels as a kernel argument (uniform
+// across the wave) rather than being evaluated per thread.
+struct ZPhase {
+  double2 e[32];
+};
+
 template <int NN, int MODE>
 __global__ void __launch_bounds__(128) k_qc_col(const double2* __restrict__ in, double2* __restrict__ cout,
                                                  double2* __restrict__ cout2, const double* __restrict__ f,
                                                  double* __restrict__ res, const double* __restrict__ V,
-                                                 const double* __restrict__ Ws, int Q, int j, double alpha,
-                                                 double mu, int first, int batch) {
+                                                 const double* __restrict__ Ws, int Q, int j, ZPhase zp,
+                                                 int first, int batch) {
   constexpr int NP = NN * NN;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long)batch * NP) return;
@@ -65,8 +74,7 @@ __global__ void __launch_bounds__(128) k_qc_col(const double2* __restrict__ in, 
       const double sign = pass == 0 ? 1.0 : -1.0;
       static_for<0, NN>([&](auto p) {
         const double2 v = src[(size_t)p * NP];
-        double sn, cs;
-        sincos(sign * alpha * mu * sgn_idx<NN>(p), &sn, &cs);
+        const double cs = zp.e[p].x, sn = sign * zp.e[p].y;
         vr[p] = (v.x * cs - v.y * sn) * s3;
         vi[p] = (v.x * sn + v.y * cs) * s3;
       });
@@ -329,11 +337,11 @@ hipError_t quadcoll_n(const QuadCtx& c) {
   double2 *Fk = c.Fk, *Gp = c.Gp, *Gm = c.Gm, *C = c.C, *S = c.S, *Qk = c.Qk;
   hipStream_t s = c.stream;
   // F = DFT3[f]: along z, then in-plane
-  k_qc_col<NN, 0><<<gc, 128, 0, s>>>(nullptr, Fk, nullptr, c.f, nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, B);
+  k_qc_col<NN, 0><<<gc, 128, 0, s>>>(nullptr, Fk, nullptr, c.f, nullptr, nullptr, nullptr, 0, 0, ZPhase{}, 0, B);
   k_qc_plane<NN, 0><<<gp, 64, 0, s>>>(Fk, Fk, nullptr, nplanes);
   // loss: V = Re iDFT_u[Omega_u F] (into the output buffer's shadow V)
   k_qc_plane<NN, 2><<<gp, 64, 0, s>>>(Fk, C, c.Om64, nplanes);
-  k_qc_col<NN, 3><<<gc, 128, 0, s>>>(C, nullptr, nullptr, nullptr, c.V, nullptr, nullptr, 0, 0, 0, 0, 0, B);
+  k_qc_col<NN, 3><<<gc, 128, 0, s>>>(C, nullptr, nullptr, nullptr, c.V, nullptr, nullptr, 0, 0, ZPhase{}, 0, B);
   if (c.npolar < 1 || c.npolar > 32 || c.nazim < 1 || !c.phase) return hipErrorInvalidValue;
   const int npair = c.nazim / 2 + 1;
   PolarSines sines{};
@@ -342,18 +350,22 @@ hipError_t quadcoll_n(const QuadCtx& c) {
     const double alpha = M_PI * c.g[j] / (2.0 * c.L);
     k_qc_phases<NN><<<c.npolar * npair, 2 * NN, 0, s>>>(c.phase, alpha, sines, c.nazim, npair);
     for (int i = 0; i < c.npolar; ++i) {
-      const double mu = c.mu[i];
-      k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gp, Gm, nullptr, nullptr, nullptr, nullptr, 0, 0, alpha, mu, 0, B);
+      ZPhase zp{};
+      for (int p = 0; p < NN; ++p) {
+        const double a = alpha * c.mu[i] * (p < NN / 2 ? p : p - NN);
+        zp.e[p] = double2{std::cos(a), std::sin(a)};
+      }
+      k_qc_col<NN, 1><<<gc, 128, 0, s>>>(Fk, Gp, Gm, nullptr, nullptr, nullptr, nullptr, 0, 0, zp, 0, B);
       k_qc_azim<NN><<<nplanes, 2 * NN, 0, s>>>(Gp, Gm, S, c.phase + (size_t)i * npair * 4 * NN,
                                                  c.wpolar[i] / c.nazim, c.nazim, i == 0);
     }
     // Qk (+)= W_j s_j DFT3[S_j]
     k_qc_plane<NN, 1><<<gp, 64, 0, s>>>(S, S, nullptr, nplanes);
-    k_qc_col<NN, 2><<<gc, 128, 0, s>>>(S, Qk, nullptr, nullptr, nullptr, nullptr, c.Ws, c.Q, j, 0, 0, j == 0, B);
+    k_qc_col<NN, 2><<<gc, 128, 0, s>>>(S, Qk, nullptr, nullptr, nullptr, nullptr, c.Ws, c.Q, j, ZPhase{}, j == 0, B);
   }
   // Q = 16 pi^2 / n^3 Re iDFT_u[Qk] - f V
   k_qc_plane<NN, 3><<<gp, 64, 0, s>>>(Qk, Qk, nullptr, nplanes);
-  k_qc_col<NN, 4><<<gc, 128, 0, s>>>(Qk, nullptr, nullptr, c.f, c.out, c.V, nullptr, 0, 0, 0, 0, 0, B);
+  k_qc_col<NN, 4><<<gc, 128, 0, s>>>(Qk, nullptr, nullptr, c.f, c.out, c.V, nullptr, 0, 0, ZPhase{}, 0, B);
   return hipGetLastError();
 }
 
