@@ -49,6 +49,26 @@ def test_quadcoll_matches_binary_oracle(n, L, om, polar, azim):
         assert rel(got[b], ref) <= 1e-12, (b, rel(got[b], ref))
 
 
+def test_hemisphere_rule_changes_between_calls():
+    """One plan, successive calls with different hemisphere rules: the
+    azimuth phase tables grow (reallocation) and shrink (reuse) with the
+    rule, and every call matches the oracle at 1e-12."""
+    n, L, om = 8, 4.0, 1.0
+    h, params = mixed_inputs(n, L, 2, seed=1650)
+    f = h + np.stack([wl.maxwellian(n, L, q[0], q[1:4], q[4]) for q in params])
+    plan = lc.Plan(n, L, om, "f64")
+    fd_plan = fd.make_plan(n, L, om)
+    fdev = torch.from_numpy(np.ascontiguousarray(f)).to(DEV, torch.float64)
+    for polar, azim in [(4, 6), (8, 16), (4, 5), (10, 24), (2, 1)]:
+        plan.set_option("sphere_polar", polar)
+        plan.set_option("sphere_azimuth", azim)
+        got = plan.quadcoll(fdev).cpu().numpy()
+        sphere = quadrature.hemisphere_product_rule(polar, azim)
+        for b in range(2):
+            ref = binary.q_binary(fd_plan, sphere, f[b], f[b], method="fast")
+            assert rel(got[b], ref) <= 1e-12, (polar, azim, b, rel(got[b], ref))
+
+
 def test_polarisation_gives_the_linearized_binary_operator():
     n, L, om = 16, 8.0, 0.74
     M = wl.maxwellian(n, L, 1.0, (0, 0, 0), 1.0)
