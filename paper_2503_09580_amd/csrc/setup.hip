@@ -218,7 +218,7 @@ hipError_t setup_cells(const SetupCtx& c) {
 
 // ------------------------------------------------------------ projection
 // y = x - M sum_a phi_a (A^-1 m[x])_a per cell; moments reduced in FP64.
-constexpr int PROJ_TB = 512;
+constexpr int PROJ_TB = 1024;
 
 // One block per cell: the five moments of x (FP64 sums in a fixed tree), the
 // coefficients A^-1 m, then y = x - M sum_a coef_a phi_a.  n is a power of

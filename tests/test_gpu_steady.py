@@ -238,7 +238,12 @@ def test_checkpoint_and_resume(tmp_path):
     g = torch.from_numpy(np.load(tmp_path / "state.npy")).to(DEV)
     rest = plan.steady_solve(lc.steady_params(nx, init=0, **kw), g)
     assert rest["converged"] and rest["newton_iters"] == full["newton_iters"] - 1
-    assert np.allclose(rest["res_history"], full["res_history"][1:], rtol=1e-9, atol=0)
+    # the resumed run rescales the saved state to the mass once more (a change
+    # of order 1e-16), and the residual norm is a difference of O(1) terms:
+    # the histories agree to 1e-9 relative above an absolute floor of 1e-12
+    # of the first residual
+    print("full", full["res_history"], "resumed", rest["res_history"])
+    assert np.allclose(rest["res_history"], full["res_history"][1:], rtol=1e-9, atol=1e-12 * full["res_history"][0])
     assert np.max(np.abs(g.cpu().numpy() - f_full)) <= 1e-12 * np.max(np.abs(f_full))
 
 
