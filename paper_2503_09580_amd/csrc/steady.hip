@@ -52,10 +52,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 __global__ void __launch_bounds__(TB) k_cell_sums(const double* __restrict__ f, int n, double L, double hv,
                                                   double* __restrict__ sums) {
   const long n3 = (long)n * n * n;
+  const int lgn = 31 - __builtin_clz(n), msk = n - 1;   // n is a power of two
   const double* x = f + (long)blockIdx.x * n3;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   for (long e = threadIdx.x; e < n3; e += TB) {
-    const int i1 = (int)(e / ((long)n * n)), i2 = (int)((e / n) % n), i3 = (int)(e % n);
+    const int i1 = (int)(e >> (2 * lgn)), i2 = (int)(e >> lgn) & msk, i3 = (int)e & msk;
     const double v1 = -L + i1 * hv, v2 = -L + i2 * hv, v3 = -L + i3 * hv, y = x[e];
     v[0] += y;
     v[1] += v1 * y;
@@ -130,9 +131,11 @@ __global__ void __launch_bounds__(TB) k_transport(const double* __restrict__ x, 
                                                   const double* __restrict__ ysums, double* __restrict__ out, int n,
                                                   int nx, double L, double hv, double dx) {
   const long n3 = (long)n * n * n, total = (long)nx * n3;
+  const int lgn = 31 - __builtin_clz(n), msk = n - 1;   // n is a power of two
+  const double rdx = 1.0 / dx;
   for (long idx = (long)blockIdx.x * TB + threadIdx.x; idx < total; idx += (long)gridDim.x * TB) {
-    const long c = idx / n3, e = idx - c * n3;
-    const int i1 = (int)(e / ((long)n * n)), i2 = (int)((e / n) % n), i3 = (int)(e % n);
+    const long c = idx >> (3 * lgn), e = idx & (n3 - 1);
+    const int i1 = (int)(e >> (2 * lgn)), i2 = (int)(e >> lgn) & msk, i3 = (int)e & msk;
     const double v1 = -L + i1 * hv;
     const double xc = x[idx];
     double t = 0.0;
@@ -144,7 +147,7 @@ __global__ void __launch_bounds__(TB) k_transport(const double* __restrict__ x, 
         const double rho = -wall[0] / wg.flux_in[0];
         nb = rho * wall_shape(v1, -L + i2 * hv, -L + i3 * hv, wg, 0);
       }
-      t = v1 * (xc - nb) / dx;
+      t = v1 * (xc - nb) * rdx;
     } else if (v1 < 0.0) {
       double nb;
       if (c < nx - 1) {
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(TB) k_transport(const double* __restrict__ x, 
         const double rho = -wall[1] / wg.flux_in[1];
         nb = rho * wall_shape(v1, -L + i2 * hv, -L + i3 * hv, wg, 1);
       }
-      t = v1 * (nb - xc) / dx;
+      t = v1 * (nb - xc) * rdx;
     }
     if (y) {
       const double m = ysums ? ysums[c * SUMS_STRIDE] / (double)n3 : 0.0;
