@@ -52,7 +52,9 @@ def busy_work():
 
 
 @pytest.mark.parametrize("n,dtype,path,batch", [(16, "f64", "staged", 5), (32, "f32", "fused", 9),
-                                                (32, "f32", "staged", 4), (16, "f32", "fused", 11)])
+                                                (32, "f32", "staged", 4), (16, "f32", "fused", 11),
+                                                (32, "bf16x3", "staged", 3), (64, "f32", "staged", 2),
+                                                (64, "bf16x3", "staged", 2)])
 def test_graph_replay_is_bitwise_eager(n, dtype, path, batch):
     L, om = 8.0, 0.74
     td = torch.float64 if dtype == "f64" else torch.float32
