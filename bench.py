@@ -247,7 +247,7 @@ def bench_rk4(a, torch, lincoll, dev):
 
 
 def bench_steady(a, torch, lincoll, dev):
-    """Newton solve wall-time of the steady 1-D heat-transfer problem (Sec. 5.2,
+    """Newton solve wall-time of the steady 1-D heat-transfer problem (Sec. 5.3.2,
     Fourier flow; scheme of Appendix B): 256 cells on [-0.5, 0.5], walls at
     temperature 1 and 1.5, Kn = 0.1, mass 1, n = 32, box [-8,8)^3,
     VHS omega = 0.74; residuals by quadcoll_apply (FP64), Newton operator with
@@ -357,7 +357,7 @@ PAPER_TABLE7 = {0.1: {0.1: 174.8, 1.0: 127.1, 10.0: 121.6}, 0.2: {0.1: 242.3, 1.
 
 
 def bench_couette(a, torch, lincoll, dev):
-    """The paper's Couette flow (Sec. 5.2; walls at -+u_W, theta = 1): 200
+    """The paper's Couette flow (Sec. 5.3.1; walls at -+u_W, theta = 1): 200
     cells on [-0.5, 0.5], n = 32, Maxwell molecules, R = 3.5 and
     L = (3 + sqrt 2) R / 4, mass 1, Newton tolerance 1e-5, inner 1e-3 / 1e-7.
     A step is one whole solve from the initial guess of eq. (initial)."""

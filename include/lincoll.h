@@ -85,8 +85,9 @@ int lincoll_plan_ex(const lincoll_params_t* p, lincoll_plan_t* out);
 /* Sets the HIP stream (a hipStream_t passed as void*) for all later calls. */
 int lincoll_set_stream(lincoll_plan_t plan, void* hip_stream);
 
-/* Per-cell Maxwellians (Algorithm 1, first loop; Sec. 5.2 uses one local
- * Maxwellian per spatial cell).  params: device double [batch][5].  Computes
+/* Per-cell Maxwellians (Algorithm 1, first loop; the modified Newton
+ * operator of Sec. 5.2, eq. (modified_lin_eq), uses one local Maxwellian per
+ * spatial cell).  params: device double [batch][5].  Computes
  * in FP64 on the device: the cutoff mask, the kernel modes
  * K_j = DFT[G phi_j] with G = rho (pi theta)^(-3/2) exp(-|v|^2/theta) (eq. (24)),
  * nu = iDFT[Omega DFT[M]] (eq. (20)) and the invariant Gram matrix.  batch = 1
@@ -220,7 +221,7 @@ typedef struct {
   double u_l[3], u_r[3];    /* wall velocities (default 0) */
   double tol;               /* Newton stops when the residual norm < tol (default 1e-5) */
   double inner_rtol;        /* inner stop: residual <= inner_rtol * |r| ... (default 1e-3) */
-  double inner_atol;        /* ... or <= min(inner_atol, tol / 100) (default 1e-7) (Sec. 5.2) */
+  double inner_atol;        /* ... or <= min(inner_atol, tol / 100) (default 1e-7) (Sec. 5.3) */
   int max_newton;           /* Newton steps, >= 0 (default 30) */
   int max_inner;            /* inner iterations per Newton step, >= 1 (default 2000) */
   int restart;              /* GMRES cycle length, 1..64 (default 30) */
@@ -237,7 +238,7 @@ typedef struct {
 
 typedef enum {
   LINCOLL_INNER_GMRES = 0,   /* restarted flexible GMRES with sp->precond */
-  LINCOLL_INNER_SOURCE = 1   /* source iteration (Sec. 5.1, eq. (source_iteration)): g <- g + M^-1 (r - A g)
+  LINCOLL_INNER_SOURCE = 1   /* source iteration (Sec. 5.2, eq. (source_iteration)): g <- g + M^-1 (r - A g)
                                 from g = 0 with M^-1 the zero-mass sweep, i.e. (T + nu/Kn) g' =
                                 (P L P + nu) g / Kn + r; one operator application per iteration */
 } lincoll_inner_t;
@@ -245,7 +246,7 @@ typedef enum {
 typedef enum {
   LINCOLL_PRECOND_NONE = 0,  /* plain GMRES */
   LINCOLL_PRECOND_SWEEP = 1, /* one transport sweep z = (T + diag(nu)/Kn)^-1 y: the upwind recurrence of the
-                                source iteration (Sec. 5.1) with nu(v) the loss collision frequency of each
+                                source iteration (Sec. 5.2) with nu(v) the loss collision frequency of each
                                 cell's L; left wall ghost from z, right ghost empty; then the total of z is
                                 removed along the current iterate, so corrections keep zero mass */
   LINCOLL_PRECOND_LEARNED = 2 /* SWEEP inside GMRES, and each inner solve starts from a z + alpha Delta with
@@ -289,7 +290,7 @@ int lincoll_steady_newton_apply(lincoll_plan_t plan, const lincoll_steady_params
 int lincoll_steady_precondition(lincoll_plan_t plan, const lincoll_steady_params_t* sp, const double* f,
                                 const double* y, double* z);
 
-/* Modified Newton iteration (Sec. 5.1): f <- f - g with A g = r(f) solved by
+/* Modified Newton iteration (Sec. 5.2): f <- f - g with A g = r(f) solved by
  * restarted flexible GMRES from g = 0 (right preconditioner sp->precond,
  * classical Gram-Schmidt, FP64 vectors, the plan's apply dtype inside A) to
  * the inner tolerances; stops at the
@@ -354,6 +355,16 @@ void lincoll_destroy(lincoll_plan_t plan);
 
 /* Static string for a status code. */
 const char* lincoll_strerror(int status);
+
+/* Testing hook for the out-of-memory paths (not a paper operation): with
+ * after = k > 0, the k-th device allocation the library attempts from now
+ * on fails as if hipMalloc returned out-of-memory (the k - 1 before it
+ * proceed); after <= 0 switches injection off.  A call that fails this way
+ * returns LINCOLL_ENOMEM and leaves the plan usable: its capacities are
+ * reset, so the next call allocates again, and a plan whose Maxwellian cache
+ * was lost reports LINCOLL_ENOTREADY until lincoll_set_maxwellians succeeds.
+ * Process-wide, not thread-safe. */
+void lincoll_debug_fail_alloc(int after);
 
 #define LINCOLL_TABLE_G 0      /* g_j, [J] */
 #define LINCOLL_TABLE_W 1      /* W_j = w_j^g B(g_j), [J] */

@@ -122,7 +122,7 @@ class Problem:
         return grid.idft3(self.plan.Omega * grid.dft3(M)).real
 
     def sweep(self, y, f):
-        """One source-iteration sweep (Sec. 5.1) as a preconditioner about the
+        """One source-iteration sweep (Sec. 5.2, eq. (source_iteration)) as a preconditioner about the
         local Maxwellians of f: z solves
             v1 (z_c - z_{c-1})/dx + nu+_c z_c/Kn = y_c   (v1 > 0)
             v1 (z_{c+1} - z_c)/dx + nu+_c z_c/Kn = y_c   (v1 <= 0)

@@ -92,21 +92,31 @@ size_t esize(int dtype) { return dtype == LINCOLL_F64 ? sizeof(double) : sizeof(
 // so its code is kept here as well).
 thread_local int g_last_hip = 0;
 
+// Failure injection for tests of the out-of-memory paths: when positive, the
+// k-th dalloc call from now fails with hipErrorOutOfMemory (the k - 1 before
+// it succeed); set by lincoll_debug_fail_alloc.
+int g_fail_alloc_after = 0;
+
 int hip_fail(lincoll_plan_t pl, hipError_t e) {
   if (pl) pl->last_hip = (int)e;
   g_last_hip = (int)e;
   return e == hipErrorOutOfMemory ? LINCOLL_ENOMEM : LINCOLL_EHIP;
 }
 
+// (Re)allocates *ptr.  The old buffer is freed first, so after a failure
+// *ptr is null; every caller then zeroes the capacities that describe the
+// buffers it was growing, and the next call allocates them again (or reports
+// LINCOLL_ENOTREADY) instead of launching kernels on null pointers.
 template <typename P>
 hipError_t dalloc(lincoll_plan_t pl, P** ptr, size_t bytes) {
   if (*ptr) {
     (void)hipFree(*ptr);
     *ptr = nullptr;
   }
+  ++pl->alloc_gen;   // device pointers changed: a captured graph is stale
+  if (g_fail_alloc_after > 0 && --g_fail_alloc_after == 0) return hipErrorOutOfMemory;
   void* v = nullptr;
   hipError_t e = hipMalloc(&v, bytes);
-  ++pl->alloc_gen;   // device pointers changed: a captured graph is stale
   if (e == hipSuccess) {
     *ptr = static_cast<P*>(v);
     pl->bytes += bytes;
@@ -162,17 +172,26 @@ int ensure_cells(lincoll_plan_t pl, int B) {
       (e = dalloc(pl, &pl->d_Ainv, (size_t)B * 25 * sizeof(double))) ||
       (e = dalloc(pl, &pl->d_facT, (size_t)B * 6 * n * es)) || (e = dalloc(pl, &pl->d_prefT, (size_t)B * 2 * es)) ||
       (e = dalloc(pl, &pl->d_mask, (size_t)B * n * n * MW * sizeof(uint32_t))) ||
-      (e = dalloc(pl, &pl->d_Kh, (size_t)B * J * kh_stride(n) * es)) || (e = dalloc(pl, &pl->d_nu, (size_t)B * n3 * es)))
+      (e = dalloc(pl, &pl->d_Kh, (size_t)B * J * kh_stride(n) * es)) || (e = dalloc(pl, &pl->d_nu, (size_t)B * n3 * es))) {
+    pl->cap_cells = 0;
+    pl->Bc = 0;          // the Maxwellian cache is gone: applies report ENOTREADY
     return hip_fail(pl, e);
+  }
   pl->cap_cells = B;
-  // setup scratch: chunks of cells bounded to ~256 MiB per buffer
-  const size_t per_cell = (size_t)J * P3 * sizeof(double);
+  // Setup scratch, in chunks of cells bounded to ~256 MiB per buffer.  Per
+  // cell, tmpA holds the J kernel-mode octants (J P^3 doubles) and later the
+  // FP64 loss frequency nu (n^3 doubles); small J makes the second larger.
+  const size_t per_cell = std::max<size_t>((size_t)J * P3, n3) * sizeof(double);
   int chunk = (int)std::max<size_t>(1, (size_t)(256u << 20) / per_cell);
   if (chunk > B) chunk = B;
   if (chunk > pl->setup_chunk) {
     if ((e = dalloc(pl, &pl->d_tmpA, (size_t)chunk * per_cell)) || (e = dalloc(pl, &pl->d_tmpB, (size_t)chunk * per_cell)) ||
-        (e = dalloc(pl, &pl->d_planes64, (size_t)chunk * P * n * n * 2 * sizeof(double))))
+        (e = dalloc(pl, &pl->d_planes64, (size_t)chunk * P * n * n * 2 * sizeof(double)))) {
+      pl->setup_chunk = 0;
+      pl->cap_cells = 0;
+      pl->Bc = 0;
       return hip_fail(pl, e);
+    }
     pl->setup_chunk = chunk;
   }
   return LINCOLL_OK;
@@ -183,23 +202,32 @@ int ensure_work(lincoll_plan_t pl, int B) {
   const size_t es = esize(pl->p.dtype);
   hipError_t e;
   if (pl->p.project && B > pl->cap_pin) {
-    if ((e = dalloc(pl, &pl->d_pin, (size_t)B * n * n * n * es))) return hip_fail(pl, e);
+    if ((e = dalloc(pl, &pl->d_pin, (size_t)B * n * n * n * es))) {
+      pl->cap_pin = 0;
+      return hip_fail(pl, e);
+    }
     pl->cap_pin = B;
   }
   if (use_fused(pl)) {
     const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus));
-    if (need > pl->R_bytes) {
-      if ((e = dalloc(pl, &pl->d_R, need))) return hip_fail(pl, e);
-      pl->R_bytes = need;
+    if (need > pl->R_bytes || !pl->d_R) {
       pl->cap_work = 0;
+      if ((e = dalloc(pl, &pl->d_R, need))) {
+        pl->R_bytes = 0;
+        return hip_fail(pl, e);
+      }
+      pl->R_bytes = need;
     }
     return LINCOLL_OK;
   }
   const size_t vol = (size_t)B * P * n * n * 2 * es, vol64 = (size_t)B * P * n * n * 2 * sizeof(double);
   if (B <= pl->cap_work && pl->d_H && pl->R_bytes >= vol64) return LINCOLL_OK;
   if ((e = dalloc(pl, &pl->d_R, vol64)) || (e = dalloc(pl, &pl->d_H, vol)) || (e = dalloc(pl, &pl->d_W, vol64)) ||
-      (e = dalloc(pl, &pl->d_Wq, vol)) || (e = dalloc(pl, &pl->d_Lp, vol)))
+      (e = dalloc(pl, &pl->d_Wq, vol)) || (e = dalloc(pl, &pl->d_Lp, vol))) {
+    pl->cap_work = 0;
+    pl->R_bytes = 0;
     return hip_fail(pl, e);
+  }
   pl->R_bytes = vol64;
   pl->cap_work = B;
   return LINCOLL_OK;
@@ -210,7 +238,10 @@ int do_set_maxwellians(lincoll_plan_t pl, const double* params, int batch) {
   if (st) return st;
   hipError_t e = hipMemcpyAsync(pl->d_params, params, (size_t)batch * 5 * sizeof(double), hipMemcpyDeviceToDevice,
                                 pl->stream);
-  if (e) return hip_fail(pl, e);
+  if (e) {
+    pl->Bc = 0;
+    return hip_fail(pl, e);
+  }
   SetupCtx c;
   c.n = pl->p.n;
   c.J = pl->t.J;
@@ -238,7 +269,10 @@ int do_set_maxwellians(lincoll_plan_t pl, const double* params, int batch) {
   c.planes64 = pl->d_planes64;
   c.chunk = pl->setup_chunk;
   e = setup_cells(c);
-  if (e) return hip_fail(pl, e);
+  if (e) {
+    pl->Bc = 0;
+    return hip_fail(pl, e);
+  }
   pl->Bc = batch;
   return LINCOLL_OK;
 }
@@ -630,20 +664,28 @@ int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
     std::vector<double> ws(pl->t.Phi);
     for (auto& v : ws) v /= 4.0 * M_PI * M_PI;
     if ((e = dalloc(pl, &pl->d_Ws, ws.size() * sizeof(double))) ||
-        (e = hipMemcpy(pl->d_Ws, ws.data(), ws.size() * sizeof(double), hipMemcpyHostToDevice)))
+        (e = hipMemcpy(pl->d_Ws, ws.data(), ws.size() * sizeof(double), hipMemcpyHostToDevice))) {
+      dfree(pl->d_Ws);
+      pl->d_Ws = nullptr;
       return hip_fail(pl, e);
+    }
   }
   if (batch > pl->cap_qc) {
     const size_t cb = (size_t)batch * n3 * sizeof(double2);
     if ((e = dalloc(pl, &pl->d_qV, bytes)) || (e = dalloc(pl, &pl->d_qF, cb)) || (e = dalloc(pl, &pl->d_qGp, cb)) ||
         (e = dalloc(pl, &pl->d_qGm, cb)) || (e = dalloc(pl, &pl->d_qC, cb)) || (e = dalloc(pl, &pl->d_qS, cb)) ||
-        (e = dalloc(pl, &pl->d_qQ, cb)))
+        (e = dalloc(pl, &pl->d_qQ, cb))) {
+      pl->cap_qc = 0;
       return hip_fail(pl, e);
+    }
     pl->cap_qc = batch;
   }
   const long nph = quadcoll_phase_count(n, (int)mu.size(), pl->sphere_azim);
   if (nph > pl->cap_qph) {
-    if ((e = dalloc(pl, &pl->d_qPh, (size_t)nph * sizeof(double2)))) return hip_fail(pl, e);
+    if ((e = dalloc(pl, &pl->d_qPh, (size_t)nph * sizeof(double2)))) {
+      pl->cap_qph = 0;
+      return hip_fail(pl, e);
+    }
     pl->cap_qph = nph;
   }
   std::vector<double> st(mu.size());
@@ -707,8 +749,10 @@ int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
   if (batch > pl->cap_rk) {
     const size_t bytes = (size_t)batch * pl->p.n * pl->p.n * pl->p.n * esize(pl->p.dtype);
     if ((e = dalloc(pl, &pl->d_rk_k, bytes)) || (e = dalloc(pl, &pl->d_rk_tmp, bytes)) ||
-        (e = dalloc(pl, &pl->d_rk_acc, bytes)))
+        (e = dalloc(pl, &pl->d_rk_acc, bytes))) {
+      pl->cap_rk = 0;
       return hip_fail(pl, e);
+    }
     pl->cap_rk = batch;
   }
   if (!pl->opt_graph) {
@@ -757,6 +801,8 @@ void plan_note_hip(lincoll_plan_s* pl, hipError_t e) {
 }  // namespace lincoll
 
 extern "C" {
+
+void lincoll_debug_fail_alloc(int after) { g_fail_alloc_after = after > 0 ? after : 0; }
 
 int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
   if (!pl && val && key == LINCOLL_INFO_HIP_ERROR) {   // last HIP error of this thread

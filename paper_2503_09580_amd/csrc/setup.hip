@@ -222,9 +222,11 @@ constexpr int PROJ_TB = 1024;
 
 // One block per cell: the five moments of x (FP64 sums in a fixed tree), the
 // coefficients A^-1 m, then y = x - M sum_a coef_a phi_a.  n is a power of
-// two, so velocity indices come from shifts of the flat index.
+// two, so velocity indices come from shifts of the flat index.  x and y may
+// be the same array (the in-place projection of an apply's output), so
+// neither is declared __restrict__.
 template <typename T>
-__global__ void __launch_bounds__(PROJ_TB) k_project(const T* __restrict__ x, T* __restrict__ y, int n, int lgn,
+__global__ void __launch_bounds__(PROJ_TB) k_project(const T* x, T* y, int n, int lgn,
                                                      double L, const double* __restrict__ fac64,
                                                      const double* __restrict__ pref64,
                                                      const double* __restrict__ Ainv, int Bc) {

@@ -340,7 +340,7 @@ struct Solver {
   // Stops when the weighted residual <= max(inner_rtol |b|, inner_atol) or
   // after max_inner operator evaluations.  V: (restart + 1) vectors, Z:
   // restart vectors, tmp: one.
-  // Source iteration (Sec. 5.1): x <- x + M^-1 (b - A x) from x = 0, M^-1 the
+  // Source iteration (Sec. 5.2, eq. (source_iteration)): x <- x + M^-1 (b - A x) from x = 0, M^-1 the
   // zero-mass sweep; stops like gmres.  w, z: scratch vectors.
   int source_iteration(const double* b, double bnorm, double* x, double* w, double* z, int* iters) {
     const double target = std::max(sp.inner_rtol * bnorm * wnorm, inner_atol()) / wnorm;   // plain norm

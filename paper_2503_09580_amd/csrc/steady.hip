@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(TB) k_transport(const double* __restrict__ x, 
 // Transport sweep z = (T + D/Kn)^-1 y, D = diag(nu_c(v)) the loss collision
 // frequency of each cell's linearized operator: per velocity a first-order
 // recurrence along x in the upwind direction (the fast sweeping of the source
-// iteration, Sec. 5.1):
+// iteration, Sec. 5.2):
 //   z_c = (y_c + |v1|/dx z_prev) / (|v1|/dx + nu_c/Kn) = alpha_c z_prev + beta_c.
 // NEG (v1 <= 0) runs from the right wall leftwards with an empty (zero) ghost;
 // the POS pass (v1 > 0) runs rightwards from the left ghost rho_L E_L with

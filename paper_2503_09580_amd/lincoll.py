@@ -32,7 +32,7 @@ SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll
            "lincoll_steady_precondition",
            "lincoll_mlp_create", "lincoll_mlp_destroy", "lincoll_mlp_set_stream", "lincoll_mlp_weights",
            "lincoll_mlp_forward", "lincoll_mlp_loss_grad", "lincoll_mlp_train", "lincoll_learned_features",
-           "lincoll_learned_correction"]
+           "lincoll_learned_correction", "lincoll_debug_fail_alloc"]
 
 
 class LincollError(RuntimeError):
@@ -125,6 +125,7 @@ def _load():
         "lincoll_get_info": (i, [vp, i, P(d)]),
         "lincoll_destroy": (None, [vp]),
         "lincoll_strerror": (ctypes.c_char_p, [i]),
+        "lincoll_debug_fail_alloc": (None, [i]),
         "lincoll_plan_tables": (ctypes.c_longlong, [P(Params), i, P(d), ctypes.c_longlong]),
         "lincoll_set_option": (i, [vp, i, i]),
         "lincoll_autotune": (i, [vp, vp, vp, i, i]),

@@ -16,7 +16,7 @@ the configurations below are synthetic stand-ins of the same kind:
   C3  n=32, L=8,  omega=0.74, 4096 cells along a 1-D grid with sinusoidal
       rho, u, theta (amplitude 0.2), h_i = M_i p_i((v-u_i)/sqrt(theta_i))
   C4  n=32, L=8,  omega=0.74, the steady 1-D slab x in [-0.5, 0.5] on 256
-      cells, wall temperatures 1 and 1.5, Kn = 0.1, total mass 1 (Sec. 5.2,
+      cells, wall temperatures 1 and 1.5, Kn = 0.1, total mass 1 (Sec. 5.3.2,
       the heat-transfer case); states from the solver, test states from
       slab_state
   C5  n=64, L=10, omega=0.74, 512 cells, rho=1, u=0, theta log-uniform in

@@ -1,5 +1,5 @@
 """Writes steady_slab_n16.txt: the oracle's converged solution of the steady
-1-D heat-transfer problem (Sec. 5.2, the Fourier flow; Appendix B scheme) on a
+1-D heat-transfer problem (Sec. 5.3.2, the Fourier flow; Appendix B scheme) on a
 small grid, for the GPU solver's parity test.  Calls only oracle/ and the
 input generators.
 
@@ -29,7 +29,7 @@ def main():
     idx = np.stack([rng.integers(0, c["nx"], SAMPLES)] + [rng.integers(0, c["n"], SAMPLES) for _ in range(3)], 1)
     out = os.path.join(HERE, "steady_slab_n16.txt")
     with open(out, "w") as fh:
-        fh.write("# Oracle solution of the steady 1-D heat-transfer problem (Sec. 5.2; scheme of\n")
+        fh.write("# Oracle solution of the steady 1-D heat-transfer problem (Sec. 5.3.2; scheme of\n")
         fh.write("# Appendix B; readings: zero-flux wall densities, Q with Q^_0 = 0, P L P in the\n")
         fh.write("# Newton operator, iterates rescaled to the mass C).  Written by\n")
         fh.write("# tests/golden/make_steady.py from oracle/ only.\n")

@@ -88,6 +88,36 @@ def test_adam_step_matches_oracle():
     assert np.all(np.abs((got - flat)[big] - step_ref[big]) <= tol)
 
 
+def test_adam_five_steps_match_oracle_sequence():
+    """Five full-batch training steps (gradient, then Adam with the step
+    count t = 1..5 in its bias corrections) against the oracle's
+    loss_grad + adam_step sequence.  After the first step m/sqrt(v) is no
+    longer sign(g), so a wrong power of beta1 or beta2 in the bias
+    correction changes the steps by tens of percent; the bar is FP32
+    rounding of the weights (2 ulp per step) plus 1e-3 of the five steps."""
+    flat, w = _weights(5)
+    X, T = _data(6, 80)
+    lr, steps = 1e-3, 5
+    net = lc.MLP(seed=0)
+    net.set_weights(flat)
+    net.train(_dev32(X), _dev32(T), steps=steps, lr=lr)
+    got = net.get_weights().astype(np.float64)
+    ww = [a.copy() for a in w]
+    m = [np.zeros_like(a) for a in w]
+    v = [np.zeros_like(a) for a in w]
+    gmin = np.full(ol.N_WEIGHTS, np.inf)
+    for t in range(1, steps + 1):
+        _, g = ol.loss_grad(ww, X.astype(np.float64), T.astype(np.float64))
+        gmin = np.minimum(gmin, np.abs(ol.pack(g)))
+        ww, m, v = ol.adam_step(ww, list(g), m, v, t, lr)
+    ref = ol.pack(ww)
+    d_got, d_ref = got - flat, ref - flat.astype(np.float64)
+    big = gmin > 1e-3     # gradients well above their FP32 error at every step
+    assert big.sum() > 1000
+    tol = steps * 2 * np.spacing(np.abs(flat[big])).astype(np.float64) + 1e-3 * steps * lr
+    assert np.all(np.abs(d_got[big] - d_ref[big]) <= tol), np.max(np.abs(d_got[big] - d_ref[big]))
+
+
 def test_features_and_correction_match_oracle():
     n, L, nx = 16, 5.0, 7
     sp = lc.steady_params(nx)

@@ -17,7 +17,8 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
-from test_gpu_parity import mixed_inputs, rel  # noqa: E402
+from test_gpu_parity import mixed_inputs  # noqa: E402
+from parity_util import check  # noqa: E402
 
 DEV = torch.device("cuda:0")
 
@@ -46,7 +47,7 @@ def test_quadcoll_matches_binary_oracle(n, L, om, polar, azim):
     sphere = quadrature.hemisphere_product_rule(polar, azim)
     for b in range(3):
         ref = binary.q_binary(plan, sphere, f[b], f[b], method="fast")
-        assert rel(got[b], ref) <= 1e-12, (b, rel(got[b], ref))
+        check(got[b], ref, 1e-12, tag=b)
 
 
 def test_hemisphere_rule_changes_between_calls():
@@ -66,7 +67,7 @@ def test_hemisphere_rule_changes_between_calls():
         sphere = quadrature.hemisphere_product_rule(polar, azim)
         for b in range(2):
             ref = binary.q_binary(fd_plan, sphere, f[b], f[b], method="fast")
-            assert rel(got[b], ref) <= 1e-12, (polar, azim, b, rel(got[b], ref))
+            check(got[b], ref, 1e-12, tag=(polar, azim, b))
 
 
 def test_polarisation_gives_the_linearized_binary_operator():
@@ -77,7 +78,7 @@ def test_polarisation_gives_the_linearized_binary_operator():
     lin_gpu = q[0] - q[1] - q[2]
     plan = fd.make_plan(n, L, om)
     ref = binary.linearized_binary(plan, quadrature.hemisphere_product_rule(8, 16), h[0], M)
-    assert rel(lin_gpu, ref) <= 1e-10, rel(lin_gpu, ref)
+    check(lin_gpu, ref, 1e-10)
 
 
 def test_quadcoll_errors():

@@ -25,7 +25,8 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
-from test_gpu_parity import mixed_inputs, rel  # noqa: E402
+from test_gpu_parity import mixed_inputs  # noqa: E402
+from parity_util import check  # noqa: E402
 
 DEV = torch.device("cuda:0")
 
@@ -56,7 +57,7 @@ def test_rk4_matches_oracle(n, dtype, tol):
         if dtype == "f32":
             lm = fd.apply(op, fin[b], params[b, 0], params[b, 1:4], params[b, 4], parts=True)[2]
             bar = tol * (1.0 + 4 * steps * dt * np.linalg.norm(lm) / np.linalg.norm(ref[b]))
-        assert rel(got[b], ref[b]) <= bar, (b, rel(got[b], ref[b]), bar)
+        check(got[b], ref[b], bar, tag=b)
 
 
 def test_rk4_graph_replay_equals_eager_and_zero_steps():

@@ -100,3 +100,31 @@ def test_moments_invert_the_correction():
     m = lr_.moments(d, params, n, L)
     # the box edge truncates the theta = 1.2 tail of |v - u|^4 M at about 1e-10
     assert np.max(np.abs(m - s * Y)) < 1e-9
+
+
+def test_adam_bias_correction_beyond_the_first_step():
+    """Pins Adam's bias correction at t > 1 against two closed forms
+    (Kingma & Ba, 2015, Algorithm 1):
+    - a constant gradient g for t = 1..5 gives m_t = (1 - b1^t) g and
+      v_t = (1 - b2^t) g^2, so the corrected ratio is g/|g| at every step
+      and each step moves the weight by lr * sign(g);
+    - g at t = 1 and -g at t = 2 gives m_2 = -(1 - b1)^2 g and
+      v_2 = (1 - b2^2) g^2; corrected, m_2/(1 - b1^2) = -(1 - b1)/(1 + b1) g
+      and v_2/(1 - b2^2) = g^2, so the second step is
+      +lr (1 - b1)/(1 + b1) sign(g).
+    A bias correction with the wrong power of b1 or b2 fails both."""
+    lr, b1 = 1e-2, 0.9
+    g = np.array([0.3, -2.0, 5e-3, -1e-2, 7.0])
+    w = [np.zeros(5)]
+    m, v = [np.zeros(5)], [np.zeros(5)]
+    for t in range(1, 6):
+        before = w[0].copy()
+        lr_.adam_step(w, [g], m, v, t, lr)
+        assert np.allclose(w[0] - before, -lr * np.sign(g), rtol=1e-5, atol=0), t
+    w = [np.zeros(5)]
+    m, v = [np.zeros(5)], [np.zeros(5)]
+    lr_.adam_step(w, [g], m, v, 1, lr)
+    first = w[0].copy()
+    lr_.adam_step(w, [-g], m, v, 2, lr)
+    want = lr * (1 - b1) / (1 + b1) * np.sign(g)
+    assert np.allclose(w[0] - first, want, rtol=1e-5, atol=0)
