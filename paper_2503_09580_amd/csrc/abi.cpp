@@ -172,7 +172,7 @@ int ensure_cells(lincoll_plan_t pl, int B) {
       (e = dalloc(pl, &pl->d_Ainv, (size_t)B * 25 * sizeof(double))) ||
       (e = dalloc(pl, &pl->d_facT, (size_t)B * 6 * n * es)) || (e = dalloc(pl, &pl->d_prefT, (size_t)B * 2 * es)) ||
       (e = dalloc(pl, &pl->d_mask, (size_t)B * n * n * MW * sizeof(uint32_t))) ||
-      (e = dalloc(pl, &pl->d_Kh, (size_t)B * J * kh_stride(n) * es)) || (e = dalloc(pl, &pl->d_nu, (size_t)B * n3 * es))) {
+      (e = dalloc(pl, &pl->d_Kh, (size_t)B * J * kh_stride(n) * sizeof(double))) || (e = dalloc(pl, &pl->d_nu, (size_t)B * n3 * es))) {
     pl->cap_cells = 0;
     pl->Bc = 0;          // the Maxwellian cache is gone: applies report ENOTREADY
     return hip_fail(pl, e);

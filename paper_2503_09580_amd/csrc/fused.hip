@@ -15,14 +15,22 @@
 // Y <-> X transposes are local to a wave's own LDS region and need no
 // workgroup barrier; only X <-> Z exchanges synchronise the workgroup.
 //
-// Precision (FP32 at the HBM boundary): the spectrum of r = chi h / M is
-// stored in double, and every butterfly that acts on r-derived data (the
-// forward transform of r, the inverse transforms giving psi_j) runs in
-// double, with float storage between axis passes.  r is large where M is
-// small (Sec. 3.3): rounding its spectrum to float, or float arithmetic on
-// it, spreads that size over the box, while rounding partially transformed
-// values between passes does not measurably change the result.  After the
-// product with M^h everything runs in float.
+// Precision (FP32 at the HBM boundary): everything that acts on r-derived data
+// (the forward transform of r = chi h / M, its stored spectrum, the kernel
+// modes K_j, the inverse transforms giving psi_j) is double, including the
+// LDS exchanges between axis passes, which move one component at a time.  r
+// is large where M is small (Sec. 3.3): a float rounding anywhere on that
+// path (of K_j, or of partially transformed values between passes) spreads
+// that size over the box and cost up to 1.8e-5 of max |L| element-wise.
+// After the product with M^h everything runs in float.
+//
+// LDS: one float2 volume for the exchanges, the radial table of the node
+// and the 1-D Maxwellian factors.  The kernel modes K_j of a node are needed
+// only in the Y role, where each wave handles its own planes: each wave
+// copies its planes of K_j (and, wave 0, the Nyquist plane kz = N) into its
+// own region of the exchange volume, which no other wave touches between the
+// end of one node's forward transform and the start of the next node's
+// X -> Z exchange.
 #include "fft.h"
 #include "internal.h"
 
@@ -98,6 +106,27 @@ __device__ __forceinline__ void z_inverse(const T (&vr)[NN], const T (&vi)[NN], 
   fft<NN, true>(zr, zi);
 }
 
+// Wave-private copy of K_j: wave w's planes kp = w*PW .. w*PW+PW-1 of the
+// octant [P][P][P] (and, wave 0 only, plane N after them) into the start of
+// the wave's own region of the exchange volume, as double.  Completion is
+// tracked by vmcnt; the wave waits for it before reading.
+template <int NN>
+__device__ __forceinline__ void k_slice_dma(const double* Kj, float2* lds, int t) {
+  constexpr int N = NN / 2, P = N + 1, PP = P * P, PW = 64 / NN, LD = NN + 1;
+  const int wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64;
+  float* dst = reinterpret_cast<float*>(lds + wave * PW * NN * LD);
+  auto copy = [&](const float* src, float* d, int count) {
+    for (int c = 0; c * 64 < count; ++c) {
+      const int q = c * 64 + lane;
+      if (q < count)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + q),
+                                         (__attribute__((address_space(3))) void*)(d + c * 64), 4, 0, 0);
+    }
+  };
+  copy(reinterpret_cast<const float*>(Kj + (size_t)wave * PW * PP), dst, PW * PP * 2);
+  if (wave == 0) copy(reinterpret_cast<const float*>(Kj + (size_t)N * PP), dst + PW * PP * 2, PP * 2);
+}
+
 // ---- transposes through LDS (float2 storage) ----------------------------------
 // Within plane kp: thread (kp, i) holds v[j] = element (i, j); afterwards it
 // holds v[j] = element (j, i).  Plane kp lives in the region of the wave that
@@ -153,6 +182,62 @@ __device__ __forceinline__ void z_to_x(T (&vr)[NN], T (&vi)[NN], float2* lds, in
   });
 }
 
+// The same three exchanges in double for r-derived data: the volume holds
+// one double per complex slot, so the real and the imaginary parts go in two
+// rounds.
+template <int NN>
+__device__ __forceinline__ void transpose_plane_d(double (&vr)[NN], double (&vi)[NN], float2* lds, int t) {
+  constexpr int LD = NN + 1;
+  const int kp = t / NN, i = t % NN;
+  double* pl = reinterpret_cast<double*>(lds + kp * NN * LD);
+  auto one = [&](double(&w)[NN]) {
+    static_for<0, NN>([&](auto j) { pl[i * LD + j] = w[j]; });
+    wave_lds_sync();
+    static_for<0, NN>([&](auto j) { w[j] = pl[j * LD + i]; });
+    wave_lds_sync();
+  };
+  one(vr);
+  one(vi);
+}
+
+template <int NN>
+__device__ __forceinline__ void x_to_z_d(double (&vr)[NN], double (&vi)[NN], float2* lds, int t) {
+  constexpr int N = NN / 2, KP = N, LD = NN + 1;
+  const int kp = t / NN, y = t % NN;
+  const int x = t / N, yp = t % N;
+  double* ld = reinterpret_cast<double*>(lds);
+  auto one = [&](double(&w)[NN]) {
+    static_for<0, NN>([&](auto xx) { ld[(kp * NN + xx) * LD + y] = w[xx]; });
+    __syncthreads();
+    static_for<0, KP>([&](auto k) {
+      w[k] = ld[(k * NN + x) * LD + yp];
+      w[N + k] = ld[(k * NN + x) * LD + yp + N];
+    });
+  };
+  one(vr);
+  __syncthreads();   // every wave has read the real parts
+  one(vi);
+}
+
+template <int NN>
+__device__ __forceinline__ void z_to_x_d(double (&vr)[NN], double (&vi)[NN], float2* lds, int t) {
+  constexpr int N = NN / 2, KP = N, LD = NN + 1;
+  const int kp = t / NN, y = t % NN;
+  const int x = t / N, yp = t % N;
+  double* ld = reinterpret_cast<double*>(lds);
+  auto one = [&](double(&w)[NN]) {
+    __syncthreads();
+    static_for<0, KP>([&](auto k) {
+      ld[(k * NN + x) * LD + yp] = w[k];
+      ld[(k * NN + x) * LD + yp + N] = w[N + k];
+    });
+    __syncthreads();
+    static_for<0, NN>([&](auto xx) { w[xx] = ld[(kp * NN + xx) * LD + y]; });
+  };
+  one(vr);
+  one(vi);
+}
+
 // Y role, pencil along ky: multiply by a real spectral factor m(kx, ky, kz)
 // that is even in every component.  getm(ky) returns (m at the pencil's own
 // plane, m at kz = N).  Plane 0 carries kz = 0 (real part) and kz = N
@@ -201,15 +286,14 @@ __device__ __forceinline__ void mode_multiply(T (&vr)[NN], T (&vi)[NN], int t, G
 template <int NN>
 __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     const float* __restrict__ h, float* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
-    const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const float* __restrict__ Kh,
+    const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
     const float* __restrict__ nu, const float* __restrict__ Phi, const float* __restrict__ Om,
     double2* __restrict__ scratch, int J) {
   using C = Cfg<NN>;
-  constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, P3 = C::P3;
+  constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, PW = 64 / NN, LD = C::LD;
   __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
   __shared__ double fs[9 * NN + 3];
   __shared__ float tab[Q];
-  __shared__ float Ks[P3];
   const int t0 = threadIdx.x;
   // Scratch slot of this workgroup: R (KP*NP complex double) then the L+
   // accumulator (KP*NP complex float).  Both are interleaved by thread
@@ -232,7 +316,6 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     for (int i = t; i < 6 * NN; i += C::T) fs[i] = fac64[(size_t)cc * 6 * NN + i];
     if (t < 2) fs[6 * NN + t] = pref64[2 * cc + t];
     for (int q = t; q < Q; q += C::T) tab[q] = Om[q];
-    lds_dma(Kh + (size_t)cc * J * kh_stride(NN), Ks, P3, t, C::T);   // K_0, waited for before the gain loop
     __syncthreads();
     // reciprocal factors of M for r = chi h / M (infinite where a factor
     // underflows; such points are outside the cutoff and never selected)
@@ -300,20 +383,19 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         });
         z_forward<NN, double>(zr, zi, vr, vi);
       }
-      z_to_x<NN, double>(vr, vi, lds, t);
+      z_to_x_d<NN>(vr, vi, lds, t);
       fft<NN, false>(vr, vi);
-      transpose_plane<NN, double>(vr, vi, lds, t);
+      transpose_plane_d<NN>(vr, vi, lds, t);
       fft<NN, false>(vr, vi);
       static_for<0, NN>([&](auto ky) { Rs[ky * C::T + t] = double2{vr[ky], vi[ky]}; });
     }
+    k_slice_dma<NN>(Kh + (size_t)cc * J * kh_stride(NN), lds, t);   // K_0 into this wave's region
 
     // ---------------- gain loop ---------------------------------------------------
     // The running sum of Phi_j Q_j lives in the scratch slot between nodes (it
     // is loaded back only during the float part of a node, where registers are
     // free); after the last node it stays in registers.
     float Lr[NN], Li[NN];
-    __builtin_amdgcn_s_waitcnt(0x0f70);     // vmcnt(0): K_0 has landed
-    __syncthreads();
     for (int j = 0; j < J; ++j) {
       asm volatile("" : "+v"(t));
       float fr[NN], fi[NN];
@@ -324,18 +406,20 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
           vr[ky] = v.x;
           vi[ky] = v.y;
         });
+        __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copy of K_j has landed
+        const double* Kw = reinterpret_cast<const double*>(lds + (t / 64) * PW * NN * LD);
+        const int kw = kp - (t / 64) * PW;
         mode_multiply<NN, double>(vr, vi, t, [&](auto ky) {     // K_j / n^3
           constexpr int fy = ky <= N ? ky : NN - ky;
-          return float2{Ks[(kp * P + fy) * P + fx], Ks[(N * P + fy) * P + fx]};
+          return double2{Kw[(kw * P + fy) * P + fx], Kw[(PW * P + fy) * P + fx]};
         });
         fft<NN, true>(vr, vi);
-        transpose_plane<NN, double>(vr, vi, lds, t);
+        transpose_plane_d<NN>(vr, vi, lds, t);
         fft<NN, true>(vr, vi);
-        x_to_z<NN, double>(vr, vi, lds, t);
-        // Every wave has used K_j and Phi_{j-1} by now: stream K_{j+1} and
-        // Phi_j into LDS while the z stage runs.  Both are complete and
-        // visible after the wait and first barrier of the next X <- Z exchange.
-        if (j + 1 < J) lds_dma(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), Ks, P3, t, C::T);
+        x_to_z_d<NN>(vr, vi, lds, t);
+        // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
+        // the z stage runs.  It is complete and visible after the wait and
+        // first barrier of the next X <- Z exchange.
         lds_dma(Phi + (size_t)j * phi_stride(NN), tab, Q, t, C::T);
         // psi on the two columns, times M^h; float from here on
         double zr[NN], zi[NN];
@@ -356,6 +440,12 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       static_for<0, NN / 2>([&](auto c) { acc[c] = j > 0 ? Ac[c * C::T + t] : float4{0.f, 0.f, 0.f, 0.f}; });
       fft<NN, false>(fr, fi);
       transpose_plane<NN, float>(fr, fi, lds, t);
+      // This wave is done with its region until the next node's K_j product;
+      // its transpose reads complete (lgkmcnt(0)) before the copy may land.
+      if (j + 1 < J) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        k_slice_dma<NN>(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), lds, t);
+      }
       fft<NN, false>(fr, fi);
       mode_multiply<NN, float>(fr, fi, t, [&](auto ky) {       // Phi_j / n^3
         constexpr int fy = ky <= N ? ky : NN - ky;
@@ -413,7 +503,7 @@ hipError_t fused_apply(const ApplyCtx& c) {
   const int slots = fused_slots(c.n, c.batch, c.per_cu, c.cus);
   const float* h = static_cast<const float*>(c.h);
   float* out = static_cast<float*>(c.out);
-  const float* Kh = static_cast<const float*>(c.Kh);
+  const double* Kh = static_cast<const double*>(c.Kh);
   const float* nu = static_cast<const float*>(c.nu);
   const float* Phi = static_cast<const float*>(c.Phi);
   const float* Om = static_cast<const float*>(c.Om);

@@ -40,7 +40,7 @@ struct ApplyCtx {
   const double* fac64 = nullptr;   // the same two in FP64
   const double* pref64 = nullptr;
   const uint32_t* mask = nullptr;  // [Bc][n*n][(n+31)/32] cutoff bits along z
-  const void* Kh = nullptr;    // [Bc][J][kh_stride(n)]  K_j / n^3 on the octant [P][P][P], P = n/2+1
+  const void* Kh = nullptr;    // [Bc][J][kh_stride(n)]  K_j / n^3 on the octant [P][P][P], P = n/2+1, double
   const void* nu = nullptr;    // [Bc][n^3]
   void* R = nullptr;           // work, complex [batch][P][n][n] each; R and W in double
   void* H = nullptr;
@@ -67,7 +67,7 @@ struct SetupCtx {
   void* facT = nullptr;            // copies in the apply dtype
   void* prefT = nullptr;
   uint32_t* mask = nullptr;
-  void* Kh = nullptr;              // [Bc][J][kh_stride(n)] apply dtype (octant [P][P][P] first)
+  void* Kh = nullptr;              // [Bc][J][kh_stride(n)] double for every dtype (octant [P][P][P] first)
   void* nu = nullptr;              // [Bc][n^3] apply dtype
   double* tmpA = nullptr;          // scratch, [chunk][J][P^3] FP64 each
   double* tmpB = nullptr;

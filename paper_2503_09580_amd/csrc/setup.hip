@@ -198,7 +198,10 @@ hipError_t setup_cells(const SetupCtx& c) {
   }
   for (int c0 = 0; c0 < c.Bc; c0 += c.chunk) {
     const int nc = c.Bc - c0 < c.chunk ? c.Bc - c0 : c.chunk;
-    e = c.dtype == 0 ? kh_dispatch<double>(c, c0, nc) : kh_dispatch<float>(c, c0, nc);
+    // K_j is kept in double for every dtype: its product with the spectrum of
+    // r (large where M is small, Sec. 3.3) turns a float rounding of K_j into
+    // an error of about 1e-5 of the result.
+    e = kh_dispatch<double>(c, c0, nc);
     if (e != hipSuccess) return e;
     // nu in FP64 for this chunk, written to tmpA (n^3 doubles per cell fit:
     // J P^3 >= n^3 for every supported n), then stored in the apply dtype

@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restr
 // POST 2: as 1 and accumulate into out (store when first).
 template <typename TI, typename TO, typename TS, typename T, int NN, bool INV, int PRE, int POST>
 __global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, typename V2<TO>::t* out,
-                                               const TS* __restrict__ Kh, const TS* __restrict__ table, int J,
+                                               const double* __restrict__ Kh, const TS* __restrict__ table, int J,
                                                int j, int Bc, int nplanes, int first) {
   using CI = typename V2<TI>::t;
   using C = typename V2<TO>::t;
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, type
       vi[k1] = T(v.y);
     });
     if constexpr (PRE == 1) {
-      const TS* K = Kh + ((size_t)cc * J + j) * kh_stride(NN) + (size_t)kz * P * P + fold<NN>(a);
+      const double* K = Kh + ((size_t)cc * J + j) * kh_stride(NN) + (size_t)kz * P * P + fold<NN>(a);
       static_for<0, NN>([&](auto k1) {
         const T kv = T(K[fold<NN>(k1) * P]);
         vr[k1] *= kv;
@@ -322,18 +322,18 @@ static hipError_t apply_n(const ApplyCtx& c) {
   const int B = c.batch;
   const TS* fac = static_cast<const TS*>(c.fac);
   const TS* pref = static_cast<const TS*>(c.pref);
-  const TS* Kh = static_cast<const TS*>(c.Kh);
+  const double* Kh = static_cast<const double*>(c.Kh);
   const TS* Phi = static_cast<const TS*>(c.Phi);
   const TS* Om = static_cast<const TS*>(c.Om);
   // r-derived spectra are transformed in double for every dtype; R is stored
   // in double, W as below; H, W after the product and L+ use TS.
   double2* R = static_cast<double2*>(c.R);
   double2* W = static_cast<double2*>(c.W);
-  // W between the in-plane and z passes of a node is stored in the storage
-  // precision up to n = 32 (FP32 staged C3: 20.8 -> 17.2 ms at an unchanged
-  // error); at n = 64 the float copy measured slower (41.4 -> 44.0 ms), so it
-  // stays double there.
-  using TW = std::conditional_t<NN == 64, double, TS>;
+  // W between the in-plane and z passes of a node stays in double: rounding
+  // this partially transformed r-derived spectrum to float (like storing the
+  // kernel modes K_j in float) raised the largest element-wise FP32 error to
+  // about 1.8e-5 of max |L| on per-cell Maxwellian inputs at n = 16.
+  using TW = double;
   using CW = typename V2<TW>::t;
   CW* WS = static_cast<CW*>(c.W);
   Cx* H = static_cast<Cx*>(c.H);

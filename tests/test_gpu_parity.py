@@ -298,7 +298,7 @@ def test_c3_fp32_fused_every_cell():
     full = run(ref64, hin, params, "f64")
     ref64.close()
     # the GPU FP64 result is itself the oracle's on the sampled cells
-    check_cells(full, ref, 1e-12, cells=sample[::8], tag="f64 vs oracle")
+    check_cells(full, ref[::8], 1e-12, cells=sample[::8], tag="f64 vs oracle")
     l2, mx = check_batch(got, full, 1e-5, tag="f32 vs gpu f64")
     print(f"C3 FP32, 4096 cells vs GPU FP64: worst l2 {l2:.3e}, worst element-wise {mx:.3e}; "
           f"64 cells vs oracle: {l2o:.3e}, {mxo:.3e}")
