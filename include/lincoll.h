@@ -101,6 +101,24 @@ int lincoll_set_maxwellians(lincoll_plan_t plan, const double* params, int batch
  * the Maxwellian batch must be 1 (else LINCOLL_ENOTREADY). */
 int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
 
+/* lincoll_apply without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and argument checks as
+ * lincoll_apply; the output is bitwise identical to lincoll_apply's on the
+ * same plan.  It calls no hipMalloc, hipFree or other allocating routine and
+ * never records a graph: the fused kernel's per-workgroup scratch (the
+ * spectrum of r and the L+ accumulator) lives in a fixed 96 MiB device array
+ * of the library, one per GPU, held until the process ends, which limits
+ * the persistent workgroups to 256 at n = 32 and 1024 at n = 16 (any batch
+ * is processed; the workgroups loop over cells).  Nothing in that array needs
+ * to start at zero.  All calls on one GPU share it: calls that overlap in
+ * time on one GPU (other streams, other plans, other threads) race and give
+ * wrong results; serialise them.  Requirements beyond lincoll_apply's: the
+ * plan's apply takes the fused path (LINCOLL_F32, n = 16 or 32, path AUTO or
+ * FUSED), project = 0, the Maxwellians already set (lincoll_set_maxwellians
+ * allocates), and the plan's device current; otherwise LINCOLL_EINVAL. */
+int lincoll_apply_noalloc(lincoll_plan_t plan, const void* h, void* out, int batch);
+
 /* y[b] = P x[b]: removes the collision-invariant part in the inner product
  * <a,b> = sum a b / M, i.e. y = x - M sum_a phi_a (A^-1 m[x])_a with
  * phi_a in {1, v1, v2, v3, |v|^2}, A_ab = sum M phi_a phi_b, m_a = sum x phi_a.

@@ -451,15 +451,7 @@ int lincoll_project(lincoll_plan_t pl, const void* x, void* y, int batch) {
 
 namespace {
 
-// Every launch of one apply, on `stream` (the plan's stream, or the capture
-// stream while a replayable graph is recorded).  Work buffers must exist.
-hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, hipStream_t stream) {
-  hipError_t e;
-  const void* hin = h;
-  if (pl->p.project) {
-    if ((e = launch_project(pl, h, pl->d_pin, batch, stream))) return e;
-    hin = pl->d_pin;
-  }
+ApplyCtx apply_ctx(lincoll_plan_t pl, const void* hin, void* out, int batch, hipStream_t stream) {
   ApplyCtx c;
   c.n = pl->p.n;
   c.J = pl->t.J;
@@ -486,6 +478,19 @@ hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, 
   c.W = pl->d_W;
   c.Wq = pl->d_Wq;
   c.Lp = pl->d_Lp;
+  return c;
+}
+
+// Every launch of one apply, on `stream` (the plan's stream, or the capture
+// stream while a replayable graph is recorded).  Work buffers must exist.
+hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, hipStream_t stream) {
+  hipError_t e;
+  const void* hin = h;
+  if (pl->p.project) {
+    if ((e = launch_project(pl, h, pl->d_pin, batch, stream))) return e;
+    hin = pl->d_pin;
+  }
+  const ApplyCtx c = apply_ctx(pl, hin, out, batch, stream);
   if ((e = use_fused(pl) ? fused_apply(c) : staged_apply(c))) return e;
   if (pl->p.project) return launch_project(pl, out, out, batch, stream);
   return hipSuccess;
@@ -548,6 +553,26 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
                     k.fused == key.fused && k.per_cu == key.per_cu && k.project == key.project && k.gen == key.gen;
   if (!same && (e = capture_apply(pl, h, out, batch, key))) return hip_fail(pl, e);
   if ((e = hipGraphLaunch(pl->gexec, pl->stream))) return hip_fail(pl, e);
+  return LINCOLL_OK;
+}
+
+int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch) {
+  int st = checked_apply_args(pl, h, out, batch);
+  if (st) return st;
+  if (!use_fused(pl) || pl->p.project) return LINCOLL_EINVAL;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e) return hip_fail(pl, e);
+  if (dev != pl->device) return LINCOLL_EINVAL;
+  void* scr = nullptr;
+  size_t bytes = 0;
+  if ((e = fused_noalloc_scratch(dev, &scr, &bytes))) return hip_fail(pl, e);
+  const size_t slot = fused_scratch_bytes(pl->p.n, 1);
+  if (slot == 0 || slot > bytes) return LINCOLL_EINVAL;
+  ApplyCtx c = apply_ctx(pl, h, out, batch, pl->stream);
+  c.R = scr;
+  c.max_slots = (int)(bytes / slot);
+  if ((e = fused_apply(c))) return hip_fail(pl, e);
   return LINCOLL_OK;
 }
 

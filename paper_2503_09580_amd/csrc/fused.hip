@@ -31,10 +31,20 @@
 // own region of the exchange volume, which no other wave touches between the
 // end of one node's forward transform and the start of the next node's
 // X -> Z exchange.
+#include <mutex>
+
 #include "fft.h"
 #include "internal.h"
 
 namespace lincoll {
+
+// Slots of lincoll_apply_noalloc: the persistent workgroups' scratch (the
+// spectrum of r and the L+ accumulator) in a file-scope device array instead
+// of plan memory, so that the entry point allocates nothing.  Each device the
+// library runs on holds its own copy until the process ends.  96 MiB holds
+// 256 slots at n = 32 (one per compute unit of an MI355X) or 1024 at n = 16.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -288,7 +298,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     const float* __restrict__ h, float* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
     const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
     const float* __restrict__ nu, const float* __restrict__ Phi, const float* __restrict__ Om,
-    double2* __restrict__ scratch, int J) {
+    double2* __restrict__ slots, int J) {
   using C = Cfg<NN>;
   constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, PW = 64 / NN, LD = C::LD;
   __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
@@ -299,7 +309,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
   // accumulator (KP*NP complex float).  Both are interleaved by thread
   // (element i of thread t at i*T + t) so that each load or store
   // instruction of a wave covers one contiguous segment.
-  double2* Rs = scratch + (size_t)blockIdx.x * (KP * NP + KP * NP / 2);
+  double2* Rs = slots + (size_t)blockIdx.x * (KP * NP + KP * NP / 2);
   float4* Ac = reinterpret_cast<float4*>(Rs + KP * NP);
 
   for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
@@ -499,8 +509,32 @@ int fused_slots(int n, int batch, int per_cu, int cus) {
   return batch < slots ? batch : slots;
 }
 
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the host-side name of a __device__ array is only a
+// stand-in, never a device address).
+namespace {
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64];
+}  // namespace
+
+hipError_t fused_noalloc_scratch(int device, void** ptr, size_t* bytes) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = p;
+  }
+  *ptr = g_noalloc_ptr[device];
+  *bytes = NOALLOC_SCRATCH_BYTES;
+  return hipSuccess;
+}
+
 hipError_t fused_apply(const ApplyCtx& c) {
-  const int slots = fused_slots(c.n, c.batch, c.per_cu, c.cus);
+  int slots = fused_slots(c.n, c.batch, c.per_cu, c.cus);
+  if (c.max_slots > 0 && slots > c.max_slots) slots = c.max_slots;   // the kernel is persistent over cells
   const float* h = static_cast<const float*>(c.h);
   float* out = static_cast<float*>(c.out);
   const double* Kh = static_cast<const double*>(c.Kh);

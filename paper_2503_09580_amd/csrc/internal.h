@@ -29,6 +29,7 @@ struct ApplyCtx {
   int batch = 0, Bc = 0;       // cells in this call; cells in the Maxwellian cache (1 = broadcast)
   int cus = 256;               // compute units of the device
   int per_cu = 0;              // fused path: workgroups per compute unit (0 = default)
+  int max_slots = 0;           // fused path: cap on the persistent workgroups (0 = none)
   int dtype = 0;
   hipStream_t stream = nullptr;
   const void* h = nullptr;
@@ -124,6 +125,9 @@ hipError_t rk_stage(int dtype, const void* f, const void* k, void* acc, void* tm
                     int first, hipStream_t s);
 hipError_t rk_final(int dtype, void* f, const void* acc, const void* k, long count, double a, hipStream_t s);
 size_t fused_scratch_bytes(int n, int nslots);
+// The fixed device scratch of lincoll_apply_noalloc on `device` (which must
+// be current): its address and size.
+hipError_t fused_noalloc_scratch(int device, void** ptr, size_t* bytes);
 int fused_max_per_cu(int n);
 int fused_slots(int n, int batch, int per_cu, int cus);
 

@@ -32,7 +32,7 @@ SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll
            "lincoll_steady_precondition",
            "lincoll_mlp_create", "lincoll_mlp_destroy", "lincoll_mlp_set_stream", "lincoll_mlp_weights",
            "lincoll_mlp_forward", "lincoll_mlp_loss_grad", "lincoll_mlp_train", "lincoll_learned_features",
-           "lincoll_learned_correction", "lincoll_debug_fail_alloc"]
+           "lincoll_learned_correction", "lincoll_debug_fail_alloc", "lincoll_apply_noalloc"]
 
 
 class LincollError(RuntimeError):
@@ -120,6 +120,7 @@ def _load():
         "lincoll_set_stream": (i, [vp, vp]),
         "lincoll_set_maxwellians": (i, [vp, vp, i]),
         "lincoll_apply": (i, [vp, vp, vp, i]),
+        "lincoll_apply_noalloc": (i, [vp, vp, vp, i]),
         "lincoll_project": (i, [vp, vp, vp, i]),
         "quadcoll_apply": (i, [vp, vp, vp, i]),
         "lincoll_get_info": (i, [vp, i, P(d)]),
@@ -247,6 +248,16 @@ class Plan:
         self._sync_stream()
         _check(_lib.lincoll_apply(self._h, self._dev(h, self.tdtype, (n, n, n), "h"),
                                   self._dev(out, self.tdtype, (n, n, n), "out"), h.shape[0]), "lincoll_apply")
+        return out
+
+    def apply_noalloc(self, h, out):
+        """lincoll_apply_noalloc: out must be preallocated (nothing is
+        allocated, by the library or here)."""
+        n = self.n
+        self._sync_stream()
+        _check(_lib.lincoll_apply_noalloc(self._h, self._dev(h, self.tdtype, (n, n, n), "h"),
+                                          self._dev(out, self.tdtype, (n, n, n), "out"), h.shape[0]),
+               "lincoll_apply_noalloc")
         return out
 
     def project(self, x, y=None):

@@ -1,0 +1,73 @@
+"""lincoll_apply_noalloc (the entry point that allocates nothing) through the
+C ABI against lincoll_apply on the same plan: bitwise equal outputs on two
+calls in a row, the second with a smaller input; no allocation attempted
+(an injected allocation failure stays unused, the plan's and torch's device
+memory unchanged); unsupported configurations rejected."""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
+from test_gpu_parity import mixed_inputs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+@pytest.mark.parametrize("n,big,small", [(32, 300, 37), (16, 1500, 5)])
+def test_noalloc_matches_apply_twice(n, big, small):
+    L, om = 8.0, 0.74
+    lib = lc.library()
+    h, params = mixed_inputs(n, L, big, seed=2900 + n)
+    plan = lc.Plan(n, L, om, "f32")
+    assert plan.info("path") == 2
+    for B in (big, small):
+        print(f"noalloc n={n} batch={B}", flush=True)
+        plan.set_maxwellians(dev(params[:B], torch.float64))
+        x = dev(h[:B], torch.float32)
+        ref = plan.apply(x)
+        out = torch.full_like(x, float("nan"))
+        torch.cuda.synchronize()
+        held = plan.info("device_bytes")
+        torch_held = torch.cuda.memory_allocated(DEV)
+        lib.lincoll_debug_fail_alloc(1)     # any library allocation now fails
+        try:
+            st = lib.lincoll_apply_noalloc(plan._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), B)
+        finally:
+            lib.lincoll_debug_fail_alloc(0)
+        assert st == lc.OK, lc.library().lincoll_strerror(st)
+        torch.cuda.synchronize()
+        assert plan.info("device_bytes") == held
+        assert torch.cuda.memory_allocated(DEV) == torch_held
+        assert torch.equal(out, ref), float((out - ref).abs().max())
+
+
+def test_noalloc_rejects_unsupported_plans():
+    lib = lc.library()
+    n, L, om = 16, 8.0, 0.74
+    x = torch.zeros((2, n, n, n), dtype=torch.float32, device=DEV)
+    y = torch.zeros_like(x)
+    px, py = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    for kw in (dict(path="staged"), dict(project=1)):
+        plan = lc.Plan(n, L, om, "f32", **kw)
+        assert lib.lincoll_apply_noalloc(plan._h, px, py, 2) == lc.EINVAL
+    p64 = lc.Plan(n, L, om, "f64")
+    x64 = torch.zeros((2, n, n, n), dtype=torch.float64, device=DEV)
+    y64 = torch.zeros_like(x64)
+    assert lib.lincoll_apply_noalloc(p64._h, ctypes.c_void_p(x64.data_ptr()), ctypes.c_void_p(y64.data_ptr()), 2) \
+        == lc.EINVAL
+    plan = lc.Plan(n, L, om, "f32")
+    assert lib.lincoll_apply_noalloc(plan._h, px, px, 2) == lc.EINVAL       # aliased
+    assert lib.lincoll_apply_noalloc(plan._h, px, py, 0) == lc.EINVAL       # empty
+    plan.set_maxwellians(torch.tensor([[1, 0, 0, 0, 1.0]] * 3, dtype=torch.float64, device=DEV))
+    assert lib.lincoll_apply_noalloc(plan._h, px, py, 2) == lc.ENOTREADY
