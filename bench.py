@@ -189,20 +189,26 @@ def bench_quadcoll(a, torch, lincoll, dev):
 
 
 def bench_rk4(a, torch, lincoll, dev):
-    """The paper's timed workload (Table 5, Case 1): 100 RK4 steps (dt = 0.1)
-    of df/dt = L[f], n = 32 (N = 16), R = 6, L = (3 + sqrt 2) R / 4, Maxwell
-    molecules (omega = 1, B = 1/(4 pi)), one homogeneous cell, f^(1) initial
-    data, cutoff 1e-9; FP64 unless --dtype says otherwise."""
+    """The paper's timed workload (Table 5): 100 RK4 steps (dt = 0.1) of
+    df/dt = L[f], n = 32 (N = 16), R = 6, L = (3 + sqrt 2) R / 4, one
+    homogeneous cell about the standard Maxwellian, cutoff 1e-9; FP64 unless
+    --dtype says otherwise.  --case 1: Maxwell molecules (omega = 1) from the
+    mass-1 f^(1); --case 2: B2 = g^0.56/(4 pi) (omega = 0.72) from f^(2).
+    After the timed 100 steps another 100 run untimed, and the line reports
+    the L2 distance to M at t = 10 and t = 20 next to Table 4's printed value
+    (t = 20) and the mass drift."""
     from paper_2503_09580_amd import workloads as wl
     n, R = 32, 6.0
     L = (3.0 + math.sqrt(2.0)) * R / 4.0
     dtype = a.dtype if a.dtype in ("f64", "f32") else "f64"
     td = torch.float64 if dtype == "f64" else torch.float32
-    f0 = wl.paper_f1(n, L)[None]
+    case = a.case
+    omega = 1.0 if case == 1 else 0.72
+    f0 = (wl.paper_f1(n, L, unit_mass=True) if case == 1 else wl.paper_f2(n, L))[None]
     stream = torch.cuda.Stream(device=dev)
     steps = 100
     with torch.cuda.stream(stream):
-        plan = lincoll.Plan(n, L, 1.0, dtype, R=R)
+        plan = lincoll.Plan(n, L, omega, dtype, R=R)
         plan.set_option("graph", 1)
         f = torch.from_numpy(f0).to(dev, td)
         plan.rk4(f, 0.1, max(1, a.warmup))
@@ -214,26 +220,37 @@ def bench_rk4(a, torch, lincoll, dev):
         ev1.record(stream)
         ev1.synchronize()
         path = "fused" if plan.info("path") == 2 else "staged"
+        f10 = f.double().cpu().numpy()[0]
+        plan.rk4(f, 0.1, steps)
+        stream.synchronize()
+        f20 = f.double().cpu().numpy()[0]
     ms = ev0.elapsed_time(ev1)
+    h3 = (2.0 * L / n) ** 3
+    M = wl.maxwellian(n, L, 1.0, (0, 0, 0), 1.0)
+    m0 = h3 * f0.sum()
+    table4 = {"dist_t10": math.sqrt(h3 * np.sum((f10 - M) ** 2)), "dist_t20": math.sqrt(h3 * np.sum((f20 - M) ** 2)),
+              "paper_t20": 3.09e-5 if case == 1 else 4.25e-4,
+              "mass_drift_t10": abs(h3 * f10.sum() - m0) / m0, "mass_drift_t20": abs(h3 * f20.sum() - m0) / m0}
     J = n // 2 + 1
-    paper_s = 2.81          # Table 5, Case 1, linearized operator, 100 steps, one CPU thread
+    paper_s = 2.81          # Table 5, linearized operator, double, 100 steps, one CPU thread (both cases)
     value = steps / (ms / 1e3)
     fl = 4 * alg_flops_per_cell(n, J) * steps
     ach = fl / (ms / 1e3) / 1e12
-    rec = {"metric": "RK4 steps/sec of df/dt = L[f] (Table 5, Case 1)", "value": value, "unit": "steps/s",
+    rec = {"metric": f"RK4 steps/sec of df/dt = L[f] (Table 5, Case {case})", "value": value, "unit": "steps/s",
            "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": ms / steps, "higher_is_better": True,
            "scaling": "strong", "vs_baseline": value / (100.0 / paper_s),
            "vs_baseline_note": "paper: 100 steps in 2.81 s on one Intel i7-13800H thread, FP64 (other hardware)",
            "dtype": dtype, "data": "synthetic (closed-form f^(1))",
-           "config": {"workload": f"1 cell, n={n}, R={R:g}, L={L:.4f}, omega=1 (Maxwell), dt=0.1, 100 steps",
-                      "path": path, "graph": 1},
+           "config": {"workload": f"1 cell, n={n}, R={R:g}, L={L:.4f}, omega={omega:g}, "
+                                  f"f^({case}), dt=0.1, 100 steps", "path": path, "graph": 1},
+           "table4": table4,
            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                         "frac": ach / PEAK_VALU_TFLOPS, "traffic": None,
                         "kernel": "lincoll_rk4 (one recorded graph per step)",
                         "note": "one cell cannot fill 256 CUs: latency-bound by construction"}}
     if not a.no_cpu:
         from oracle import fast_direct, timestep
-        plan = fast_direct.make_plan(n, L, 1.0, R=R)
+        plan = fast_direct.make_plan(n, L, omega, R=R)
         p = np.array([[1.0, 0, 0, 0, 1.0]])
         t0 = time.perf_counter()
         k = 0
@@ -406,6 +423,7 @@ def main():
     ap.add_argument("--dtype", default=None, help="f32 (default for apply), f64 (default for rk4), bf16x3")
     ap.add_argument("--path", default="auto")
     ap.add_argument("--config", default="C3")
+    ap.add_argument("--case", type=int, default=1, choices=[1, 2], help="rk4: Sec. 4.2 case")
     ap.add_argument("--inner", default="gmres", choices=["gmres", "source"], help="steady: inner solver")
     ap.add_argument("--kn", type=float, default=1.0, help="couette: Knudsen number")
     ap.add_argument("--uw", type=float, default=0.5, help="couette: wall speed")

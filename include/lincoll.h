@@ -127,7 +127,8 @@ int lincoll_apply_noalloc(lincoll_plan_t plan, const void* h, void* out, int bat
 int lincoll_project(lincoll_plan_t plan, const void* x, void* y, int batch);
 
 /* out[b] = Q(f[b], f[b]), the binary collision operator by the spectral
- * method of Sec. 2.3, eq. (14) (no conservation fix), with the plan's
+ * method of Sec. 2.3, eq. (14) (the mass fix of LINCOLL_OPT_QUAD_FIX, none by
+ * default), with the plan's
  * g-quadrature (W_j, g_j, as for the linearized operator) and a product rule
  * on the hemisphere: the positive nodes of the LINCOLL_OPT_SPHERE_POLAR-point
  * Gauss-Legendre rule (default 8, i.e. 4 polar cosines) times
@@ -153,6 +154,7 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_TUNED_MS 11     /* ms per apply of the configuration lincoll_autotune chose (0 if never run) */
 #define LINCOLL_INFO_L 12            /* half-width L of the velocity box */
 #define LINCOLL_INFO_PROJECT 13      /* 1 if applies return P L P */
+#define LINCOLL_INFO_QUAD_FIX 14     /* mass fix of quadcoll_apply (LINCOLL_OPT_QUAD_FIX) */
 /* Reads one plan property into *val.  With plan == NULL only
  * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
  * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */
@@ -182,6 +184,10 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
 #define LINCOLL_OPT_SPHERE_POLAR 3    /* quadcoll: Gauss-Legendre order on [-1,1] (even, 2..64; positive nodes used) */
 #define LINCOLL_OPT_SPHERE_AZIMUTH 4  /* quadcoll: azimuths (1..256) */
 #define LINCOLL_OPT_PROJECT 5         /* 0 | 1: as lincoll_params_t.project */
+#define LINCOLL_OPT_QUAD_FIX 6        /* quadcoll: mass fix of Sec. 2.3 -- 0 none (default); 1 Q^_0 = 0 (eq. (15)),
+                                         the per-cell mean of Q removed; 2 the sinc of the loss term replaced by
+                                         its estimate on the hemisphere rule (eq. (16)), a [n]^3 FP64 table the
+                                         plan builds on the device once per rule */
 int lincoll_set_option(lincoll_plan_t plan, int key, int value);
 
 /* Launch-configuration tuner: times `reps` applies of every supported

@@ -82,6 +82,12 @@ struct lincoll_plan_s {
   double2 *d_qF = nullptr, *d_qGp = nullptr, *d_qGm = nullptr, *d_qC = nullptr, *d_qS = nullptr, *d_qQ = nullptr;
   double2* d_qPh = nullptr;   // azimuth phase tables of the hemisphere rule
   long cap_qph = 0;           // complex values held by d_qPh
+  int quad_fix = 0;           // mass fix of quadcoll_apply (LINCOLL_OPT_QUAD_FIX)
+  double* d_qOs = nullptr;    // fix 2: loss weight [n][n][n] for the rule (qos_polar, qos_azim)
+  double* d_qGW = nullptr;    // fix 2: (g_j, W_j) [J][2]
+  double* d_qRule = nullptr;  // fix 2: hemisphere rule [M][4]
+  long cap_qrule = 0;
+  int qos_polar = 0, qos_azim = 0;
 };
 
 namespace {
@@ -599,6 +605,10 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       if (value != 0 && value != 1) return LINCOLL_EINVAL;
       pl->p.project = value;
       break;
+    case LINCOLL_OPT_QUAD_FIX:
+      if (value < 0 || value > 2) return LINCOLL_EINVAL;
+      pl->quad_fix = value;
+      break;
     case LINCOLL_OPT_PATH:
       if (value < LINCOLL_PATH_AUTO || value > LINCOLL_PATH_FUSED) return LINCOLL_EINVAL;
       if (value == LINCOLL_PATH_FUSED && !fused_supported(pl->p.n, pl->p.dtype)) return LINCOLL_EINVAL;
@@ -715,6 +725,40 @@ int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
   }
   std::vector<double> st(mu.size());
   for (size_t i = 0; i < mu.size(); ++i) st[i] = std::sqrt(1.0 - mu[i] * mu[i]);
+  if (pl->quad_fix == 2 && (!pl->d_qOs || pl->qos_polar != pl->sphere_polar || pl->qos_azim != pl->sphere_azim)) {
+    // loss weight of eq. (16) for this hemisphere rule, built on the device
+    const int na = pl->sphere_azim, M = (int)mu.size() * na;
+    std::vector<double> rule((size_t)M * 4), gw((size_t)J * 2);
+    for (size_t i = 0; i < mu.size(); ++i)
+      for (int m = 0; m < na; ++m) {
+        const double ph = 2.0 * M_PI * m / na;
+        double* r = &rule[((size_t)i * na + m) * 4];
+        r[0] = st[i] * std::cos(ph);
+        r[1] = st[i] * std::sin(ph);
+        r[2] = mu[i];
+        r[3] = wmu[i] / na;
+      }
+    for (int j = 0; j < J; ++j) {
+      gw[2 * j] = pl->t.g[j];
+      gw[2 * j + 1] = pl->t.W[j];
+    }
+    pl->qos_polar = pl->qos_azim = 0;
+    if (!pl->d_qOs && (e = dalloc(pl, &pl->d_qOs, n3 * sizeof(double)))) return hip_fail(pl, e);
+    if (!pl->d_qGW && (e = dalloc(pl, &pl->d_qGW, (size_t)J * 2 * sizeof(double)))) return hip_fail(pl, e);
+    if ((long)rule.size() > pl->cap_qrule) {
+      if ((e = dalloc(pl, &pl->d_qRule, rule.size() * sizeof(double)))) {
+        pl->cap_qrule = 0;
+        return hip_fail(pl, e);
+      }
+      pl->cap_qrule = (long)rule.size();
+    }
+    if ((e = hipMemcpy(pl->d_qRule, rule.data(), rule.size() * sizeof(double), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(pl->d_qGW, gw.data(), gw.size() * sizeof(double), hipMemcpyHostToDevice)) ||
+        (e = quadcoll_sph_table(n, pl->d_qOs, pl->d_qGW, J, pl->d_qRule, M, pl->p.L, pl->stream)))
+      return hip_fail(pl, e);
+    pl->qos_polar = pl->sphere_polar;
+    pl->qos_azim = pl->sphere_azim;
+  }
   QuadCtx c;
   c.n = n;
   c.J = J;
@@ -740,6 +784,8 @@ int quadcoll_apply(lincoll_plan_t pl, const void* f, void* out, int batch) {
   c.npolar = (int)mu.size();
   c.nazim = pl->sphere_azim;
   c.phase = pl->d_qPh;
+  c.fix = pl->quad_fix;
+  c.Osph = pl->d_qOs;
   if ((e = quadcoll_apply_fp64(c))) return hip_fail(pl, e);
   return LINCOLL_OK;
 }
@@ -852,6 +898,7 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_TUNED_MS: *val = pl->tuned_ms; break;
     case LINCOLL_INFO_L: *val = pl->p.L; break;
     case LINCOLL_INFO_PROJECT: *val = pl->p.project; break;
+    case LINCOLL_INFO_QUAD_FIX: *val = pl->quad_fix; break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;
@@ -867,7 +914,7 @@ void lincoll_destroy(lincoll_plan_t pl) {
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
                   pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin,
                   pl->d_rk_k, pl->d_rk_tmp, pl->d_rk_acc, pl->d_Ws, pl->d_qV, pl->d_qF, pl->d_qGp,
-                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ, pl->d_qPh};
+                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ, pl->d_qPh, pl->d_qOs, pl->d_qGW, pl->d_qRule};
   for (void* p : ptrs) dfree(p);
   delete pl;
 }

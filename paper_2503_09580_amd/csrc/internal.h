@@ -104,7 +104,13 @@ struct QuadCtx {
   const double* wpolar = nullptr;   // host [npolar] polar weights
   int npolar = 0, nazim = 0;
   double2* phase = nullptr;      // [npolar][nazim/2+1][4][n] phase tables of one g-node (quadcoll_phase_count)
+  int fix = 0;                   // mass fix of Sec. 2.3: 0 none, 1 Q^_0 = 0 (eq. (15)), 2 sinc estimated (eq. (16))
+  const double* Osph = nullptr;  // fix 2: [n][n][n] loss weight (quadcoll_sph_table)
 };
+// The loss weight of the second mass fix into tab [n][n][n] (natural order,
+// [kz][kx][ky]); gw = device [J][2] (g_j, W_j), rule = device [nsph][4].
+hipError_t quadcoll_sph_table(int n, double* tab, const double* gw, int J, const double* rule, int nsph, double L,
+                              hipStream_t s);
 // complex values of the phase tables of QuadCtx::phase
 inline long quadcoll_phase_count(int n, int npolar, int nazim) { return (long)npolar * (nazim / 2 + 1) * 4 * n; }
 bool quadcoll_supported(int n);

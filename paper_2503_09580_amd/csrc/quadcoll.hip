@@ -130,12 +130,15 @@ __global__ void __launch_bounds__(128) k_qc_col(const double2* __restrict__ in, 
 // MODE 1: forward of S_j, plain (alias of 0, kept for clarity of the launches).
 // MODE 2: inverse after multiplying by the loss table Omega_u(|k|^2) (plane = kz).
 // MODE 3: inverse, plain.
+// MODE 4: inverse after multiplying by a full table tab[kz][kx][ky] (the
+//         hemisphere-estimated loss weight of the second mass fix, eq. (16)).
 template <int NN, int MODE>
 __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in, double2* __restrict__ out,
                                                   const double* __restrict__ tab, int nplanes) {
   constexpr int NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
   constexpr bool INV = MODE >= 2;
   __shared__ double2 lds[PPB * NN * LD];
+  static_assert(MODE >= 0 && MODE <= 4, "k_qc_plane mode");
   const int lp = threadIdx.x / NN, a = threadIdx.x % NN;
   const long pid = (long)blockIdx.x * PPB + lp;
   const bool active = pid < nplanes;
@@ -153,6 +156,15 @@ __global__ void __launch_bounds__(64) k_qc_plane(const double2* __restrict__ in,
       static_for<0, NN>([&](auto k1) {
         constexpr int f1 = k1 <= NN / 2 ? k1 : NN - k1;
         const double m = tab[f1 * f1 + fa * fa + kz * kz];
+        vr[k1] *= m;
+        vi[k1] *= m;
+      });
+    }
+    if constexpr (MODE == 4) {
+      // element [k1][a] of plane kz is (kx, ky) = (k1, a)
+      const double* t3 = tab + (size_t)(pid % NN) * NP + a;
+      static_for<0, NN>([&](auto k1) {
+        const double m = t3[(size_t)k1 * NN];
         vr[k1] *= m;
         vi[k1] *= m;
       });
@@ -329,6 +341,50 @@ __global__ void __launch_bounds__(2 * NN) k_qc_azim(const double2* __restrict__ 
   });
 }
 
+// Loss weight of the second mass fix (eq. (16)): the sinc of the loss term
+// replaced by its estimate on the hemisphere rule,
+//   tab[kz][kx][ky] = 16 pi^2 / n^3 sum_j W_j sum_m w_m cos(pi g_j sigma_m . p / L)
+// with p the signed frequency of (kx, ky, kz); gw = [J][2] (g_j, W_j),
+// rule = [nsph][4] (sigma_m, w_m).
+template <int NN>
+__global__ void __launch_bounds__(256) k_qc_sph_table(double* __restrict__ tab, const double* __restrict__ gw,
+                                                       int J, const double* __restrict__ rule, int nsph, double L) {
+  constexpr int NP = NN * NN;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NN * NP) return;
+  const double pz = sgn_idx<NN>(i / NP), px = sgn_idx<NN>((i / NN) % NN), py = sgn_idx<NN>(i % NN);
+  double acc = 0.0;
+  for (int j = 0; j < J; ++j) {
+    const double a = M_PI * gw[2 * j] / L;
+    double sj = 0.0;
+    for (int m = 0; m < nsph; ++m) {
+      const double* r = rule + 4 * m;
+      sj += r[3] * cos(a * (r[0] * px + r[1] * py + r[2] * pz));
+    }
+    acc += gw[2 * j + 1] * sj;
+  }
+  tab[i] = 16.0 * M_PI * M_PI / ((double)NN * NP) * acc;
+}
+
+// First mass fix (eq. (15)): Q^_0 = 0, i.e. the per-cell mean of the point
+// values removed.  One block per cell, FP64 sums in a fixed order.
+template <int NN>
+__global__ void __launch_bounds__(256) k_qc_remove_mean(double* __restrict__ q) {
+  constexpr int N3 = NN * NN * NN;
+  __shared__ double red[256];
+  double* qc = q + (size_t)blockIdx.x * N3;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < N3; i += 256) s += qc[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = red[0] / N3;
+  for (int i = threadIdx.x; i < N3; i += 256) qc[i] -= mean;
+}
+
 template <int NN>
 hipError_t quadcoll_n(const QuadCtx& c) {
   constexpr int NP = NN * NN;
@@ -339,8 +395,14 @@ hipError_t quadcoll_n(const QuadCtx& c) {
   // F = DFT3[f]: along z, then in-plane
   k_qc_col<NN, 0><<<gc, 128, 0, s>>>(nullptr, Fk, nullptr, c.f, nullptr, nullptr, nullptr, 0, 0, ZPhase{}, 0, B);
   k_qc_plane<NN, 0><<<gp, 64, 0, s>>>(Fk, Fk, nullptr, nplanes);
-  // loss: V = Re iDFT_u[Omega_u F] (into the output buffer's shadow V)
-  k_qc_plane<NN, 2><<<gp, 64, 0, s>>>(Fk, C, c.Om64, nplanes);
+  // loss: V = Re iDFT_u[Omega_u F] (into the output buffer's shadow V); with
+  // the second mass fix the weight is the hemisphere estimate of eq. (16)
+  if (c.fix == 2) {
+    if (!c.Osph) return hipErrorInvalidValue;
+    k_qc_plane<NN, 4><<<gp, 64, 0, s>>>(Fk, C, c.Osph, nplanes);
+  } else {
+    k_qc_plane<NN, 2><<<gp, 64, 0, s>>>(Fk, C, c.Om64, nplanes);
+  }
   k_qc_col<NN, 3><<<gc, 128, 0, s>>>(C, nullptr, nullptr, nullptr, c.V, nullptr, nullptr, 0, 0, ZPhase{}, 0, B);
   if (c.npolar < 1 || c.npolar > 32 || c.nazim < 1 || !c.phase) return hipErrorInvalidValue;
   const int npair = c.nazim / 2 + 1;
@@ -366,12 +428,29 @@ hipError_t quadcoll_n(const QuadCtx& c) {
   // Q = 16 pi^2 / n^3 Re iDFT_u[Qk] - f V
   k_qc_plane<NN, 3><<<gp, 64, 0, s>>>(Qk, Qk, nullptr, nplanes);
   k_qc_col<NN, 4><<<gc, 128, 0, s>>>(Qk, nullptr, nullptr, c.f, c.out, c.V, nullptr, 0, 0, ZPhase{}, 0, B);
+  if (c.fix == 1) k_qc_remove_mean<NN><<<B, 256, 0, s>>>(c.out);
+  return hipGetLastError();
+}
+
+template <int NN>
+hipError_t sph_table_n(double* tab, const double* gw, int J, const double* rule, int nsph, double L, hipStream_t s) {
+  k_qc_sph_table<NN><<<(NN * NN * NN + 255) / 256, 256, 0, s>>>(tab, gw, J, rule, nsph, L);
   return hipGetLastError();
 }
 
 }  // namespace
 
 bool quadcoll_supported(int n) { return n == 8 || n == 16 || n == 32; }
+
+hipError_t quadcoll_sph_table(int n, double* tab, const double* gw, int J, const double* rule, int nsph, double L,
+                              hipStream_t s) {
+  switch (n) {
+    case 8: return sph_table_n<8>(tab, gw, J, rule, nsph, L, s);
+    case 16: return sph_table_n<16>(tab, gw, J, rule, nsph, L, s);
+    case 32: return sph_table_n<32>(tab, gw, J, rule, nsph, L, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t quadcoll_apply_fp64(const QuadCtx& c) {
   switch (c.n) {

@@ -174,10 +174,12 @@ def burnett(n, L, nn, l):
     return maxwellian(n, L, 1.0, (0, 0, 0), 1.0) * rad * ang
 
 
-def paper_f1(n, L):
-    """Initial/test distribution f^(1) of Sec. 4 (Cases of Sec. 4.1-4.2) as
-    printed: four shifted Gaussians, u = sqrt 2, theta = 1/3, prefactor
-    1/(4 pi^(3/2)) (its mass is (2/3)^(3/2), see the readings)."""
+def paper_f1(n, L, unit_mass=False):
+    """Initial/test distribution f^(1) of Sec. 4 (Cases of Sec. 4.1-4.2):
+    four shifted Gaussians, u = sqrt 2, theta = 1/3.  With the printed
+    prefactor 1/(4 pi^(3/2)) its mass is (2/3)^(3/2); unit_mass=True uses
+    (3/(2 pi))^(3/2)/4 instead, the mass-1 form that relaxes to the standard
+    Maxwellian (as the time-stepping experiments of Sec. 4.2 need)."""
     v = axis(n, L)
     VX, VY, VZ = np.meshgrid(v, v, v, indexing="ij")
     u, th = math.sqrt(2.0), 1.0 / 3.0
@@ -185,7 +187,23 @@ def paper_f1(n, L):
     def e(a, b):
         return np.exp(-((VX + a) ** 2 + (VY + b) ** 2 + VZ ** 2) / (2 * th))
 
-    return (e(u, 0) + e(-u, 0) + e(0, u) + e(0, -u)) / (4 * math.pi ** 1.5)
+    pref = (3.0 / (2.0 * math.pi)) ** 1.5 / 4.0 if unit_mass else 1.0 / (4 * math.pi ** 1.5)
+    return (e(u, 0) + e(-u, 0) + e(0, u) + e(0, -u)) * pref
+
+
+def paper_f2(n, L):
+    """The discontinuous distribution f^(2) of Sec. 4: a narrow Gaussian
+    (variance 1/sqrt 2 per axis) for v1 > 0 and a wide one (variance sqrt 2)
+    at a quarter of the prefactor for v1 < 0, prefactor
+    2^(1/4) (2 - sqrt 2) / pi^(3/2); mass 1, velocity 0, temperature 1.  On
+    the grid plane v1 = 0 it takes the mean of the two one-sided values."""
+    v = axis(n, L)
+    VX, VY, VZ = np.meshgrid(v, v, v, indexing="ij")
+    r2 = VX ** 2 + VY ** 2 + VZ ** 2
+    a = 2.0 ** 0.25 * (2.0 - math.sqrt(2.0)) / math.pi ** 1.5
+    pos = a * np.exp(-r2 / math.sqrt(2.0))
+    neg = 0.25 * a * np.exp(-r2 / (2.0 * math.sqrt(2.0)))
+    return np.where(VX > 0, pos, np.where(VX < 0, neg, 0.5 * (pos + neg)))
 
 
 def slab_state(n, L, nx, theta_l=1.0, theta_r=1.5, seed=404, amp=0.05):

@@ -93,3 +93,32 @@ def test_quadcoll_errors():
     y = torch.zeros((1, 64, 64, 64), dtype=torch.float64, device=DEV)
     z = torch.zeros_like(y)
     assert lib.quadcoll_apply(big._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(z.data_ptr()), 1) == lc.ENOTIMPL
+
+
+@pytest.mark.parametrize("n,L,polar,azim,fix", [
+    (8, 4.0, 4, 3, 1), (8, 4.0, 4, 3, 2), (16, 4.5, 4, 5, 1), (16, 4.5, 4, 5, 2), (16, 8.0, 8, 16, 2),
+    (32, 8.0, 4, 6, 1), (32, 8.0, 4, 6, 2)])
+def test_quadcoll_mass_fixes_match_oracle(n, L, polar, azim, fix):
+    """The mass fixes of Sec. 2.3 (LINCOLL_OPT_QUAD_FIX): 1 = Q^_0 set to 0
+    (eq. (15)), 2 = the loss sinc replaced by its hemisphere estimate
+    (eq. (16)), against O2 with the same fix at 1e-12; fix 1 conserves mass
+    to round-off.  The plan switches fixes and rules between calls."""
+    h, params = mixed_inputs(n, L, 2, seed=1800 + n + fix)
+    f = h + np.stack([wl.maxwellian(n, L, q[0], q[1:4], q[4]) for q in params])
+    plan = lc.Plan(n, L, 0.74, "f64")
+    plan.set_option("sphere_polar", polar)
+    plan.set_option("sphere_azimuth", azim)
+    fdev = torch.from_numpy(np.ascontiguousarray(f)).to(DEV, torch.float64)
+    plain = plan.quadcoll(fdev).cpu().numpy()
+    plan.set_option("quad_fix", fix)
+    assert plan.info("quad_fix") == fix
+    got = plan.quadcoll(fdev).cpu().numpy()
+    fd_plan = fd.make_plan(n, L, 0.74)
+    sphere = quadrature.hemisphere_product_rule(polar, azim)
+    for b in range(2):
+        ref = binary.q_binary(fd_plan, sphere, f[b], f[b], method="fast", fix=fix)
+        check(got[b], ref, 1e-12, tag=(fix, b))
+        if fix == 1:
+            assert abs(got[b].sum()) < 1e-13 * np.abs(got[b]).sum()
+    plan.set_option("quad_fix", 0)
+    assert np.array_equal(plan.quadcoll(fdev).cpu().numpy(), plain)

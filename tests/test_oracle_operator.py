@@ -315,3 +315,31 @@ def test_self_adjointness_defect_shrinks_with_resolution():
         # non-positivity of the quadratic form
         assert np.sum((a * La / M)[w]) < 1e-3 * np.sum((a * a / M)[w])
     assert defects[1] < defects[0]
+
+
+def test_binary_mass_fixes_restore_mass():
+    """Sec. 2.3, eqs. (15)-(16): the binary method conserves mass only when
+    the bracket of eq. (15) vanishes, i.e. when the hemisphere rule
+    integrates cos(pi g sigma.l / L) exactly.  On a coarse rule and a
+    resolved f (h_v = 0.56, Nyquist coefficients ~1e-8):
+    - fix 1 (Q^_0 = 0) makes the sum of the point values vanish to round-off;
+    - fix 2 (the loss sinc replaced by the same rule's estimate, eq. (16))
+      leaves only the Nyquist terms of the cyclic index reduction, shrinking
+      the mass defect by more than 1e4;
+    - on a fine rule (8 x 16) fix 2 changes the result by little."""
+    n, L = 16, 4.5
+    p = fd.make_plan(n, L, 0.74)
+    f = wl.maxwellian(n, L, 1.0, (0.3, -0.2, 0.1), 0.9) + 0.5 * wl.maxwellian(n, L, 0.7, (-0.5, 0.4, 0.0), 1.3)
+    for pol, az in [(4, 3), (4, 5)]:
+        sph = quadrature.hemisphere_product_rule(pol, az)
+        q0, q1, q2 = (binary.q_binary(p, sph, f, f, "fast", fix) for fix in (0, 1, 2))
+        scale = np.abs(q0).sum()
+        assert abs(q0.sum()) > 1e-3 * scale                 # the unfixed rule loses mass
+        assert abs(q1.sum()) < 1e-14 * scale
+        assert abs(q2.sum()) < 1e-4 * abs(q0.sum())
+        # fix 1 only shifts every point value by the same constant
+        d = q1 - q0
+        assert np.max(np.abs(d - d.mean())) < 1e-14 * np.max(np.abs(q0))
+    sph = quadrature.hemisphere_product_rule(8, 16)
+    q0, q2 = (binary.q_binary(p, sph, f, f, "fast", fix) for fix in (0, 2))
+    assert np.linalg.norm(q2 - q0) < 1e-3 * np.linalg.norm(q0)
