@@ -335,8 +335,8 @@ def bench_steady(a, torch, lincoll, dev):
     extra = {}
     with torch.cuda.stream(stream):
         plan = lincoll.Plan(n, L, om, dtype)
-        if a.graph is not None:
-            plan.set_option("graph", a.graph)
+        graph = 1 if a.graph is None else a.graph     # each GMRES cycle replays one recorded graph
+        plan.set_option("graph", graph)
         f = torch.empty((nx, n, n, n), dtype=torch.float64, device=dev)
         if precond == "learned":
             # training data from plain solves at wall temperatures spread over [1.1, 2.0],
@@ -358,8 +358,21 @@ def bench_steady(a, torch, lincoll, dev):
                                        precond="learned", mlp=net)
             extra = {"train_rows": used, "train_loss": loss, "train_thetas": [round(float(t), 4) for t in thetas],
                      "train_s": time.perf_counter() - t0}
+            # the same solver without the network (sweep preconditioner, same dtype), timed alike:
+            # what the learned start gains or loses by itself
+            sps = lincoll.steady_params(nx, kn=c["kn"], theta_l=c["theta_l"], theta_r=c["theta_r"], mass=c["mass"])
+            plan.steady_solve(sps, f)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                reps_s = plan.steady_solve(sps, f)
+            stream.synchronize()
+            extra["sweep_same_dtype_s"] = (time.perf_counter() - t0) / steps
+            extra["sweep_same_dtype_inner_iters"] = reps_s["inner_iters"]
+            extra["sweep_same_dtype_residual"] = reps_s["residual"]
             # the plain FP64 solver (sweep preconditioner) on the same problem, timed alike
             plan64 = lincoll.Plan(n, L, om, "f64")
+            plan64.set_option("graph", graph)
             sp64 = lincoll.steady_params(nx, kn=c["kn"], theta_l=c["theta_l"], theta_r=c["theta_r"], mass=c["mass"])
             plan64.steady_solve(sp64, f)
             stream.synchronize()
@@ -391,6 +404,7 @@ def bench_steady(a, torch, lincoll, dev):
            "data": "synthetic (closed-form initial guess)",
            "config": {"workload": f"{nx} cells x n={n}^3 velocities, box [-{L:g},{L:g})^3, omega={om}, Kn={c['kn']}, "
                                   f"walls theta 1/1.5, tol 1e-5", "precond": precond, "inner": a.inner,
+                      "graph": graph,
                       "newton_iters": rep["newton_iters"], "inner_iters": rep["inner_iters"],
                       "residual": rep["residual"], "res_history": rep["res_history"],
                       "ms_residual": rep["ms_residual"], "ms_inner": rep["ms_inner"], "ms_total": rep["ms_total"],

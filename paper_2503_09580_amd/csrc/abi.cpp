@@ -88,6 +88,9 @@ struct lincoll_plan_s {
   double* d_qRule = nullptr;  // fix 2: hemisphere rule [M][4]
   long cap_qrule = 0;
   int qos_polar = 0, qos_azim = 0;
+  // steady solver work memory (plan_steady_work)
+  void* d_steady = nullptr;
+  size_t cap_steady = 0;
 };
 
 namespace {
@@ -430,8 +433,10 @@ int lincoll_set_maxwellians(lincoll_plan_t pl, const double* params, int batch) 
 
 namespace {
 
-hipError_t launch_project(lincoll_plan_t pl, const void* x, void* y, int batch, hipStream_t stream) {
+hipError_t launch_project(lincoll_plan_t pl, const void* x, void* y, int batch, hipStream_t stream,
+                          const int* gate = nullptr) {
   ProjectCtx c;
+  c.gate = gate;
   c.n = pl->p.n;
   c.batch = batch;
   c.Bc = pl->Bc;
@@ -489,16 +494,18 @@ ApplyCtx apply_ctx(lincoll_plan_t pl, const void* hin, void* out, int batch, hip
 
 // Every launch of one apply, on `stream` (the plan's stream, or the capture
 // stream while a replayable graph is recorded).  Work buffers must exist.
-hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, hipStream_t stream) {
+hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, hipStream_t stream,
+                        const int* gate = nullptr) {
   hipError_t e;
   const void* hin = h;
   if (pl->p.project) {
-    if ((e = launch_project(pl, h, pl->d_pin, batch, stream))) return e;
+    if ((e = launch_project(pl, h, pl->d_pin, batch, stream, gate))) return e;
     hin = pl->d_pin;
   }
-  const ApplyCtx c = apply_ctx(pl, hin, out, batch, stream);
+  ApplyCtx c = apply_ctx(pl, hin, out, batch, stream);
+  c.gate = gate;
   if ((e = use_fused(pl) ? fused_apply(c) : staged_apply(c))) return e;
-  if (pl->p.project) return launch_project(pl, out, out, batch, stream);
+  if (pl->p.project) return launch_project(pl, out, out, batch, stream, gate);
   return hipSuccess;
 }
 
@@ -863,6 +870,41 @@ int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
 }  // extern "C"
 
 namespace lincoll {
+int plan_apply_on(lincoll_plan_s* pl, const void* h, void* out, int batch, hipStream_t s, const int* gate) {
+  int st = checked_apply_args(pl, h, out, batch);
+  if (st) return st;
+  if ((st = ensure_work(pl, batch))) return st;
+  const hipError_t e = launch_apply(pl, h, out, batch, s, gate);
+  return e ? hip_fail(pl, e) : LINCOLL_OK;
+}
+
+int plan_ensure_work(lincoll_plan_s* pl, int batch) { return ensure_work(pl, batch); }
+
+hipError_t plan_capture_stream(lincoll_plan_s* pl, hipStream_t* s) {
+  if (!pl->cap_stream) {
+    const hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    if (e) return e;
+  }
+  *s = pl->cap_stream;
+  return hipSuccess;
+}
+
+int plan_graph_option(const lincoll_plan_s* pl) { return pl->opt_graph; }
+
+void* plan_steady_work(lincoll_plan_s* pl, size_t bytes, int* status) {
+  *status = LINCOLL_OK;
+  if (bytes > pl->cap_steady || !pl->d_steady) {
+    pl->cap_steady = 0;
+    const hipError_t e = dalloc(pl, &pl->d_steady, bytes);
+    if (e) {
+      *status = hip_fail(pl, e);
+      return nullptr;
+    }
+    pl->cap_steady = bytes;
+  }
+  return pl->d_steady;
+}
+
 hipStream_t plan_stream(const lincoll_plan_s* pl) { return pl->stream; }
 const void* plan_nu(const lincoll_plan_s* pl) { return pl->d_nu; }
 void plan_note_hip(lincoll_plan_s* pl, hipError_t e) {
@@ -914,7 +956,7 @@ void lincoll_destroy(lincoll_plan_t pl) {
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
                   pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin,
                   pl->d_rk_k, pl->d_rk_tmp, pl->d_rk_acc, pl->d_Ws, pl->d_qV, pl->d_qF, pl->d_qGp,
-                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ, pl->d_qPh, pl->d_qOs, pl->d_qGW, pl->d_qRule};
+                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ, pl->d_qPh, pl->d_qOs, pl->d_qGW, pl->d_qRule, pl->d_steady};
   for (void* p : ptrs) dfree(p);
   delete pl;
 }

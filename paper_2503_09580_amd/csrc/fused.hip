@@ -298,8 +298,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     const float* __restrict__ h, float* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
     const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
     const float* __restrict__ nu, const float* __restrict__ Phi, const float* __restrict__ Om,
-    double2* __restrict__ slots, int J) {
+    double2* __restrict__ slots, int J, const int* __restrict__ gate) {
   using C = Cfg<NN>;
+  if (gate && *gate == 0) return;   // a gated-off step of the device-resident GMRES
   constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, PW = 64 / NN, LD = C::LD;
   __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
   __shared__ double fs[9 * NN + 3];
@@ -545,11 +546,11 @@ hipError_t fused_apply(const ApplyCtx& c) {
   switch (c.n) {
     case 16:
       k_fused<16><<<slots, Cfg<16>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
-                                                       Phi, Om, scr, c.J);
+                                                       Phi, Om, scr, c.J, c.gate);
       break;
     case 32:
       k_fused<32><<<slots, Cfg<32>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
-                                                       Phi, Om, scr, c.J);
+                                                       Phi, Om, scr, c.J, c.gate);
       break;
     default:
       return hipErrorInvalidValue;

@@ -14,6 +14,22 @@ void plan_note_hip(lincoll_plan_s* pl, hipError_t e);   // records e as the plan
 // Loss collision frequency nu = iDFT[Omega DFT[M]] of the Maxwellians set,
 // [Bc][n^3], double for LINCOLL_F64 plans and float otherwise.
 const void* plan_nu(const lincoll_plan_s* pl);
+// lincoll_apply's checks and launches on stream s, never through a recorded
+// graph (so that a caller can record it into a graph of its own), with the
+// fused kernel and the projections gated by *gate (nullptr: always run).
+// Work buffers are allocated here if needed: call once outside any capture.
+int plan_apply_on(lincoll_plan_s* pl, const void* h, void* out, int batch, hipStream_t s, const int* gate);
+// The apply work buffers for batch cells (lincoll_apply allocates them on
+// first use; a caller that records launches into a graph calls this first).
+int plan_ensure_work(lincoll_plan_s* pl, int batch);
+// A stream the plan owns for recording graphs (created on first use).
+hipError_t plan_capture_stream(lincoll_plan_s* pl, hipStream_t* s);
+// 1 if the plan replays recorded graphs (LINCOLL_OPT_GRAPH).
+int plan_graph_option(const lincoll_plan_s* pl);
+// Device work memory of the steady solver, owned by the plan and kept between
+// calls (grown when a call needs more; freed with the plan).  Returns null and
+// sets *status on failure.
+void* plan_steady_work(lincoll_plan_s* pl, size_t bytes, int* status);
 
 // Row strides of the device mode tables (K_j octants and Phi_j radial
 // tables), padded to whole blocks of 512 values so that the fused kernel copies
@@ -30,6 +46,7 @@ struct ApplyCtx {
   int cus = 256;               // compute units of the device
   int per_cu = 0;              // fused path: workgroups per compute unit (0 = default)
   int max_slots = 0;           // fused path: cap on the persistent workgroups (0 = none)
+  const int* gate = nullptr;   // fused path: the kernel does nothing unless *gate != 0 (device flag)
   int dtype = 0;
   hipStream_t stream = nullptr;
   const void* h = nullptr;
@@ -85,6 +102,7 @@ struct ProjectCtx {
   const double* fac64 = nullptr;
   const double* pref64 = nullptr;
   const double* Ainv = nullptr;
+  const int* gate = nullptr;       // nothing is done unless *gate != 0
 };
 
 // Binary operator Q(f, f) (eq. (14)), FP64.

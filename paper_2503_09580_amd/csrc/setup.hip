@@ -232,7 +232,9 @@ template <typename T>
 __global__ void __launch_bounds__(PROJ_TB) k_project(const T* x, T* y, int n, int lgn,
                                                      double L, const double* __restrict__ fac64,
                                                      const double* __restrict__ pref64,
-                                                     const double* __restrict__ Ainv, int Bc) {
+                                                     const double* __restrict__ Ainv, int Bc,
+                                                     const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double red[5][PROJ_TB];
   __shared__ double coef[5];
   const int cell = blockIdx.x, cc = Bc > 1 ? cell : 0;
@@ -281,10 +283,10 @@ hipError_t project_cells(const ProjectCtx& c) {
   if ((1 << lgn) != c.n) return hipErrorInvalidValue;
   if (c.dtype == 0)
     k_project<double><<<c.batch, PROJ_TB, 0, c.stream>>>(static_cast<const double*>(c.x), static_cast<double*>(c.y),
-                                                          c.n, lgn, c.L, c.fac64, c.pref64, c.Ainv, c.Bc);
+                                                          c.n, lgn, c.L, c.fac64, c.pref64, c.Ainv, c.Bc, c.gate);
   else
     k_project<float><<<c.batch, PROJ_TB, 0, c.stream>>>(static_cast<const float*>(c.x), static_cast<float*>(c.y), c.n,
-                                                         lgn, c.L, c.fac64, c.pref64, c.Ainv, c.Bc);
+                                                         lgn, c.L, c.fac64, c.pref64, c.Ainv, c.Bc, c.gate);
   return hipGetLastError();
 }
 

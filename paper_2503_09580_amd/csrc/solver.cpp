@@ -1,14 +1,20 @@
 // Steady 1-D problem with diffuse walls (Sec. 5, Appendix B): residual,
 // modified Newton operator and the modified Newton iteration with restarted
-// GMRES as the inner solver.  Host orchestration only; the operator
-// applications are the library's own entry points (quadcoll_apply for the
-// residual, lincoll_apply with the invariant projection inside the Newton
-// operator) and the remaining steps are the kernels of steady.hip.
+// flexible GMRES as the inner solver.  Host orchestration of device work: the
+// operator applications are the library's own (quadcoll_apply for the
+// residual, the linearized apply with the invariant projection inside the
+// Newton operator) and the remaining steps are the kernels of steady.hip.
+// GMRES keeps its bookkeeping on the device (steady.h, GmresState): a whole
+// restart cycle is one fixed sequence of launches, gated by device flags once
+// the cycle has converged, recorded into a hipGraph once per solve and
+// replayed (LINCOLL_OPT_GRAPH), with one host read of the state per cycle.
+// Work memory belongs to the plan and is kept between calls.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -80,35 +86,43 @@ struct Solver {
   double f_sum = 0.0;              // its plain sum (mass / (dx h^3))
   bool project_set = false;
   long matvecs = 0;
-  std::vector<void*> owned;
+  // Work memory carved from the plan's steady-solver buffer.
+  char* carve_at = nullptr;
+  size_t carve_left = 0;
   // small buffers
   double *d_sums = nullptr, *d_ysums = nullptr, *d_params = nullptr, *d_wall = nullptr;
-  double *d_partial = nullptr, *d_red = nullptr, *d_y = nullptr;
+  double *d_partial = nullptr, *d_red = nullptr, *d_y = nullptr, *d_ifsum = nullptr;
+  GmresState* d_gm = nullptr;
   // learned correction: moments, scale, features, network output
   double *d_m5 = nullptr, *d_scale = nullptr;
   float *d_X = nullptr, *d_Y = nullptr;
   int rec_rows = 0;
   // fields of N values
-  double* d_q = nullptr;   // Q(f, f)
-  void* d_in = nullptr;    // apply input (plan dtype)
-  void* d_o = nullptr;     // apply output (plan dtype)
+  double* d_q = nullptr;     // Q(f, f)
+  double* d_aux = nullptr;   // a spare field (lincoll_steady_residual without an output)
+  void* d_in = nullptr;      // apply input (plan dtype)
+  void* d_o = nullptr;       // apply output (plan dtype)
+  // solve only: residual, correction, restart scratch, Krylov bases
+  double *d_r = nullptr, *d_g = nullptr, *d_tmp = nullptr, *d_V = nullptr, *d_Z = nullptr;
+  // the recorded GMRES cycle of this solve (LINCOLL_OPT_GRAPH)
+  hipGraphExec_t cycle = nullptr;
 
   ~Solver() {
-    if (pl) (void)hipStreamSynchronize(s);   // also the null stream: work may still read these buffers
-    for (void* p : owned) (void)hipFree(p);
+    if (pl) (void)hipStreamSynchronize(s);   // work may still read the plan's buffers
+    if (cycle) (void)hipGraphExecDestroy(cycle);
     if (project_set) (void)lincoll_set_option(pl, LINCOLL_OPT_PROJECT, project_before);
   }
 
+  static size_t rnd(size_t b) { return (b + 255) / 256 * 256; }
+
   template <typename P>
-  int alloc(P** p, size_t bytes) {
-    void* q = nullptr;
-    HIPCK(hipMalloc(&q, bytes));
-    owned.push_back(q);
-    *p = static_cast<P*>(q);
-    return LINCOLL_OK;
+  void carve(P** p, size_t bytes) {
+    *p = reinterpret_cast<P*>(carve_at);
+    carve_at += rnd(bytes);
+    carve_left -= rnd(bytes);
   }
 
-  int init(lincoll_plan_t plan, const lincoll_steady_params_t* params) {
+  int init(lincoll_plan_t plan, const lincoll_steady_params_t* params, bool full = false) {
     pl = plan;
     if (!pl) return LINCOLL_EINVAL;
     STCK(check_params(params));
@@ -150,18 +164,44 @@ struct Solver {
       if (acc == 0.0) return LINCOLL_EINVAL;
       wg.flux_in[w] = acc;
     }
-    const size_t nb = vec_blocks(N);
-    STCK(alloc(&d_sums, (size_t)nx * SUMS_STRIDE * sizeof(double)));
-    STCK(alloc(&d_ysums, (size_t)nx * SUMS_STRIDE * sizeof(double)));
-    STCK(alloc(&d_params, (size_t)nx * 5 * sizeof(double)));
-    STCK(alloc(&d_wall, 8 * sizeof(double)));
-    STCK(alloc(&d_partial, nb * GMRES_MAXK * sizeof(double)));
-    STCK(alloc(&d_red, (GMRES_MAXK + 1) * sizeof(double)));
-    STCK(alloc(&d_y, GMRES_MAXK * sizeof(double)));
-    STCK(alloc(&d_m5, (size_t)nx * 5 * sizeof(double)));
-    STCK(alloc(&d_scale, sizeof(double)));
-    STCK(alloc(&d_X, (size_t)nx * MLP_IN * sizeof(float)));
-    STCK(alloc(&d_Y, (size_t)nx * MLP_OUT * sizeof(float)));
+    // one block of plan memory for everything this call needs
+    const size_t nb = vec_blocks(N), es = dtype == LINCOLL_F64 ? sizeof(double) : sizeof(float);
+    const size_t vec = (size_t)N * sizeof(double);
+    const size_t sizes[] = {(size_t)nx * SUMS_STRIDE * 8, (size_t)nx * SUMS_STRIDE * 8, (size_t)nx * 5 * 8, 8 * 8,
+                            nb * GMRES_MAXK * 8, (GMRES_MAXK + 1) * 8, GMRES_MAXK * 8, 8, sizeof(GmresState),
+                            (size_t)nx * 5 * 8, 8, (size_t)nx * MLP_IN * 4, (size_t)nx * MLP_OUT * 4,
+                            vec, vec, (size_t)N * es, (size_t)N * es};
+    size_t total = 0;
+    for (size_t b : sizes) total += rnd(b);
+    if (full) total += rnd(vec) * (3 + 2 * (size_t)sp.restart + 1);
+    int st = LINCOLL_OK;
+    carve_at = static_cast<char*>(plan_steady_work(pl, total, &st));
+    if (!carve_at) return st;
+    carve_left = total;
+    carve(&d_sums, sizes[0]);
+    carve(&d_ysums, sizes[1]);
+    carve(&d_params, sizes[2]);
+    carve(&d_wall, sizes[3]);
+    carve(&d_partial, sizes[4]);
+    carve(&d_red, sizes[5]);
+    carve(&d_y, sizes[6]);
+    carve(&d_ifsum, sizes[7]);
+    carve(&d_gm, sizes[8]);
+    carve(&d_m5, sizes[9]);
+    carve(&d_scale, sizes[10]);
+    carve(&d_X, sizes[11]);
+    carve(&d_Y, sizes[12]);
+    carve(&d_q, sizes[13]);
+    carve(&d_aux, sizes[14]);
+    carve(&d_in, sizes[15]);
+    carve(&d_o, sizes[16]);
+    if (full) {
+      carve(&d_r, vec);
+      carve(&d_g, vec);
+      carve(&d_tmp, vec);
+      carve(&d_V, vec * (sp.restart + 1));
+      carve(&d_Z, vec * sp.restart);
+    }
     return LINCOLL_OK;
   }
 
@@ -179,7 +219,6 @@ struct Solver {
 
   // r = T[f] - (Q(f,f) - mean Q)/Kn; *norm = sqrt(dx h^3 |r|^2)
   int residual(const double* f, double* r, double* norm) {
-    if (!d_q) STCK(alloc(&d_q, (size_t)N * sizeof(double)));
     STCK(quadcoll_apply(pl, f, d_q, nx));
     HIPCK(st_cell_sums(d_q, nx, n, L, d_ysums, s));
     HIPCK(st_wall_sums(f, nx, n, L, d_wall, s));
@@ -207,6 +246,7 @@ struct Solver {
     f_cur = f;
     f_sum = 0.0;
     for (int c = 0; c < nx; ++c) f_sum += hp[(size_t)c * 5] / h3;
+    HIPCK(st_set(d_ifsum, 1.0 / f_sum, s));
     for (int c = 0; c < nx; ++c) {
       const double* q = &hp[(size_t)c * 5];
       if (!finite_pos(q[0]) || !finite_pos(q[4]) || !std::isfinite(q[1]) || !std::isfinite(q[2]) ||
@@ -221,22 +261,18 @@ struct Solver {
     return LINCOLL_OK;
   }
 
-  // out = T[x] - P L P x / Kn about the Maxwellians set by set_local
-  int matvec(const double* x, double* out) {
-    if (!d_o) {
-      const size_t es = dtype == LINCOLL_F64 ? sizeof(double) : sizeof(float);
-      STCK(alloc(&d_in, (size_t)N * es));
-      STCK(alloc(&d_o, (size_t)N * es));
-    }
-    // the apply always reads the same buffer, so a recorded graph replays
+  // out = T[x] - P L P x / Kn about the Maxwellians set by set_local; with a
+  // gate, nothing is written unless *gate != 0 (on the staged path the
+  // linearized apply itself still runs)
+  int matvec(const double* x, double* out, const int* gate = nullptr) {
     if (dtype == LINCOLL_F64)
-      HIPCK(st_axpby(static_cast<double*>(d_in), 1.0, x, 0.0, nullptr, N, s));
+      HIPCK(st_axpby(static_cast<double*>(d_in), 1.0, x, 0.0, nullptr, N, s, gate));
     else
-      HIPCK(st_to_f32(x, static_cast<float*>(d_in), N, s));
-    STCK(lincoll_apply(pl, d_in, d_o, nx));
-    HIPCK(st_wall_sums(x, nx, n, L, d_wall, s));
-    HIPCK(st_transport(x, d_wall, wg, d_o, dtype != LINCOLL_F64, -1.0 / sp.kn, nullptr, out, nx, n, L, dx, s));
-    ++matvecs;
+      HIPCK(st_to_f32(x, static_cast<float*>(d_in), N, s, gate));
+    STCK(plan_apply_on(pl, d_in, d_o, nx, s, gate));
+    HIPCK(st_wall_sums(x, nx, n, L, d_wall, s, gate));
+    HIPCK(st_transport(x, d_wall, wg, d_o, dtype != LINCOLL_F64, -1.0 / sp.kn, nullptr, out, nx, n, L, dx, s, gate));
+    if (!gate) ++matvecs;
     return LINCOLL_OK;
   }
 
@@ -260,8 +296,8 @@ struct Solver {
   // preconditioned vector at zero mass (removing its total along the current
   // iterate f) keeps the inner solution on it: the correction is then well
   // defined (and learnable) and the Newton update preserves the mass.
-  int zero_mass(double* z) {
-    HIPCK(st_remove_mass(z, f_cur, f_sum, N, d_partial, d_red, s));
+  int zero_mass(double* z, const int* gate = nullptr) {
+    HIPCK(st_remove_mass(z, f_cur, d_ifsum, N, d_partial, d_red, s, gate));
     return LINCOLL_OK;
   }
 
@@ -270,13 +306,13 @@ struct Solver {
   double inner_atol() const { return std::min(sp.inner_atol, 0.01 * sp.tol); }
 
   // z = M^-1 v, the right preconditioner (z = v without one)
-  int precondition(const double* v, double* z) {
+  int precondition(const double* v, double* z, const int* gate = nullptr) {
     if (sp.precond == LINCOLL_PRECOND_NONE) {
-      HIPCK(st_axpby(z, 1.0, v, 0.0, nullptr, N, s));
+      HIPCK(st_axpby(z, 1.0, v, 0.0, nullptr, N, s, gate));
       return LINCOLL_OK;
     }
-    HIPCK(st_sweep(v, z, plan_nu(pl), dtype != LINCOLL_F64, d_wall, wg, nx, n, L, dx, sp.kn, s));
-    return zero_mass(z);
+    HIPCK(st_sweep(v, z, plan_nu(pl), dtype != LINCOLL_F64, d_wall, wg, nx, n, L, dx, sp.kn, s, gate));
+    return zero_mass(z, gate);
   }
 
   // features of z (about d_params) into X, scale into d_scale
@@ -365,89 +401,85 @@ struct Solver {
     return LINCOLL_OK;
   }
 
-  // With x0 set, x holds the starting guess on entry and V[0] its residual
-  // b - A x (the tolerance stays relative to |b|); start counts operator
-  // evaluations already spent on the start.
-  int gmres(const double* b, double bnorm, double* x, double* V, double* Z, double* tmp, int* iters, bool x0 = false,
-            long start = -1) {
+  // One restart cycle of flexible GMRES, as a fixed sequence of launches on s:
+  // the restart product and V0, then `restart` Arnoldi steps (preconditioner,
+  // operator, classical Gram-Schmidt, Givens update on the device), the back
+  // substitution and x += Z y.  Device flags make the launches after
+  // convergence (or of a finished solve) return at once.
+  int cycle_launches(const double* b, double* x, double* V, double* Z, double* tmp) {
     const int m = sp.restart;
+    const int* go = &d_gm->go;
+    const int* act = &d_gm->active;
+    STCK(matvec(x, tmp, &d_gm->pro));
+    HIPCK(gm_v0(V, b, tmp, d_gm, N, s));
+    HIPCK(st_mdot(V, N, 1, V, d_partial, d_red, s, go));
+    HIPCK(gm_begin(d_gm, d_red, s));
+    HIPCK(st_scale_dev(V, &d_gm->inv, N, act, s));
+    for (int j = 0; j < m; ++j) {
+      double* w = V + (long)(j + 1) * N;
+      double* zj = Z + (long)j * N;
+      STCK(precondition(V + (long)j * N, zj, act));
+      STCK(matvec(zj, w, act));
+      HIPCK(st_mdot(V, N, j + 1, w, d_partial, d_red, s, act));
+      HIPCK(st_update(w, V, N, j + 1, d_red, d_partial, d_red + (j + 1), s, act));
+      HIPCK(gm_step(d_gm, d_red, j, s));
+      HIPCK(st_scale_dev(w, &d_gm->inv, N, act, s));
+    }
+    HIPCK(gm_end(d_gm, s));
+    HIPCK(st_combine_dev(x, Z, N, &d_gm->j, d_gm->y, go, s));
+    HIPCK(gm_finish(d_gm, s));
+    return LINCOLL_OK;
+  }
+
+  // Runs one cycle: replays the recorded graph (recording it on first use,
+  // on a stream the plan owns) or launches the same sequence directly.
+  int run_cycle(const double* b, double* x, double* V, double* Z, double* tmp) {
+    if (!plan_graph_option(pl)) return cycle_launches(b, x, V, Z, tmp);
+    if (!cycle) {
+      hipStream_t cap = nullptr, s0 = s;
+      HIPCK(plan_capture_stream(pl, &cap));
+      HIPCK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      s = cap;
+      const int st = cycle_launches(b, x, V, Z, tmp);
+      s = s0;
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(cap, &g);
+      if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (!e) e = hipGraphInstantiate(&cycle, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e) cycle = nullptr;
+      HIPCK(e);
+    }
+    HIPCK(hipGraphLaunch(cycle, s));
+    return LINCOLL_OK;
+  }
+
+  // Restarted flexible GMRES for A x = b with right preconditioning
+  // (A M^-1 u = b, x = M^-1 u; the preconditioned vectors Z are kept, so M
+  // may change between iterations) and classical Gram-Schmidt.  Stops when
+  // the weighted residual <= max(inner_rtol |b|, inner_atol) or after
+  // max_inner operator evaluations.  Without x0, x starts at 0; with x0, x
+  // holds the start and V[0] its residual b - A x (the tolerance stays
+  // relative to |b|), and `spent` operator evaluations count against the
+  // budget.  V: restart + 1 vectors, Z: restart vectors, tmp: one.
+  int gmres(const double* b, double bnorm, double* x, double* V, double* Z, double* tmp, int* iters, bool x0 = false,
+            int spent = 0) {
     const double target = std::max(sp.inner_rtol * bnorm * wnorm, inner_atol()) / wnorm;   // plain norm
-    if (start < 0) start = matvecs;
-    double beta = bnorm;
-    *iters = 0;
-    if (x0) {
-      double bb = 0.0;
-      STCK(dot(V, V, &bb));
-      beta = std::sqrt(bb);
-      if (!(beta > target)) {
-        *iters = (int)(matvecs - start);
-        return LINCOLL_OK;
-      }
-      HIPCK(st_axpby(V, 1.0 / beta, V, 0.0, nullptr, N, s));
-    } else {
-      HIPCK(hipMemsetAsync(x, 0, (size_t)N * sizeof(double), s));
-      if (!(beta > target)) return LINCOLL_OK;
-      HIPCK(st_axpby(V, 1.0 / beta, b, 0.0, nullptr, N, s));
-    }
-    std::vector<double> R((size_t)m * m, 0.0), cs(m), sn(m), g(m + 1), col(m + 2), y(m);
+    STCK(plan_ensure_work(pl, nx));   // no allocation may happen while a cycle is recorded
+    if (!x0) HIPCK(hipMemsetAsync(x, 0, (size_t)N * sizeof(double), s));
+    HIPCK(gm_init(d_gm, sp.restart, target, sp.max_inner, x0 ? 1 : 0, spent, s));
+    GmresState h;
     for (;;) {
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
-      int j = 0;
-      bool stop = false;
-      while (j < m) {
-        double* w = V + (long)(j + 1) * N;
-        double* zj = Z + (long)j * N;
-        STCK(precondition(V + (long)j * N, zj));
-        STCK(matvec(zj, w));
-        HIPCK(st_mdot(V, N, j + 1, w, d_partial, d_red, s));
-        HIPCK(st_update(w, V, N, j + 1, d_red, d_partial, d_red + (j + 1), s));
-        STCK(host_copy(col.data(), d_red, (size_t)(j + 2) * sizeof(double)));
-        const double hn = std::sqrt(std::max(col[j + 1], 0.0));
-        col[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-          const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-          col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-          col[i] = t;
-        }
-        const double rr = std::hypot(col[j], col[j + 1]);
-        cs[j] = rr > 0.0 ? col[j] / rr : 1.0;
-        sn[j] = rr > 0.0 ? col[j + 1] / rr : 0.0;
-        col[j] = rr;
-        for (int i = 0; i <= j; ++i) R[(size_t)i * m + j] = col[i];
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        const double resid = std::fabs(g[j + 1]);
-        ++j;
-        if (!(hn > 0.0) || !std::isfinite(resid)) {   // breakdown (exact) or non-finite values
-          stop = true;
-          break;
-        }
-        HIPCK(st_axpby(w, 1.0 / hn, w, 0.0, nullptr, N, s));
-        if (resid <= target || matvecs - start >= sp.max_inner) {
-          stop = true;
-          break;
-        }
-      }
-      for (int i = j - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int k = i + 1; k < j; ++k) t -= R[(size_t)i * m + k] * y[k];
-        y[i] = t / R[(size_t)i * m + i];
-      }
-      HIPCK(hipMemcpyAsync(d_y, y.data(), (size_t)j * sizeof(double), hipMemcpyHostToDevice, s));
-      HIPCK(st_combine(x, Z, N, j, d_y, s));
-      HIPCK(hipStreamSynchronize(s));   // y is read from host memory
-      if (stop || matvecs - start >= sp.max_inner) break;
-      // restart from the true residual b - A x
-      STCK(matvec(x, tmp));
-      HIPCK(st_axpby(V, 1.0, b, -1.0, tmp, N, s));
-      double bb = 0.0;
-      STCK(dot(V, V, &bb));
-      beta = std::sqrt(bb);
-      if (!(beta > target) || matvecs - start >= sp.max_inner) break;
-      HIPCK(st_axpby(V, 1.0 / beta, V, 0.0, nullptr, N, s));
+      STCK(run_cycle(b, x, V, Z, tmp));
+      HIPCK(hipMemcpyAsync(&h, d_gm, offsetof(GmresState, cs), hipMemcpyDeviceToHost, s));
+      HIPCK(hipStreamSynchronize(s));
+      if (!h.go) break;
     }
-    *iters = (int)(matvecs - start);
+    *iters = h.iters;
+    matvecs += h.iters - spent;
     return LINCOLL_OK;
   }
 
@@ -455,12 +487,7 @@ struct Solver {
     const clk::time_point t0 = clk::now();
     lincoll_steady_report_t rp;
     std::memset(&rp, 0, sizeof(rp));
-    double *r = nullptr, *gcor = nullptr, *V = nullptr, *Z = nullptr, *tmp = nullptr;
-    STCK(alloc(&r, (size_t)N * sizeof(double)));
-    STCK(alloc(&gcor, (size_t)N * sizeof(double)));
-    STCK(alloc(&tmp, (size_t)N * sizeof(double)));
-    STCK(alloc(&V, (size_t)(sp.restart + 1) * N * sizeof(double)));
-    STCK(alloc(&Z, (size_t)sp.restart * N * sizeof(double)));
+    double *r = d_r, *gcor = d_g, *V = d_V, *Z = d_Z, *tmp = d_tmp;
     if (sp.init) HIPCK(st_initial(f, nx, n, L, sp.x_l, sp.x_r, sp.theta_l, sp.theta_r, sp.mass, s));
     int status = constrain(f, nullptr);
     double res_prev = 0.0, lambda = 1.0;
@@ -503,7 +530,7 @@ struct Solver {
       if (sp.inner == LINCOLL_INNER_SOURCE) {
         if ((status = source_iteration(r, res / wnorm, gcor, V, V + N, &its))) break;
       } else if ((learned && (status = learned_start(r, gcor, V, Z))) ||
-                 (status = gmres(r, res / wnorm, gcor, V, Z, tmp, &its, learned, mv0))) {
+                 (status = gmres(r, res / wnorm, gcor, V, Z, tmp, &its, learned, (int)(matvecs - mv0)))) {
         break;
       }
       if ((status = record(r, gcor, tmp))) break;
@@ -572,8 +599,7 @@ int lincoll_steady_residual(lincoll_plan_t plan, const lincoll_steady_params_t* 
   Solver S;
   STCK(S.init(plan, sp));
   if (r && overlap(f, r, (size_t)S.N * sizeof(double))) return LINCOLL_EINVAL;
-  double* out = r;
-  if (!out) STCK(S.alloc(&out, (size_t)S.N * sizeof(double)));
+  double* out = r ? r : S.d_aux;
   double v = 0.0;
   STCK(S.residual(f, out, &v));
   lincoll_plan_t pl = plan;
@@ -638,7 +664,7 @@ int lincoll_steady_solve(lincoll_plan_t plan, const lincoll_steady_params_t* sp,
                          lincoll_steady_report_t* rep) {
   if (!plan || !f) return LINCOLL_EINVAL;
   Solver S;
-  STCK(S.init(plan, sp));
+  STCK(S.init(plan, sp, true));
   return S.solve(f, rep);
 }
 

@@ -92,7 +92,8 @@ __global__ void k_params(const double* __restrict__ sums, int nx, double h3, dou
 // path) reads them plane by plane.
 constexpr int TBW = 1024;
 __global__ void __launch_bounds__(TBW) k_wall_sums(const double* __restrict__ x, int n, int nx, double L, double hv,
-                                                   double* __restrict__ wall) {
+                                                   double* __restrict__ wall, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int n2 = n * n;
   const long n3 = (long)n2 * n;
   const bool left = blockIdx.x == 0;
@@ -129,7 +130,9 @@ template <typename T>
 __global__ void __launch_bounds__(TB) k_transport(const double* __restrict__ x, const double* __restrict__ wall,
                                                   WallGeom wg, const T* __restrict__ y, double alpha,
                                                   const double* __restrict__ ysums, double* __restrict__ out, int n,
-                                                  int nx, double L, double hv, double dx) {
+                                                  int nx, double L, double hv, double dx,
+                                                  const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const long n3 = (long)n * n * n, total = (long)nx * n3;
   const int lgn = 31 - __builtin_clz(n), msk = n - 1;   // n is a power of two
   const double rdx = 1.0 / dx;
@@ -187,7 +190,8 @@ __global__ void __launch_bounds__(SWEEP_VEL * SWEEP_CHUNKS) k_sweep(const double
                                                                     const TN* __restrict__ nu,
                                                                     const double* __restrict__ wall, WallGeom wg,
                                                                     int n, int nx, double L, double hv, double dx,
-                                                                    double kn) {
+                                                                    double kn, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double cA[SWEEP_CHUNKS][SWEEP_VEL], cB[SWEEP_CHUNKS][SWEEP_VEL];
   const long n2 = (long)n * n, n3 = n2 * n;
   const long count = NEG ? (long)(n / 2 + 1) * n2 : (long)(n / 2 - 1) * n2;
@@ -259,7 +263,8 @@ __device__ __forceinline__ long vec_index(int r) { return ((long)blockIdx.x * EP
 
 // partial[b][i] = block b's part of <V_i, w>, i < k
 __global__ void __launch_bounds__(TB) k_mdot(const double* __restrict__ V, long N, int k, const double* __restrict__ w,
-                                             double* __restrict__ partial) {
+                                             double* __restrict__ partial, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double sm[GMRES_MAXK][WAVES];
   double wr[EPT];
 #pragma unroll
@@ -289,7 +294,8 @@ __global__ void __launch_bounds__(TB) k_mdot(const double* __restrict__ V, long 
 
 // out[a] = sum over blocks of partial[b][a], a < k (one block per a)
 __global__ void __launch_bounds__(TB) k_reduce_cols(const double* __restrict__ partial, int nblk,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int a = blockIdx.x;
   double v[1] = {0.0};
   for (int b = threadIdx.x; b < nblk; b += TB) v[0] += partial[(long)b * GMRES_MAXK + a];
@@ -299,7 +305,9 @@ __global__ void __launch_bounds__(TB) k_reduce_cols(const double* __restrict__ p
 
 // w -= sum_{a<k} h[a] V_a; partial[b][0] = block b's part of |w|^2
 __global__ void __launch_bounds__(TB) k_update(double* __restrict__ w, const double* __restrict__ V, long N, int k,
-                                               const double* __restrict__ h, double* __restrict__ partial) {
+                                               const double* __restrict__ h, double* __restrict__ partial,
+                                               const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   double v[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
@@ -315,9 +323,12 @@ __global__ void __launch_bounds__(TB) k_update(double* __restrict__ w, const dou
   if (threadIdx.x == 0) partial[(long)blockIdx.x * GMRES_MAXK] = v[0];
 }
 
-// x += sum_{a<k} y[a] V_a
+// x += sum_{a<k} y[a] V_a, with k = *kdev when kdev is set
 __global__ void __launch_bounds__(TB) k_combine(double* __restrict__ x, const double* __restrict__ V, long N, int k,
-                                                const double* __restrict__ y) {
+                                                const double* __restrict__ y, const int* __restrict__ kdev,
+                                                const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  if (kdev) k = *kdev;
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     const long i = vec_index(r);
@@ -330,7 +341,9 @@ __global__ void __launch_bounds__(TB) k_combine(double* __restrict__ x, const do
 }
 
 // partial[b][0] = block b's part of sum x
-__global__ void __launch_bounds__(TB) k_sum(const double* __restrict__ x, long N, double* __restrict__ partial) {
+__global__ void __launch_bounds__(TB) k_sum(const double* __restrict__ x, long N, double* __restrict__ partial,
+                                            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   double v[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
@@ -341,10 +354,12 @@ __global__ void __launch_bounds__(TB) k_sum(const double* __restrict__ x, long N
   if (threadIdx.x == 0) partial[(long)blockIdx.x * GMRES_MAXK] = v[0];
 }
 
-// z -= (*sz / fmass) f
+// z -= (*sz * *ifmass) f
 __global__ void __launch_bounds__(TB) k_remove_mass(double* __restrict__ z, const double* __restrict__ f,
-                                                    const double* __restrict__ sz, double ifmass, long N) {
-  const double c = *sz * ifmass;
+                                                    const double* __restrict__ sz, const double* __restrict__ ifmass,
+                                                    long N, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const double c = *sz * *ifmass;
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     const long i = vec_index(r);
@@ -354,7 +369,8 @@ __global__ void __launch_bounds__(TB) k_remove_mass(double* __restrict__ z, cons
 
 // out = a x + b y (y may be null: out = a x); out may alias x or y
 __global__ void __launch_bounds__(TB) k_axpby(double* out, double a, const double* x, double b, const double* y,
-                                              long N) {
+                                              long N, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     const long i = vec_index(r);
@@ -362,7 +378,9 @@ __global__ void __launch_bounds__(TB) k_axpby(double* out, double a, const doubl
   }
 }
 
-__global__ void __launch_bounds__(TB) k_to_f32(const double* __restrict__ x, float* __restrict__ y, long N) {
+__global__ void __launch_bounds__(TB) k_to_f32(const double* __restrict__ x, float* __restrict__ y, long N,
+                                               const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     const long i = vec_index(r);
@@ -390,13 +408,13 @@ hipError_t st_params(const double* sums, int nx, int n, double L, double* params
   return hipGetLastError();
 }
 
-hipError_t st_wall_sums(const double* x, int nx, int n, double L, double* wall, hipStream_t s) {
-  k_wall_sums<<<2, TBW, 0, s>>>(x, n, nx, L, 2.0 * L / n, wall);
+hipError_t st_wall_sums(const double* x, int nx, int n, double L, double* wall, hipStream_t s, const int* gate) {
+  k_wall_sums<<<2, TBW, 0, s>>>(x, n, nx, L, 2.0 * L / n, wall, gate);
   return hipGetLastError();
 }
 
 hipError_t st_sweep(const double* y, double* z, const void* nu, int nu_f32, double* wall, const WallGeom& wg, int nx,
-                    int n, double L, double dx, double kn, hipStream_t s) {
+                    int n, double L, double dx, double kn, hipStream_t s, const int* gate) {
   const double hv = 2.0 * L / n;
   const long n2 = (long)n * n;
   const unsigned bneg = (unsigned)(((n / 2 + 1) * n2 + SWEEP_VEL - 1) / SWEEP_VEL),
@@ -404,29 +422,29 @@ hipError_t st_sweep(const double* y, double* z, const void* nu, int nu_f32, doub
   constexpr int TBS = SWEEP_VEL * SWEEP_CHUNKS;
   if (nu_f32) {
     const float* q = static_cast<const float*>(nu);
-    k_sweep<float, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
-    k_wall_sums<<<1, TBW, 0, s>>>(z, n, nx, L, hv, wall);
-    k_sweep<float, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<float, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn, gate);
+    k_wall_sums<<<1, TBW, 0, s>>>(z, n, nx, L, hv, wall, gate);
+    k_sweep<float, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn, gate);
   } else {
     const double* q = static_cast<const double*>(nu);
-    k_sweep<double, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
-    k_wall_sums<<<1, TBW, 0, s>>>(z, n, nx, L, hv, wall);
-    k_sweep<double, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn);
+    k_sweep<double, true><<<bneg, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn, gate);
+    k_wall_sums<<<1, TBW, 0, s>>>(z, n, nx, L, hv, wall, gate);
+    k_sweep<double, false><<<bpos, TBS, 0, s>>>(y, z, q, wall, wg, n, nx, L, hv, dx, kn, gate);
   }
   return hipGetLastError();
 }
 
 hipError_t st_transport(const double* x, const double* wall, const WallGeom& wg, const void* y, int y_f32,
                         double alpha, const double* ysums, double* out, int nx, int n, double L, double dx,
-                        hipStream_t s) {
+                        hipStream_t s, const int* gate) {
   const long total = (long)nx * n * n * n;
   const double hv = 2.0 * L / n;
   if (y_f32)
     k_transport<float><<<grid_stride_blocks(total), TB, 0, s>>>(x, wall, wg, static_cast<const float*>(y), alpha,
-                                                                ysums, out, n, nx, L, hv, dx);
+                                                                ysums, out, n, nx, L, hv, dx, gate);
   else
     k_transport<double><<<grid_stride_blocks(total), TB, 0, s>>>(x, wall, wg, static_cast<const double*>(y), alpha,
-                                                                 ysums, out, n, nx, L, hv, dx);
+                                                                 ysums, out, n, nx, L, hv, dx, gate);
   return hipGetLastError();
 }
 
@@ -437,42 +455,232 @@ hipError_t st_initial(double* f, int nx, int n, double L, double x_l, double x_r
   return hipGetLastError();
 }
 
-hipError_t st_mdot(const double* V, long N, int k, const double* w, double* partial, double* out, hipStream_t s) {
+hipError_t st_mdot(const double* V, long N, int k, const double* w, double* partial, double* out, hipStream_t s,
+                   const int* gate) {
   const unsigned nb = vec_blocks(N);
-  k_mdot<<<nb, TB, 0, s>>>(V, N, k, w, partial);
-  k_reduce_cols<<<k, TB, 0, s>>>(partial, (int)nb, out);
+  k_mdot<<<nb, TB, 0, s>>>(V, N, k, w, partial, gate);
+  k_reduce_cols<<<k, TB, 0, s>>>(partial, (int)nb, out, gate);
   return hipGetLastError();
 }
 
 hipError_t st_update(double* w, const double* V, long N, int k, const double* h, double* partial, double* norm2,
-                     hipStream_t s) {
+                     hipStream_t s, const int* gate) {
   const unsigned nb = vec_blocks(N);
-  k_update<<<nb, TB, 0, s>>>(w, V, N, k, h, partial);
-  k_reduce_cols<<<1, TB, 0, s>>>(partial, (int)nb, norm2);
+  k_update<<<nb, TB, 0, s>>>(w, V, N, k, h, partial, gate);
+  k_reduce_cols<<<1, TB, 0, s>>>(partial, (int)nb, norm2, gate);
   return hipGetLastError();
 }
 
 hipError_t st_combine(double* x, const double* V, long N, int k, const double* y, hipStream_t s) {
-  k_combine<<<vec_blocks(N), TB, 0, s>>>(x, V, N, k, y);
+  k_combine<<<vec_blocks(N), TB, 0, s>>>(x, V, N, k, y, nullptr, nullptr);
   return hipGetLastError();
 }
 
-hipError_t st_axpby(double* out, double a, const double* x, double b, const double* y, long N, hipStream_t s) {
-  k_axpby<<<vec_blocks(N), TB, 0, s>>>(out, a, x, b, y, N);
+hipError_t st_axpby(double* out, double a, const double* x, double b, const double* y, long N, hipStream_t s,
+                    const int* gate) {
+  k_axpby<<<vec_blocks(N), TB, 0, s>>>(out, a, x, b, y, N, gate);
   return hipGetLastError();
 }
 
-hipError_t st_remove_mass(double* z, const double* f, double fsum, long N, double* partial, double* red,
-                          hipStream_t s) {
+hipError_t st_remove_mass(double* z, const double* f, const double* ifsum, long N, double* partial, double* red,
+                          hipStream_t s, const int* gate) {
   const unsigned nb = vec_blocks(N);
-  k_sum<<<nb, TB, 0, s>>>(z, N, partial);
-  k_reduce_cols<<<1, TB, 0, s>>>(partial, (int)nb, red);
-  k_remove_mass<<<nb, TB, 0, s>>>(z, f, red, 1.0 / fsum, N);
+  k_sum<<<nb, TB, 0, s>>>(z, N, partial, gate);
+  k_reduce_cols<<<1, TB, 0, s>>>(partial, (int)nb, red, gate);
+  k_remove_mass<<<nb, TB, 0, s>>>(z, f, red, ifsum, N, gate);
   return hipGetLastError();
 }
 
-hipError_t st_to_f32(const double* x, float* y, long N, hipStream_t s) {
-  k_to_f32<<<vec_blocks(N), TB, 0, s>>>(x, y, N);
+hipError_t st_to_f32(const double* x, float* y, long N, hipStream_t s, const int* gate) {
+  k_to_f32<<<vec_blocks(N), TB, 0, s>>>(x, y, N, gate);
+  return hipGetLastError();
+}
+
+// ---- restarted flexible GMRES with its bookkeeping on the device -----------
+// One thread does the O(m) Givens work of an Arnoldi step and the O(m^2)
+// back substitution of a cycle; the vector kernels of a step are gated by
+// st->active, those of a cycle by st->go, and the restart product by st->pro,
+// so a whole cycle can be replayed as one recorded graph and the host reads
+// the state once per cycle.
+
+namespace {
+
+__global__ void k_gm_init(GmresState* st, int m, double target, int budget, int mode, int iters0) {
+  st->m = m;
+  st->j = 0;
+  st->iters = iters0;
+  st->budget = budget;
+  st->mode = mode;
+  st->go = 1;
+  st->active = 0;
+  st->pro = 0;
+  st->done = 0;
+  st->target = target;
+  st->beta = 0.0;
+  st->resid = 0.0;
+  st->inv = 1.0;
+}
+
+// V0 = b (mode 0, start x = 0), kept (mode 1: it holds the residual of the
+// given start) or b - A x (mode 2, restarts; tmp = A x)
+__global__ void __launch_bounds__(TB) k_gm_v0(double* __restrict__ V0, const double* __restrict__ b,
+                                              const double* __restrict__ tmp, const GmresState* __restrict__ st,
+                                              long N) {
+  if (!st->go || st->mode == 1) return;
+  const bool rs = st->mode == 2;
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const long i = vec_index(r);
+    if (i < N) V0[i] = rs ? b[i] - tmp[i] : b[i];
+  }
+}
+
+// red[0] = |V0|^2: start of a cycle
+__global__ void k_gm_begin(GmresState* st, const double* red) {
+  if (!st->go) return;
+  if (st->pro) ++st->iters;   // the restart product A x
+  const double beta = sqrt(red[0]);
+  st->beta = beta;
+  st->resid = beta;
+  if (!(beta > st->target) || (st->pro && st->iters >= st->budget)) {
+    st->go = 0;
+    st->done = 1;
+    st->active = 0;
+    st->j = 0;
+    st->pro = 0;
+    return;
+  }
+  st->pro = 0;
+  for (int i = 0; i <= st->m; ++i) st->g[i] = 0.0;
+  st->g[0] = beta;
+  st->inv = 1.0 / beta;
+  st->j = 0;
+  st->active = 1;
+}
+
+// Step j: red[0..j] = <V_i, w>, red[j + 1] = |w|^2 after the Gram-Schmidt
+// update.  Applies the previous rotations to the new column, forms the next
+// one, updates g and the residual estimate |g[j+1]|.
+__global__ void k_gm_step(GmresState* st, const double* red, int j) {
+  if (!st->active) return;
+  const int m = st->m;
+  ++st->iters;
+  double col[GMRES_MAXK + 1];
+  for (int i = 0; i <= j + 1; ++i) col[i] = red[i];
+  const double hn = sqrt(fmax(col[j + 1], 0.0));
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
+    col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double rr = hypot(col[j], col[j + 1]);
+  st->cs[j] = rr > 0.0 ? col[j] / rr : 1.0;
+  st->sn[j] = rr > 0.0 ? col[j + 1] / rr : 0.0;
+  col[j] = rr;
+  for (int i = 0; i <= j; ++i) st->R[i * m + j] = col[i];
+  st->g[j + 1] = -st->sn[j] * st->g[j];
+  st->g[j] = st->cs[j] * st->g[j];
+  const double resid = fabs(st->g[j + 1]);
+  st->resid = resid;
+  st->j = j + 1;
+  if (!(hn > 0.0) || !isfinite(resid)) {   // breakdown (exact) or non-finite values
+    st->active = 0;
+    st->done = 1;
+    st->inv = 1.0;
+    return;
+  }
+  st->inv = 1.0 / hn;
+  if (resid <= st->target || st->iters >= st->budget) {
+    st->active = 0;
+    st->done = 1;
+  }
+}
+
+// back substitution R y = g over the st->j columns of this cycle
+__global__ void k_gm_end(GmresState* st) {
+  if (!st->go) return;
+  const int m = st->m, j = st->j;
+  for (int i = j - 1; i >= 0; --i) {
+    double t = st->g[i];
+    for (int k = i + 1; k < j; ++k) t -= st->R[i * m + k] * st->y[k];
+    st->y[i] = t / st->R[i * m + i];
+  }
+}
+
+// after the cycle's combine: restart (mode 2) unless done or out of budget
+__global__ void k_gm_finish(GmresState* st) {
+  if (!st->go) return;
+  st->active = 0;
+  if (st->done || st->iters >= st->budget) {
+    st->done = 1;
+    st->go = 0;
+    st->pro = 0;
+  } else {
+    st->mode = 2;
+    st->pro = 1;
+  }
+}
+
+// x *= *a
+__global__ void __launch_bounds__(TB) k_scale_dev(double* __restrict__ x, const double* __restrict__ a, long N,
+                                                  const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const double c = *a;
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const long i = vec_index(r);
+    if (i < N) x[i] *= c;
+  }
+}
+
+__global__ void k_set(double* dst, double v) { *dst = v; }
+
+}  // namespace
+
+hipError_t gm_init(GmresState* st, int m, double target, int budget, int mode, int iters0, hipStream_t s) {
+  k_gm_init<<<1, 1, 0, s>>>(st, m, target, budget, mode, iters0);
+  return hipGetLastError();
+}
+
+hipError_t gm_v0(double* V0, const double* b, const double* tmp, const GmresState* st, long N, hipStream_t s) {
+  k_gm_v0<<<vec_blocks(N), TB, 0, s>>>(V0, b, tmp, st, N);
+  return hipGetLastError();
+}
+
+hipError_t gm_begin(GmresState* st, const double* red, hipStream_t s) {
+  k_gm_begin<<<1, 1, 0, s>>>(st, red);
+  return hipGetLastError();
+}
+
+hipError_t gm_step(GmresState* st, const double* red, int j, hipStream_t s) {
+  k_gm_step<<<1, 1, 0, s>>>(st, red, j);
+  return hipGetLastError();
+}
+
+hipError_t gm_end(GmresState* st, hipStream_t s) {
+  k_gm_end<<<1, 1, 0, s>>>(st);
+  return hipGetLastError();
+}
+
+hipError_t gm_finish(GmresState* st, hipStream_t s) {
+  k_gm_finish<<<1, 1, 0, s>>>(st);
+  return hipGetLastError();
+}
+
+hipError_t st_scale_dev(double* x, const double* a, long N, const int* gate, hipStream_t s) {
+  k_scale_dev<<<vec_blocks(N), TB, 0, s>>>(x, a, N, gate);
+  return hipGetLastError();
+}
+
+hipError_t st_combine_dev(double* x, const double* V, long N, const int* k, const double* y, const int* gate,
+                          hipStream_t s) {
+  k_combine<<<vec_blocks(N), TB, 0, s>>>(x, V, N, 0, y, k, gate);
+  return hipGetLastError();
+}
+
+hipError_t st_set(double* dst, double v, hipStream_t s) {
+  k_set<<<1, 1, 0, s>>>(dst, v);
   return hipGetLastError();
 }
 
