@@ -562,7 +562,10 @@ def main():
             plan.set_option("graph", a.graph)
         path = "fused" if plan.info("path") == 2 else "staged"
         launch = {"path": path, "graph": int(plan.info("graph")), "tuned_ms": tuned_ms,
-                  "fused_per_cu": int(plan.info("fused_per_cu")) if path == "fused" else None}
+                  "fused_per_cu": int(plan.info("fused_per_cu")) if path == "fused" else None,
+                  "staged_zblock": int(plan.info("zblock")) if path == "staged" else None,
+                  "staged_plane_tile": int(plan.info("plane_tile")) if path == "staged" else None,
+                  "tuner": "lincoll_autotune over path x workgroups/CU x staged tiles x graph"}
         for _ in range(a.warmup):
             plan.apply(ht, out)
         stream.synchronize()

@@ -155,6 +155,9 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_L 12            /* half-width L of the velocity box */
 #define LINCOLL_INFO_PROJECT 13      /* 1 if applies return P L P */
 #define LINCOLL_INFO_QUAD_FIX 14     /* mass fix of quadcoll_apply (LINCOLL_OPT_QUAD_FIX) */
+#define LINCOLL_INFO_ZBLOCK 15       /* staged path: threads per block of the z-pass kernels */
+#define LINCOLL_INFO_PLANE_TILE 16   /* staged path: in-plane tile (0: 64 threads, 1: 32 threads per block) */
+#define LINCOLL_INFO_TUNE_CACHED 17  /* 1 if the last lincoll_autotune took its result from the cache */
 /* Reads one plan property into *val.  With plan == NULL only
  * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
  * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */
@@ -184,6 +187,10 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
 #define LINCOLL_OPT_SPHERE_POLAR 3    /* quadcoll: Gauss-Legendre order on [-1,1] (even, 2..64; positive nodes used) */
 #define LINCOLL_OPT_SPHERE_AZIMUTH 4  /* quadcoll: azimuths (1..256) */
 #define LINCOLL_OPT_PROJECT 5         /* 0 | 1: as lincoll_params_t.project */
+#define LINCOLL_OPT_ZBLOCK 7          /* staged path: threads per block of the z-pass kernels, 64 | 128 (default) | 256 */
+#define LINCOLL_OPT_PLANE_TILE 8      /* staged path: in-plane kernels with 64 (0, default) or 32 (1, n <= 32)
+                                         threads per block, i.e. 64/n or 32/n planes per block */
+#define LINCOLL_OPT_TUNE_CACHE 9      /* 1 (default): lincoll_autotune reuses a cached result; 0: always times */
 #define LINCOLL_OPT_QUAD_FIX 6        /* quadcoll: mass fix of Sec. 2.3 -- 0 none (default); 1 Q^_0 = 0 (eq. (15)),
                                          the per-cell mean of Q removed; 2 the sinc of the loss term replaced by
                                          its estimate on the hemisphere rule (eq. (16)), a [n]^3 FP64 table the
@@ -191,11 +198,18 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
 int lincoll_set_option(lincoll_plan_t plan, int key, int value);
 
 /* Launch-configuration tuner: times `reps` applies of every supported
- * (path, workgroups per CU, graph on/off) on the caller's h/out/batch
- * (after one warm-up each), keeps the fastest as the plan's configuration
- * and records its time (LINCOLL_INFO_TUNED_MS).  Synchronises the plan's
- * stream; out holds L[h] afterwards.  Same argument rules as lincoll_apply;
- * reps in [1, 1000]. */
+ * configuration on the caller's h/out/batch (after one warm-up each): path;
+ * on the fused path the workgroups per CU; on the staged path the z-pass
+ * block size (64, 128, 256) and the in-plane tile (LINCOLL_OPT_ZBLOCK,
+ * LINCOLL_OPT_PLANE_TILE); graph replay on and off.  Keeps the fastest as the
+ * plan's configuration, records its time (LINCOLL_INFO_TUNED_MS) and stores
+ * it in a process-wide cache keyed by (device architecture, n, dtype, batch
+ * rounded up to a power of two, projection flag, per-cell or broadcast
+ * Maxwellians); a later call with the same key takes the cached result
+ * without timing (LINCOLL_INFO_TUNE_CACHED = 1) unless LINCOLL_OPT_TUNE_CACHE
+ * is 0.  No configuration changes the arithmetic of a path.  Synchronises the
+ * plan's stream; out holds L[h] afterwards (after a cache hit it is not
+ * written).  Same argument rules as lincoll_apply; reps in [1, 1000]. */
 int lincoll_autotune(lincoll_plan_t plan, const void* h, void* out, int batch, int reps);
 
 /* Advances f[b] in place by `steps` steps of the classical fourth-order

@@ -4,7 +4,10 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/lincoll.h"
@@ -55,7 +58,10 @@ struct lincoll_plan_s {
   int cus = 256;              // compute units of the plan's device
   // options (lincoll_set_option)
   int opt_graph = 0, opt_per_cu = 0;
+  int opt_zblk = 128, opt_tile = 0, opt_tune_cache = 1;
   double tuned_ms = 0.0;
+  int tuned_cached = 0;
+  std::string arch;           // gcnArchName of the plan's device (key of the tuner's cache)
   // replayable graph of the last apply (opt_graph)
   unsigned long alloc_gen = 0;
   hipStream_t cap_stream = nullptr;
@@ -363,6 +369,8 @@ int lincoll_plan_ex(const lincoll_params_t* pin, lincoll_plan_t* out) {
   if (!e) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, pl->device) == hipSuccess && v > 0) pl->cus = v;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) pl->arch = prop.gcnArchName;
   }
   if (e) {
     pl->last_hip = (int)e;
@@ -471,6 +479,8 @@ ApplyCtx apply_ctx(lincoll_plan_t pl, const void* hin, void* out, int batch, hip
   c.Bc = pl->Bc;
   c.cus = pl->cus;
   c.per_cu = pl->opt_per_cu;
+  c.zblk = pl->opt_zblk;
+  c.plane_tile = pl->opt_tile;
   c.dtype = pl->p.dtype;
   c.stream = stream;
   c.h = hin;
@@ -616,6 +626,19 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       if (value < 0 || value > 2) return LINCOLL_EINVAL;
       pl->quad_fix = value;
       break;
+    case LINCOLL_OPT_ZBLOCK:
+      if (value != 64 && value != 128 && value != 256) return LINCOLL_EINVAL;
+      pl->opt_zblk = value;
+      break;
+    case LINCOLL_OPT_PLANE_TILE:
+      if (value != 0 && value != 1) return LINCOLL_EINVAL;
+      if (value == 1 && pl->p.n > 32) return LINCOLL_EINVAL;
+      pl->opt_tile = value;
+      break;
+    case LINCOLL_OPT_TUNE_CACHE:
+      if (value != 0 && value != 1) return LINCOLL_EINVAL;
+      pl->opt_tune_cache = value;
+      break;
     case LINCOLL_OPT_PATH:
       if (value < LINCOLL_PATH_AUTO || value > LINCOLL_PATH_FUSED) return LINCOLL_EINVAL;
       if (value == LINCOLL_PATH_FUSED && !fused_supported(pl->p.n, pl->p.dtype)) return LINCOLL_EINVAL;
@@ -629,23 +652,65 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
   return LINCOLL_OK;
 }
 
+namespace {
+
+// A launch configuration of the apply: path, fused workgroups per CU,
+// staged tile (z-pass block size, in-plane tile) and graph replay.
+struct Tuned {
+  int path, per_cu, zblk, tile, graph;
+  double ms;
+};
+
+// Process-wide cache of tuned configurations, keyed by the device
+// architecture, n, dtype, the batch rounded up to a power of two, the
+// projection flag and whether the Maxwellians are per cell.
+std::mutex g_tune_mu;
+std::map<std::string, Tuned> g_tune_cache;
+
+std::string tune_key(const lincoll_plan_s* pl, int batch) {
+  int bucket = 1;
+  while (bucket < batch) bucket <<= 1;
+  return pl->arch + "|n" + std::to_string(pl->p.n) + "|d" + std::to_string(pl->p.dtype) + "|b" +
+         std::to_string(bucket) + "|p" + std::to_string(pl->p.project) + "|c" + std::to_string(pl->Bc > 1 ? 1 : 0);
+}
+
+void apply_tuned(lincoll_plan_t pl, const Tuned& t) {
+  pl->p.path = t.path;
+  pl->opt_per_cu = t.per_cu;
+  pl->opt_zblk = t.zblk;
+  pl->opt_tile = t.tile;
+  pl->opt_graph = t.graph;
+  pl->tuned_ms = t.ms;
+  drop_graph(pl);
+}
+
+}  // namespace
+
 int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int reps) {
   int st = checked_apply_args(pl, h, out, batch);
   if (st) return st;
   if (reps < 1 || reps > 1000) return LINCOLL_EINVAL;
-  struct Cand {
-    int path, per_cu, graph;
-  };
-  Cand cands[2 * 2 * 8];
-  int nc = 0;
+  const std::string key = tune_key(pl, batch);
+  if (pl->opt_tune_cache) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      apply_tuned(pl, it->second);
+      pl->tuned_cached = 1;
+      return LINCOLL_OK;
+    }
+  }
+  std::vector<Tuned> cands;
   const int n = pl->p.n, dt = pl->p.dtype;
   for (int g = 0; g < 2; ++g) {
-    if (staged_supported(n, dt)) cands[nc++] = {LINCOLL_PATH_STAGED, 0, g};
+    if (staged_supported(n, dt))
+      for (int zb : {64, 128, 256})
+        for (int tile = 0; tile <= (n <= 32 ? 1 : 0); ++tile) cands.push_back({LINCOLL_PATH_STAGED, 0, zb, tile, g, 0.0});
     if (fused_supported(n, dt))
-      for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) cands[nc++] = {LINCOLL_PATH_FUSED, pc, g};
+      for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 0.0});
   }
-  if (nc == 0) return LINCOLL_EINVAL;
-  const int saved_path = pl->p.path, saved_pc = pl->opt_per_cu, saved_graph = pl->opt_graph;
+  if (cands.empty()) return LINCOLL_EINVAL;
+  const Tuned saved{pl->p.path, pl->opt_per_cu, pl->opt_zblk, pl->opt_tile, pl->opt_graph, pl->tuned_ms};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e;
   if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
@@ -654,11 +719,8 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
   }
   double best = 1e300;
   int bi = -1;
-  for (int i = 0; i < nc && !st; ++i) {
-    pl->p.path = cands[i].path;
-    pl->opt_per_cu = cands[i].per_cu;
-    pl->opt_graph = cands[i].graph;
-    drop_graph(pl);
+  for (size_t i = 0; i < cands.size() && !st; ++i) {
+    apply_tuned(pl, cands[i]);
     if ((st = lincoll_apply(pl, h, out, batch))) break;   // warm-up (allocates, captures)
     if ((e = hipEventRecord(e0, pl->stream))) { st = hip_fail(pl, e); break; }
     for (int r = 0; r < reps && !st; ++r) st = lincoll_apply(pl, h, out, batch);
@@ -668,24 +730,22 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
       st = hip_fail(pl, e);
       break;
     }
-    if (ms / reps < best) {
-      best = ms / reps;
-      bi = i;
+    cands[i].ms = ms / reps;
+    if (cands[i].ms < best) {
+      best = cands[i].ms;
+      bi = (int)i;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  drop_graph(pl);
   if (st || bi < 0) {
-    pl->p.path = saved_path;
-    pl->opt_per_cu = saved_pc;
-    pl->opt_graph = saved_graph;
+    apply_tuned(pl, saved);
     return st ? st : LINCOLL_EINVAL;
   }
-  pl->p.path = cands[bi].path;
-  pl->opt_per_cu = cands[bi].per_cu;
-  pl->opt_graph = cands[bi].graph;
-  pl->tuned_ms = best;
+  apply_tuned(pl, cands[bi]);
+  pl->tuned_cached = 0;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache[key] = cands[bi];
   return LINCOLL_OK;
 }
 
@@ -941,6 +1001,9 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_L: *val = pl->p.L; break;
     case LINCOLL_INFO_PROJECT: *val = pl->p.project; break;
     case LINCOLL_INFO_QUAD_FIX: *val = pl->quad_fix; break;
+    case LINCOLL_INFO_ZBLOCK: *val = pl->opt_zblk; break;
+    case LINCOLL_INFO_PLANE_TILE: *val = pl->opt_tile; break;
+    case LINCOLL_INFO_TUNE_CACHED: *val = pl->tuned_cached; break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;

@@ -46,6 +46,8 @@ struct ApplyCtx {
   int cus = 256;               // compute units of the device
   int per_cu = 0;              // fused path: workgroups per compute unit (0 = default)
   int max_slots = 0;           // fused path: cap on the persistent workgroups (0 = none)
+  int zblk = 128;              // staged path: threads per block of the z-pass kernels (64, 128, 256)
+  int plane_tile = 0;          // staged path: 0 = 64-thread in-plane blocks, 1 = 32-thread (n <= 32)
   const int* gate = nullptr;   // fused path: the kernel does nothing unless *gate != 0 (device flag)
   int dtype = 0;
   hipStream_t stream = nullptr;

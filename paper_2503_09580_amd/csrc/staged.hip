@@ -38,7 +38,7 @@ __device__ __forceinline__ int fold(int K) { return K <= NN / 2 ? K : NN - K; }
 // and its round-off would swamp the much smaller h).
 // MODE 1: M itself for the setup of nu (into H).
 template <typename TS, typename T, int NN, int MODE>
-__global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, double2* __restrict__ R,
+__global__ void __launch_bounds__(256) k_z_fwd(const TS* __restrict__ h, double2* __restrict__ R,
                                                 typename V2<TS>::t* __restrict__ H, const TS* __restrict__ fac,
                                                 const TS* __restrict__ pref, const uint32_t* __restrict__ mask,
                                                 int Bc, int batch) {
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(128) k_z_fwd(const TS* __restrict__ h, double2
 // (x, y + n/2), inverse real transform along z, multiply by M^h, forward
 // real transform, in place on W.
 template <typename TS, typename T, int NN, typename TW>
-__global__ void __launch_bounds__(128) k_z_mid(const typename V2<TW>::t* __restrict__ W, typename V2<TS>::t* __restrict__ Wq,
+__global__ void __launch_bounds__(256) k_z_mid(const typename V2<TW>::t* __restrict__ W, typename V2<TS>::t* __restrict__ Wq,
                                                 const TS* __restrict__ fac, const TS* __restrict__ pref, int Bc,
                                                 int batch) {
   using C = typename V2<TS>::t;
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(128) k_z_mid(const typename V2<TW>::t* __restr
 // columns packed), then L = L+ - M U - nu h.
 // MODE 1 (setup): nu <- inverse of H only.
 template <typename TS, typename T, int NN, int MODE>
-__global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restrict__ Lp,
+__global__ void __launch_bounds__(256) k_z_inv(const typename V2<TS>::t* __restrict__ Lp,
                                                 const typename V2<TS>::t* __restrict__ H, const TS* __restrict__ h,
                                                 const TS* __restrict__ nu, TS* __restrict__ out,
                                                 const TS* __restrict__ fac, const TS* __restrict__ pref, int Bc,
@@ -237,13 +237,16 @@ __global__ void __launch_bounds__(128) k_z_inv(const typename V2<TS>::t* __restr
 // PRE 1: multiply by K_j(|kx|,|ky|,kz) before an inverse transform.
 // POST 1: multiply by a radial table t(|k|^2) after a forward transform.
 // POST 2: as 1 and accumulate into out (store when first).
-template <typename TI, typename TO, typename TS, typename T, int NN, bool INV, int PRE, int POST>
-__global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, typename V2<TO>::t* out,
-                                               const double* __restrict__ Kh, const TS* __restrict__ table, int J,
-                                               int j, int Bc, int nplanes, int first) {
+// TPB: threads per block (64, or 32 for the half tile at n <= 32), one plane
+// per NN threads.
+template <typename TI, typename TO, typename TS, typename T, int NN, bool INV, int PRE, int POST, int TPB = 64>
+__global__ void __launch_bounds__(TPB) k_plane(const typename V2<TI>::t* in, typename V2<TO>::t* out,
+                                                const double* __restrict__ Kh, const TS* __restrict__ table, int J,
+                                                int j, int Bc, int nplanes, int first) {
   using CI = typename V2<TI>::t;
   using C = typename V2<TO>::t;
-  constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = 64 / NN, LD = NN + 1;
+  static_assert(TPB % NN == 0, "a block holds whole planes");
+  constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = TPB / NN, LD = NN + 1;
   // The transposes go through LDS in compute precision, one component at a
   // time: half the footprint of a complex tile, so that LDS does not limit the
   // blocks per CU below what the registers allow (at n = 64 a complex double
@@ -315,10 +318,14 @@ __global__ void __launch_bounds__(64) k_plane(const typename V2<TI>::t* in, type
 }
 
 // ----------------------------------------------------------- launchers
-template <typename TS, typename T, int NN>
-static hipError_t apply_n(const ApplyCtx& c) {
+// Tile of the staged path (lincoll_set_option / the launch tuner): c.zblk
+// threads per block of the z-pass kernels, TPB threads per block (planes per
+// block TPB / NN) of the in-plane kernels.  Neither changes the arithmetic:
+// every tile gives bitwise the same result.
+template <typename TS, typename T, int NN, int TPB>
+static hipError_t apply_n_tile(const ApplyCtx& c) {
   using Cx = typename V2<TS>::t;
-  constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = 64 / NN;
+  constexpr int P = NN / 2 + 1, NP = NN * NN, PPB = TPB / NN;
   const int B = c.batch;
   const TS* fac = static_cast<const TS*>(c.fac);
   const TS* pref = static_cast<const TS*>(c.pref);
@@ -341,20 +348,22 @@ static hipError_t apply_n(const ApplyCtx& c) {
   Cx* Lp = static_cast<Cx*>(c.Lp);
   const long ncol = (long)B * NP;
   const int nplanes = B * P;
-  const dim3 gz2((unsigned)((ncol / 2 + 127) / 128));
+  const int zb = c.zblk;
+  const dim3 gz2((unsigned)((ncol / 2 + zb - 1) / zb));
   const dim3 gp((unsigned)((nplanes + PPB - 1) / PPB));
-  k_z_fwd<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(static_cast<const TS*>(c.h), R, H, fac, pref, c.mask, c.Bc, B);
-  k_plane<double, double, TS, T, NN, false, 0, 0><<<gp, 64, 0, c.stream>>>(R, R, nullptr, nullptr, c.J, 0, c.Bc,
-                                                                           nplanes, 1);
+  k_z_fwd<TS, T, NN, 0><<<gz2, zb, 0, c.stream>>>(static_cast<const TS*>(c.h), R, H, fac, pref, c.mask, c.Bc, B);
+  k_plane<double, double, TS, T, NN, false, 0, 0, TPB><<<gp, TPB, 0, c.stream>>>(R, R, nullptr, nullptr, c.J, 0,
+                                                                                 c.Bc, nplanes, 1);
   // Transforms of h-derived data and of the products with M^h (the loss
   // spectrum, the gain node passes, the final inverses) compute in the storage
   // precision; only the r-derived passes keep T.
   using TF = TS;
-  k_plane<TS, TS, TS, TF, NN, false, 0, 1><<<gp, 64, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes, 1);
+  k_plane<TS, TS, TS, TF, NN, false, 0, 1, TPB><<<gp, TPB, 0, c.stream>>>(H, H, nullptr, Om, c.J, 0, c.Bc, nplanes,
+                                                                           1);
   for (int j = 0; j < c.J; ++j) {
-    k_plane<double, TW, TS, T, NN, true, 1, 0><<<gp, 64, 0, c.stream>>>(R, WS, Kh, nullptr, c.J, j, c.Bc,
-                                                                        nplanes, 1);
-    k_z_mid<TS, T, NN, TW><<<gz2, 128, 0, c.stream>>>(WS, Wq, fac, pref, c.Bc, B);
+    k_plane<double, TW, TS, T, NN, true, 1, 0, TPB><<<gp, TPB, 0, c.stream>>>(R, WS, Kh, nullptr, c.J, j, c.Bc,
+                                                                              nplanes, 1);
+    k_z_mid<TS, T, NN, TW><<<gz2, zb, 0, c.stream>>>(WS, Wq, fac, pref, c.Bc, B);
     if constexpr (std::is_same<TS, float>::value && (NN == 32 || NN == 64)) {
       if (c.dtype == 2) {   // BF16x3: the forward in-plane DFT stages on the matrix cores
         hipError_t e = plane_fwd_bf16x3(NN, reinterpret_cast<const float2*>(Wq), reinterpret_cast<float2*>(Lp), Phi,
@@ -363,15 +372,25 @@ static hipError_t apply_n(const ApplyCtx& c) {
         continue;
       }
     }
-    k_plane<TS, TS, TS, TF, NN, false, 0, 2><<<gp, 64, 0, c.stream>>>(Wq, Lp, nullptr, Phi, c.J, j, c.Bc, nplanes,
-                                                                      j == 0);
+    k_plane<TS, TS, TS, TF, NN, false, 0, 2, TPB><<<gp, TPB, 0, c.stream>>>(Wq, Lp, nullptr, Phi, c.J, j, c.Bc,
+                                                                            nplanes, j == 0);
   }
-  k_plane<TS, TS, TS, TF, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc, nplanes,
-                                                                   1);
-  k_plane<TS, TS, TS, TF, NN, true, 0, 0><<<gp, 64, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc, nplanes, 1);
-  k_z_inv<TS, T, NN, 0><<<gz2, 128, 0, c.stream>>>(Lp, H, static_cast<const TS*>(c.h), static_cast<const TS*>(c.nu),
-                                                 static_cast<TS*>(c.out), fac, pref, c.Bc, B, W);
+  k_plane<TS, TS, TS, TF, NN, true, 0, 0, TPB><<<gp, TPB, 0, c.stream>>>(Lp, Lp, nullptr, nullptr, c.J, 0, c.Bc,
+                                                                         nplanes, 1);
+  k_plane<TS, TS, TS, TF, NN, true, 0, 0, TPB><<<gp, TPB, 0, c.stream>>>(H, H, nullptr, nullptr, c.J, 0, c.Bc,
+                                                                         nplanes, 1);
+  k_z_inv<TS, T, NN, 0><<<gz2, zb, 0, c.stream>>>(Lp, H, static_cast<const TS*>(c.h), static_cast<const TS*>(c.nu),
+                                                static_cast<TS*>(c.out), fac, pref, c.Bc, B, W);
   return hipGetLastError();
+}
+
+template <typename TS, typename T, int NN>
+static hipError_t apply_n(const ApplyCtx& c) {
+  if (c.zblk != 64 && c.zblk != 128 && c.zblk != 256) return hipErrorInvalidValue;
+  if constexpr (NN <= 32) {
+    if (c.plane_tile == 1) return apply_n_tile<TS, T, NN, 32>(c);
+  }
+  return apply_n_tile<TS, T, NN, 64>(c);
 }
 
 bool staged_supported(int n, int dtype) {

@@ -146,3 +146,52 @@ def test_autotune_picks_a_valid_configuration(n, batch):
     sample = [0, batch // 2, batch - 1]
     ref = alg1.apply_batch(fd.make_plan(n, L, om), hin[sample], params[sample])
     check_cells(got, ref, 1e-5, cells=sample)
+
+
+@pytest.mark.parametrize("n,L,dtype", [(16, 8.0, "f32"), (32, 8.0, "f32"), (32, 8.0, "f64"), (64, 10.0, "f32")])
+def test_staged_tiles_are_bitwise_identical(n, L, dtype):
+    """Every staged tile the tuner searches (z-pass blocks of 64, 128, 256
+    threads; 64- or 32-thread in-plane blocks) gives bitwise the same result,
+    and that result meets the bar against the oracle (sampled cells)."""
+    om = 0.74
+    B = 5 if n < 64 else 3
+    h, params = mixed_inputs(n, L, B, seed=3000 + n)
+    hin = h if dtype == "f64" else h.astype(np.float32).astype(np.float64)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    ref = None
+    for zb in (128, 64, 256):
+        for tile in ((0, 1) if n <= 32 else (0,)):
+            got = eager_result(n, L, om, dtype, "staged", hin, params, zblock=zb, plane_tile=tile).double().numpy()
+            if ref is None:
+                ref = got
+            else:
+                assert np.array_equal(got, ref), (zb, tile)
+    sample = [0, B - 1]
+    orc = alg1.apply_batch(fd.make_plan(n, L, om), hin[sample], params[sample])
+    check_cells(ref, orc, 1e-12 if dtype == "f64" else 1e-5, cells=sample)
+
+
+def test_autotune_cache_by_key():
+    """lincoll_autotune stores its choice under (arch, n, dtype, batch bucket,
+    projection, per-cell Maxwellians): a second plan with the same key takes
+    it without timing, a different batch bucket or a disabled cache times."""
+    n, L, om = 16, 8.0, 0.74
+    h, params = mixed_inputs(n, L, 7, seed=3100)
+    ht = dev(h, torch.float64)
+    keys = ("path", "fused_per_cu", "zblock", "plane_tile", "graph")
+    plans = []
+    for _ in range(2):
+        p = lc.Plan(n, L, om, "f64")
+        p.set_maxwellians(dev(params, torch.float64))
+        plans.append(p)
+    plans[0].set_option("tune_cache", 0)
+    plans[0].autotune(ht, reps=1)
+    assert plans[0].info("tune_cached") == 0
+    plans[1].autotune(ht, reps=1)
+    assert plans[1].info("tune_cached") == 1
+    assert [plans[0].info(k) for k in keys] == [plans[1].info(k) for k in keys]
+    assert plans[1].info("tuned_ms") == plans[0].info("tuned_ms")
+    p3 = lc.Plan(n, L, om, "f64")
+    p3.set_maxwellians(dev(params[:3], torch.float64))
+    p3.autotune(dev(h[:3], torch.float64), reps=1)      # batch bucket 4, not 8
+    assert p3.info("tune_cached") == 0
