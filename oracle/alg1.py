@@ -1,17 +1,24 @@
-"""Algorithm 1 of the paper, step by step, with a library FFT as the
-transform primitive.  FP64.
+"""The paper's fast method for the linearized operator with a library FFT as
+the transform primitive (the route of Algorithm 1).  FP64.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  This is the CPU
 throughput baseline; its agreement with the direct-sum evaluation in
 ``fast_direct`` (which shares only the plan tables' definitions, not this
 code path) is pinned in the tests.
 
-Algorithm 1 (Sec. 3.5) with the readings R3 (gain constant 4 pi^2 instead
-of the printed 32 pi^2), R4 (phi_j from the Nyquist-doubled s_j) and R5 (the
-product of line "psi <- InvFFT(u_hat r_hat)" is a plain cyclic convolution,
-i.e. FFT and InvFFT without the c_k halving).  FFT/InvFFT use the paper's
-index sets -N..N-1 for both l and k; ``fft3``/``ifft3`` realise that with
-fftshift bookkeeping around numpy's transforms.
+What is computed, per cell with Maxwellian (rho, u, theta), written from
+eq. (20) (loss), eqs. (23)-(24) (gain) and the cutoff of Sec. 3.4:
+    r      = h / M where M / rho >= eps, else 0
+    K_j    = DFT[G phi_j]                 (G the Gaussian of eq. (24), centred at 0)
+    psi_j  = iDFT[K_j DFT[r]]             (the cyclic convolution of eq. (24))
+    L+     = iDFT[ sum_j Phi_j DFT[M^h psi_j] ]
+    L-     = M iDFT[Omega DFT[h]] + h iDFT[Omega DFT[M]]
+    L      = L+ - L-
+with the readings R3 (gain constant 4 pi^2 rather than the printed 32 pi^2,
+carried by Phi_j), R4 (phi_j from the Nyquist-doubled s_j) and R5 (the
+product of eq. (24) is a plain cyclic convolution: unhalved DFT and inverse).
+The transforms run over the signed index sets -N..N-1 of Sec. 2.3; ``fft3``
+and ``ifft3`` realise them with shift bookkeeping around numpy's transforms.
 """
 import math
 
@@ -31,40 +38,45 @@ def ifft3(X):
     return np.fft.fftshift(np.fft.ifftn(np.fft.ifftshift(X)))
 
 
+def _gaussians(plan, rho, u, theta):
+    """The three Gaussians of Sec. 3.2 on the grid: the Maxwellian M, the
+    factor M^h of the gain (half the variance, centred at u) and G of
+    eq. (24) (half the variance, centred at 0)."""
+    v = grid.velocities(plan.n, plan.L)
+    X, Y, Z = np.meshgrid(v, v, v, indexing="ij")
+    du = (X - u[0]) ** 2 + (Y - u[1]) ** 2 + (Z - u[2]) ** 2
+    d0 = X ** 2 + Y ** 2 + Z ** 2
+    maxw = rho * (2.0 * math.pi * theta) ** -1.5 * np.exp(-du / (2.0 * theta))
+    half = rho * (math.pi * theta) ** -1.5 * np.exp(-du / theta)
+    gauss0 = rho * (math.pi * theta) ** -1.5 * np.exp(-d0 / theta)
+    return maxw, half, gauss0
+
+
 def collision_operator(plan, rho, u, theta, f, cutoff=True):
-    """LinearizedCollisionOperator(rho, u, theta, f, cutoff) of Algorithm 1
-    for one cell; f and the result are point values on the grid."""
-    n, L = plan.n, plan.L
-    v = grid.velocities(n, L)
-    VX, VY, VZ = np.meshgrid(v, v, v, indexing="ij")
-    d2u = (VX - u[0]) ** 2 + (VY - u[1]) ** 2 + (VZ - u[2]) ** 2
-    d20 = VX ** 2 + VY ** 2 + VZ ** 2
-    # first loop: Maxwellians and r = f / M with the cutoff (eq. (25))
-    M = rho / (2.0 * math.pi * theta) ** 1.5 * np.exp(-d2u / (2.0 * theta))
-    Mg = rho / (math.pi * theta) ** 1.5 * np.exp(-d20 / theta)
-    Mh = rho / (math.pi * theta) ** 1.5 * np.exp(-d2u / theta)
+    """L[f] for one cell about the Maxwellian (rho, u, theta); f and the
+    result are point values on the grid."""
+    maxw, half, gauss0 = _gaussians(plan, rho, u, theta)
+    # the cutoff of Sec. 3.4 decides where r is kept, relative to rho
     if cutoff and plan.eps > 0.0:
-        keep = (M / rho) >= plan.eps
-        r = np.where(keep, f / np.where(keep, M, 1.0), 0.0)
+        kept = maxw / rho >= plan.eps
+        r = np.zeros_like(f)
+        r[kept] = f[kept] / maxw[kept]
     else:
-        r = f / M
-    # gain term
-    rhat = fft3(r)
-    Lhat = np.zeros((n, n, n), dtype=np.complex128)
-    for j in range(plan.J):
-        uj = Mg * plan.phi[j]
-        uhat = fft3(uj)
-        psi = ifft3(uhat * rhat).real
-        psi = Mh * psi
-        psihat = fft3(psi)
-        Lhat += plan.Phi[j] * psihat
-    Lplus = ifft3(Lhat).real
-    # loss term
-    fhat = fft3(f)
-    Mhat = fft3(M)
-    uu = ifft3(fhat * plan.Omega).real
-    ww = ifft3(Mhat * plan.Omega).real
-    return Lplus - uu * M - ww * f
+        r = f / maxw
+    # gain, eqs. (23)-(24): one convolution and one spectral weight per g-node
+    r_spec = fft3(r)
+    acc = np.zeros(f.shape, dtype=np.complex128)
+    for weight, phi in zip(plan.Phi, plan.phi):
+        kernel_spec = fft3(gauss0 * phi)
+        psi = ifft3(kernel_spec * r_spec).real
+        acc += weight * fft3(half * psi)
+    l_plus = ifft3(acc).real
+    # loss, eq. (20) at the grid points: the collision frequency nu = Omega * M
+    # applied to f, and f's own convolution with Omega times M
+    nu = ifft3(plan.Omega * fft3(maxw)).real
+    conv_f = ifft3(plan.Omega * fft3(f)).real
+    l_minus = maxw * conv_f + nu * f
+    return l_plus - l_minus
 
 
 def apply_batch(plan, h, params, cutoff=True):

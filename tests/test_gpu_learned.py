@@ -9,12 +9,17 @@ ABI, against the oracle (oracle/learned.py).
    at seeded wall temperatures, training lowers the loss, the network
    predicts the macroscopic part of the held-out Newton corrections, and the
    solve with the learned start converges to the same solution as the
-   sweep-only solve.  GMRES without a preconditioner (the fallback) hits a
-   600-iteration cap in every inner solve: about 30 times the learned
-   solve's inner iterations (2400 against 77 when measured).  The inner-iteration counts of both are printed: at this
-   size the learned start saves about as many iterations as its two extra
-   operator applications cost (the inner solves are paced by kinetic, not
-   macroscopic, error)."""
+   sweep-only solve.
+   What the network gains is judged against the method without it: the
+   same solver with the same sweep preconditioner and dtype, to the same
+   Newton tolerance.  The test records the ratio of inner iterations and of
+   solve times (learned / sweep); it was 77 / 74 iterations when measured,
+   i.e. no gain: the inner solves are paced by kinetic, not macroscopic,
+   error, and the learned start costs two operator applications.  The test
+   fails if the learned start costs more than a quarter over the sweep.
+   GMRES without any preconditioner (the fallback) is run as well: it hits a
+   600-iteration cap in every inner solve; that gap is the sweep's, not the
+   network's."""
 import numpy as np
 import pytest
 
@@ -179,6 +184,12 @@ def test_learned_start_end_to_end():
         assert rep["converged"] and abs(rep["mass"] - 1.0) < 1e-12, rep
     (rs, fs), (rl, fl) = res["sweep"], res["learned"]
     assert rl["newton_iters"] == rs["newton_iters"]
+    assert rl["residual"] < 1e-5 and rs["residual"] < 1e-5
+    it_ratio = rl["inner_iters"] / rs["inner_iters"]
+    t_ratio = rl["ms_inner"] / rs["ms_inner"]
+    print(f"learned / sweep (same solver, dtype and tolerance): inner iterations {it_ratio:.3f}, "
+          f"inner-solve time {t_ratio:.3f}")
+    assert it_ratio <= 1.25, it_ratio
     # both meet the Newton tolerance 1e-5 of the same discrete problem
     assert np.max(np.abs(fs - fl)) <= 1e-3 * np.max(np.abs(fs))
     # the fallback without a preconditioner, with one more Newton step and
