@@ -504,6 +504,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-configuration tuner (lincoll_autotune) before timing")
     ap.add_argument("--graph", type=int, default=None, help="force graph replay off (0) or on (1)")
+    ap.add_argument("--fused-ppt", type=int, default=None, choices=[1, 2],
+                    help="fused path: force one or two pencils per thread (skips the tuner)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (reference kernel for counter runs)")
     a = ap.parse_args()
@@ -556,6 +558,9 @@ def main():
         setup_ms = es0.elapsed_time(es1)
         J = int(plan.info("J"))
         tuned_ms = None
+        if a.fused_ppt is not None:
+            plan.set_option("fused_ppt", a.fused_ppt)
+            a.no_tune = True
         if not a.no_tune and a.path == "auto":
             tuned_ms = plan.autotune(ht, out, reps=3)   # untimed; picks path, workgroups/CU, graph replay
         if a.graph is not None:
@@ -563,6 +568,7 @@ def main():
         path = "fused" if plan.info("path") == 2 else "staged"
         launch = {"path": path, "graph": int(plan.info("graph")), "tuned_ms": tuned_ms,
                   "fused_per_cu": int(plan.info("fused_per_cu")) if path == "fused" else None,
+                  "fused_pencils_per_thread": int(plan.info("fused_ppt")) if path == "fused" else None,
                   "staged_zblock": int(plan.info("zblock")) if path == "staged" else None,
                   "staged_plane_tile": int(plan.info("plane_tile")) if path == "staged" else None,
                   "tuner": "lincoll_autotune over path x workgroups/CU x staged tiles x graph"}

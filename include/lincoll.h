@@ -158,6 +158,7 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_ZBLOCK 15       /* staged path: threads per block of the z-pass kernels */
 #define LINCOLL_INFO_PLANE_TILE 16   /* staged path: in-plane tile (0: 64 threads, 1: 32 threads per block) */
 #define LINCOLL_INFO_TUNE_CACHED 17  /* 1 if the last lincoll_autotune took its result from the cache */
+#define LINCOLL_INFO_FUSED_PPT 18    /* fused path: pencils per thread (LINCOLL_OPT_FUSED_PPT) */
 /* Reads one plan property into *val.  With plan == NULL only
  * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
  * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */
@@ -191,6 +192,10 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
 #define LINCOLL_OPT_PLANE_TILE 8      /* staged path: in-plane kernels with 64 (0, default) or 32 (1, n <= 32)
                                          threads per block, i.e. 64/n or 32/n planes per block */
 #define LINCOLL_OPT_TUNE_CACHE 9      /* 1 (default): lincoll_autotune reuses a cached result; 0: always times */
+#define LINCOLL_OPT_FUSED_PPT 10      /* fused path: pencils per thread, 1 (default: two waves per SIMD, the L+^
+                                         accumulator streamed through the workgroup's scratch slot every node) or
+                                         2 (one wave per SIMD with the whole register file per lane; the
+                                         accumulator stays in registers).  Same arithmetic, bitwise equal results */
 #define LINCOLL_OPT_QUAD_FIX 6        /* quadcoll: mass fix of Sec. 2.3 -- 0 none (default); 1 Q^_0 = 0 (eq. (15)),
                                          the per-cell mean of Q removed; 2 the sinc of the loss term replaced by
                                          its estimate on the hemisphere rule (eq. (16)), a [n]^3 FP64 table the
@@ -199,7 +204,8 @@ int lincoll_set_option(lincoll_plan_t plan, int key, int value);
 
 /* Launch-configuration tuner: times `reps` applies of every supported
  * configuration on the caller's h/out/batch (after one warm-up each): path;
- * on the fused path the workgroups per CU; on the staged path the z-pass
+ * on the fused path the workgroups per CU and the pencils per thread
+ * (LINCOLL_OPT_FUSED_PPT); on the staged path the z-pass
  * block size (64, 128, 256) and the in-plane tile (LINCOLL_OPT_ZBLOCK,
  * LINCOLL_OPT_PLANE_TILE); graph replay on and off.  Keeps the fastest as the
  * plan's configuration, records its time (LINCOLL_INFO_TUNED_MS) and stores

@@ -58,7 +58,7 @@ struct lincoll_plan_s {
   int cus = 256;              // compute units of the plan's device
   // options (lincoll_set_option)
   int opt_graph = 0, opt_per_cu = 0;
-  int opt_zblk = 128, opt_tile = 0, opt_tune_cache = 1;
+  int opt_zblk = 128, opt_tile = 0, opt_tune_cache = 1, opt_ppt = 1;
   double tuned_ms = 0.0;
   int tuned_cached = 0;
   std::string arch;           // gcnArchName of the plan's device (key of the tuner's cache)
@@ -224,7 +224,7 @@ int ensure_work(lincoll_plan_t pl, int B) {
     pl->cap_pin = B;
   }
   if (use_fused(pl)) {
-    const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus));
+    const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus), pl->opt_ppt);
     if (need > pl->R_bytes || !pl->d_R) {
       pl->cap_work = 0;
       if ((e = dalloc(pl, &pl->d_R, need))) {
@@ -480,6 +480,7 @@ ApplyCtx apply_ctx(lincoll_plan_t pl, const void* hin, void* out, int batch, hip
   c.cus = pl->cus;
   c.per_cu = pl->opt_per_cu;
   c.zblk = pl->opt_zblk;
+  c.fused_ppt = pl->opt_ppt;
   c.plane_tile = pl->opt_tile;
   c.dtype = pl->p.dtype;
   c.stream = stream;
@@ -590,7 +591,7 @@ int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch
   void* scr = nullptr;
   size_t bytes = 0;
   if ((e = fused_noalloc_scratch(dev, &scr, &bytes))) return hip_fail(pl, e);
-  const size_t slot = fused_scratch_bytes(pl->p.n, 1);
+  const size_t slot = fused_scratch_bytes(pl->p.n, 1, pl->opt_ppt);
   if (slot == 0 || slot > bytes) return LINCOLL_EINVAL;
   ApplyCtx c = apply_ctx(pl, h, out, batch, pl->stream);
   c.R = scr;
@@ -635,6 +636,10 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       if (value == 1 && pl->p.n > 32) return LINCOLL_EINVAL;
       pl->opt_tile = value;
       break;
+    case LINCOLL_OPT_FUSED_PPT:
+      if (value != 1 && value != 2) return LINCOLL_EINVAL;
+      pl->opt_ppt = value;
+      break;
     case LINCOLL_OPT_TUNE_CACHE:
       if (value != 0 && value != 1) return LINCOLL_EINVAL;
       pl->opt_tune_cache = value;
@@ -657,7 +662,7 @@ namespace {
 // A launch configuration of the apply: path, fused workgroups per CU,
 // staged tile (z-pass block size, in-plane tile) and graph replay.
 struct Tuned {
-  int path, per_cu, zblk, tile, graph;
+  int path, per_cu, zblk, tile, graph, ppt;
   double ms;
 };
 
@@ -680,6 +685,7 @@ void apply_tuned(lincoll_plan_t pl, const Tuned& t) {
   pl->opt_zblk = t.zblk;
   pl->opt_tile = t.tile;
   pl->opt_graph = t.graph;
+  pl->opt_ppt = t.ppt;
   pl->tuned_ms = t.ms;
   drop_graph(pl);
 }
@@ -705,12 +711,14 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
   for (int g = 0; g < 2; ++g) {
     if (staged_supported(n, dt))
       for (int zb : {64, 128, 256})
-        for (int tile = 0; tile <= (n <= 32 ? 1 : 0); ++tile) cands.push_back({LINCOLL_PATH_STAGED, 0, zb, tile, g, 0.0});
+        for (int tile = 0; tile <= (n <= 32 ? 1 : 0); ++tile)
+          cands.push_back({LINCOLL_PATH_STAGED, 0, zb, tile, g, 1, 0.0});
     if (fused_supported(n, dt))
-      for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 0.0});
+      for (int ppt = 1; ppt <= 2; ++ppt)
+        for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, ppt, 0.0});
   }
   if (cands.empty()) return LINCOLL_EINVAL;
-  const Tuned saved{pl->p.path, pl->opt_per_cu, pl->opt_zblk, pl->opt_tile, pl->opt_graph, pl->tuned_ms};
+  const Tuned saved{pl->p.path, pl->opt_per_cu, pl->opt_zblk, pl->opt_tile, pl->opt_graph, pl->opt_ppt, pl->tuned_ms};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e;
   if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
@@ -1004,6 +1012,7 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_ZBLOCK: *val = pl->opt_zblk; break;
     case LINCOLL_INFO_PLANE_TILE: *val = pl->opt_tile; break;
     case LINCOLL_INFO_TUNE_CACHED: *val = pl->tuned_cached; break;
+    case LINCOLL_INFO_FUSED_PPT: *val = pl->opt_ppt; break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;

@@ -492,11 +492,353 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
   }
 }
 
+// ---- two pencils per thread ---------------------------------------------------
+// The same computation with half the threads: thread t holds pencils
+// p = t + s T2 (s = 0, 1; T2 = NN N / 2), so a workgroup is T2 / 64 waves,
+// one per SIMD, and each lane may use the whole register file (VGPRs and
+// AGPRs).  That leaves room to keep the L+ accumulator in registers across
+// the nodes, so the only per-node traffic is the spectrum of r and K_j.
+// Wave w owns the planes of its pencils in both slots; the exchanges below
+// move both slots between one pair of barriers.
+
+namespace {
+
+template <int NN, typename T>
+__device__ __forceinline__ void x_to_z_2(T (&vr)[2][NN], T (&vi)[2][NN], float2* lds, int t, int T2) {
+  constexpr int N = NN / 2, KP = N, LD = NN + 1;
+  static_for<0, 2>([&](auto s) {
+    const int p = t + s * T2, kp = p / NN, y = p % NN;
+    static_for<0, NN>([&](auto xx) {
+      lds[(kp * NN + xx) * LD + y] = float2{float(vr[s][xx]), float(vi[s][xx])};
+    });
+  });
+  __syncthreads();
+  static_for<0, 2>([&](auto s) {
+    const int p = t + s * T2, x = p / N, yp = p % N;
+    static_for<0, KP>([&](auto k) {
+      const float2 a = lds[(k * NN + x) * LD + yp];
+      const float2 b = lds[(k * NN + x) * LD + yp + N];
+      vr[s][k] = T(a.x); vi[s][k] = T(a.y);
+      vr[s][N + k] = T(b.x); vi[s][N + k] = T(b.y);
+    });
+  });
+}
+
+template <int NN, typename T>
+__device__ __forceinline__ void z_to_x_2(T (&vr)[2][NN], T (&vi)[2][NN], float2* lds, int t, int T2) {
+  constexpr int N = NN / 2, KP = N, LD = NN + 1;
+  __syncthreads();
+  static_for<0, 2>([&](auto s) {
+    const int p = t + s * T2, x = p / N, yp = p % N;
+    static_for<0, KP>([&](auto k) {
+      lds[(k * NN + x) * LD + yp] = float2{float(vr[s][k]), float(vi[s][k])};
+      lds[(k * NN + x) * LD + yp + N] = float2{float(vr[s][N + k]), float(vi[s][N + k])};
+    });
+  });
+  __syncthreads();
+  static_for<0, 2>([&](auto s) {
+    const int p = t + s * T2, kp = p / NN, y = p % NN;
+    static_for<0, NN>([&](auto xx) {
+      const float2 a = lds[(kp * NN + xx) * LD + y];
+      vr[s][xx] = T(a.x);
+      vi[s][xx] = T(a.y);
+    });
+  });
+}
+
+template <int NN>
+__device__ __forceinline__ void x_to_z_2d(double (&vr)[2][NN], double (&vi)[2][NN], float2* lds, int t, int T2) {
+  constexpr int N = NN / 2, KP = N, LD = NN + 1;
+  double* ld = reinterpret_cast<double*>(lds);
+  auto round = [&](double(&w)[2][NN]) {
+    static_for<0, 2>([&](auto s) {
+      const int p = t + s * T2, kp = p / NN, y = p % NN;
+      static_for<0, NN>([&](auto xx) { ld[(kp * NN + xx) * LD + y] = w[s][xx]; });
+    });
+    __syncthreads();
+    static_for<0, 2>([&](auto s) {
+      const int p = t + s * T2, x = p / N, yp = p % N;
+      static_for<0, KP>([&](auto k) {
+        w[s][k] = ld[(k * NN + x) * LD + yp];
+        w[s][N + k] = ld[(k * NN + x) * LD + yp + N];
+      });
+    });
+  };
+  round(vr);
+  __syncthreads();   // every wave has read the real parts
+  round(vi);
+}
+
+template <int NN>
+__device__ __forceinline__ void z_to_x_2d(double (&vr)[2][NN], double (&vi)[2][NN], float2* lds, int t, int T2) {
+  constexpr int N = NN / 2, KP = N, LD = NN + 1;
+  double* ld = reinterpret_cast<double*>(lds);
+  auto round = [&](double(&w)[2][NN]) {
+    __syncthreads();
+    static_for<0, 2>([&](auto s) {
+      const int p = t + s * T2, x = p / N, yp = p % N;
+      static_for<0, KP>([&](auto k) {
+        ld[(k * NN + x) * LD + yp] = w[s][k];
+        ld[(k * NN + x) * LD + yp + N] = w[s][N + k];
+      });
+    });
+    __syncthreads();
+    static_for<0, 2>([&](auto s) {
+      const int p = t + s * T2, kp = p / NN, y = p % NN;
+      static_for<0, NN>([&](auto xx) { w[s][xx] = ld[(kp * NN + xx) * LD + y]; });
+    });
+  };
+  round(vr);
+  round(vi);
+}
+
+// K_j rows of wave w's planes in both slots, and (wave 0) plane N, into the
+// start of the wave's slot-0 plane region: [slot 0: PW planes][slot 1: PW
+// planes][plane N], each plane P x P doubles.
+template <int NN>
+__device__ __forceinline__ void k_slice_dma_2(const double* Kj, float2* lds, int t, int T2) {
+  constexpr int N = NN / 2, P = N + 1, PP = P * P, PW = 64 / NN, LD = NN + 1;
+  const int wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64;
+  float* dst = reinterpret_cast<float*>(lds + wave * PW * NN * LD);
+  auto copy = [&](const float* src, float* d, int count) {
+    for (int c = 0; c * 64 < count; ++c) {
+      const int q = c * 64 + lane;
+      if (q < count)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + q),
+                                         (__attribute__((address_space(3))) void*)(d + c * 64), 4, 0, 0);
+    }
+  };
+  copy(reinterpret_cast<const float*>(Kj + (size_t)wave * PW * PP), dst, PW * PP * 2);
+  copy(reinterpret_cast<const float*>(Kj + (size_t)(wave * PW + T2 / NN) * PP), dst + PW * PP * 2, PW * PP * 2);
+  if (wave == 0) copy(reinterpret_cast<const float*>(Kj + (size_t)N * PP), dst + 2 * PW * PP * 2, PP * 2);
+}
+
+}  // namespace
+
+template <int NN>
+__global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
+    const float* __restrict__ h, float* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
+    const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
+    const float* __restrict__ nu, const float* __restrict__ Phi, const float* __restrict__ Om,
+    double2* __restrict__ slots, int J, const int* __restrict__ gate) {
+  using C = Cfg<NN>;
+  if (gate && *gate == 0) return;   // a gated-off step of the device-resident GMRES
+  constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, PW = 64 / NN, LD = C::LD;
+  constexpr int T2 = C::T / 2;
+  __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
+  __shared__ double fs[9 * NN + 3];
+  __shared__ float tab[Q];
+  const int t0 = threadIdx.x;
+  // Scratch slot of this workgroup: the spectrum of r (KP*NP complex double),
+  // element i of pencil p at i*T + p.
+  double2* Rs = slots + (size_t)blockIdx.x * (KP * NP);
+
+  for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
+    const int cc = Bc > 1 ? cell : 0;
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const int ia = t % NN;                       // Y / X roles, both slots
+    const int zyp = t % N;                       // Z role, both slots
+    const int fx = ia <= N ? ia : NN - ia;
+    __syncthreads();
+    for (int i = t; i < 6 * NN; i += T2) fs[i] = fac64[(size_t)cc * 6 * NN + i];
+    if (t < 2) fs[6 * NN + t] = pref64[2 * cc + t];
+    for (int q = t; q < Q; q += T2) tab[q] = Om[q];
+    __syncthreads();
+    for (int i = t; i < 3 * NN; i += T2) fs[6 * NN + 2 + i] = 1.0 / fs[i];
+    if (t == 0) fs[9 * NN + 2] = 1.0 / fs[6 * NN];
+    __syncthreads();
+    const double* ex = fs;
+    const double* eh = fs + 3 * NN;
+    const double prefM = fs[6 * NN], prefH = fs[6 * NN + 1];
+
+    // ---------------- loss: U = iDFT[Omega DFT[h]] in float -------------------------
+    {
+      float fr[2][NN], fi[2][NN];
+      static_for<0, 2>([&](auto s) {
+        const int zx = (t + s * T2) / N;
+        const float* h1 = h + ((size_t)cell * NP + zx * NN + zyp) * NN;
+        const float* h2 = h1 + (size_t)N * NN;
+        float zr[NN], zi[NN];
+        static_for<0, NN>([&](auto z) { zr[z] = h1[z]; zi[z] = h2[z]; });
+        z_forward<NN, float>(zr, zi, fr[s], fi[s]);
+      });
+      z_to_x_2<NN, float>(fr, fi, lds, t, T2);
+      static_for<0, 2>([&](auto s) {
+        const int p = t + s * T2, kp = p / NN;
+        fft<NN, false>(fr[s], fi[s]);
+        transpose_plane<NN, float>(fr[s], fi[s], lds, p);
+        fft<NN, false>(fr[s], fi[s]);
+        mode_multiply<NN, float>(fr[s], fi[s], p, [&](auto ky) {   // Omega(|k|^2) / n^3
+          constexpr int fy = ky <= N ? ky : NN - ky;
+          const int q = fx * fx + fy * fy;
+          return float2{tab[q + kp * kp], tab[q + N * N]};
+        });
+        fft<NN, true>(fr[s], fi[s]);
+        transpose_plane<NN, float>(fr[s], fi[s], lds, p);
+        fft<NN, true>(fr[s], fi[s]);
+      });
+      x_to_z_2<NN, float>(fr, fi, lds, t, T2);
+      static_for<0, 2>([&](auto s) {
+        const int zx = (t + s * T2) / N, col1 = zx * NN + zyp;
+        const float* h1 = h + ((size_t)cell * NP + col1) * NN;
+        const float* h2 = h1 + (size_t)N * NN;
+        float zr[NN], zi[NN];
+        z_inverse<NN, float>(fr[s], fi[s], zr, zi);
+        const float* n1 = nu + ((size_t)cc * NP + col1) * NN;
+        const float* n2 = n1 + (size_t)N * NN;
+        float* o1 = out + ((size_t)cell * NP + col1) * NN;
+        float* o2 = o1 + (size_t)N * NN;
+        const double mxy1 = prefM * ex[zx] * ex[NN + zyp], mxy2 = prefM * ex[zx] * ex[NN + zyp + N];
+        static_for<0, NN>([&](auto z) {
+          const double ez = ex[2 * NN + z];
+          o1[z] = float(-(mxy1 * ez) * double(zr[z]) - double(n1[z]) * double(h1[z]));
+          o2[z] = float(-(mxy2 * ez) * double(zi[z]) - double(n2[z]) * double(h2[z]));
+        });
+      });
+    }
+    // ---------------- R = DFT[chi h / M]: double arithmetic, double result --------
+    {
+      double vr[2][NN], vi[2][NN];
+      static_for<0, 2>([&](auto s) {
+        const int zx = (t + s * T2) / N, col1 = zx * NN + zyp;
+        const float* h1 = h + ((size_t)cell * NP + col1) * NN;
+        const float* h2 = h1 + (size_t)N * NN;
+        const uint32_t* mk1 = mask + ((size_t)cc * NP + col1) * MW;
+        const uint32_t* mk2 = mk1 + (size_t)N * MW;
+        uint32_t b1[MW], b2[MW];
+        static_for<0, MW>([&](auto w) { b1[w] = mk1[w]; b2[w] = mk2[w]; });
+        const double* rx = fs + 6 * NN + 2;
+        const double rxy = fs[9 * NN + 2] * rx[zx];
+        const double r1 = rxy * rx[NN + zyp], r2 = rxy * rx[NN + zyp + N];
+        double zr[NN], zi[NN];
+        static_for<0, NN>([&](auto z) {
+          const double rz = rx[2 * NN + z];
+          const double q1 = double(h1[z]) * (r1 * rz), q2 = double(h2[z]) * (r2 * rz);
+          zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? q1 : 0.0;
+          zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? q2 : 0.0;
+        });
+        z_forward<NN, double>(zr, zi, vr[s], vi[s]);
+      });
+      z_to_x_2d<NN>(vr, vi, lds, t, T2);
+      static_for<0, 2>([&](auto s) {
+        const int p = t + s * T2;
+        fft<NN, false>(vr[s], vi[s]);
+        transpose_plane_d<NN>(vr[s], vi[s], lds, p);
+        fft<NN, false>(vr[s], vi[s]);
+        static_for<0, NN>([&](auto ky) { Rs[ky * C::T + p] = double2{vr[s][ky], vi[s][ky]}; });
+      });
+    }
+    k_slice_dma_2<NN>(Kh + (size_t)cc * J * kh_stride(NN), lds, t, T2);   // K_0 into this wave's region
+
+    // ---------------- gain loop: L+^ stays in registers -----------------------------
+    float Lr[2][NN], Li[2][NN];
+    static_for<0, 2>([&](auto s) {
+      static_for<0, NN>([&](auto k) { Lr[s][k] = 0.f; Li[s][k] = 0.f; });
+    });
+    for (int j = 0; j < J; ++j) {
+      asm volatile("" : "+v"(t));
+      float fr[2][NN], fi[2][NN];
+      {
+        double vr[2][NN], vi[2][NN];
+        static_for<0, 2>([&](auto s) {
+          const int p = t + s * T2;
+          static_for<0, NN>([&](auto ky) {
+            const double2 v = Rs[ky * C::T + p];
+            vr[s][ky] = v.x;
+            vi[s][ky] = v.y;
+          });
+        });
+        __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copy of K_j has landed
+        const double* Kw = reinterpret_cast<const double*>(lds + (t / 64) * PW * NN * LD);
+        static_for<0, 2>([&](auto s) {
+          const int p = t + s * T2, kw = (t % 64) / NN + s * PW;
+          mode_multiply<NN, double>(vr[s], vi[s], p, [&](auto ky) {     // K_j / n^3
+            constexpr int fy = ky <= N ? ky : NN - ky;
+            return double2{Kw[(kw * P + fy) * P + fx], Kw[(2 * PW * P + fy) * P + fx]};
+          });
+        });
+        static_for<0, 2>([&](auto s) {
+          const int p = t + s * T2;
+          fft<NN, true>(vr[s], vi[s]);
+          transpose_plane_d<NN>(vr[s], vi[s], lds, p);
+          fft<NN, true>(vr[s], vi[s]);
+        });
+        x_to_z_2d<NN>(vr, vi, lds, t, T2);
+        // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
+        // the z stage runs.  It is complete and visible after the wait and
+        // first barrier of the next X <- Z exchange.
+        lds_dma(Phi + (size_t)j * phi_stride(NN), tab, Q, t, T2);
+        static_for<0, 2>([&](auto s) {
+          const int zx = (t + s * T2) / N;
+          double zr[NN], zi[NN];
+          z_inverse<NN, double>(vr[s], vi[s], zr, zi);
+          const double hx = prefH * eh[zx];
+          const double g1 = hx * eh[NN + zyp], g2 = hx * eh[NN + zyp + N];
+          float qr[NN], qi[NN];
+          static_for<0, NN>([&](auto z) {
+            const double ez = eh[2 * NN + z];
+            qr[z] = float(zr[z] * (g1 * ez));
+            qi[z] = float(zi[z] * (g2 * ez));
+          });
+          z_forward<NN, float>(qr, qi, fr[s], fi[s]);
+        });
+      }
+      __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
+      z_to_x_2<NN, float>(fr, fi, lds, t, T2);
+      static_for<0, 2>([&](auto s) {
+        const int p = t + s * T2;
+        fft<NN, false>(fr[s], fi[s]);
+        transpose_plane<NN, float>(fr[s], fi[s], lds, p);
+      });
+      // This wave is done with its regions until the next node's K_j product;
+      // its transpose reads complete (lgkmcnt(0)) before the copy may land.
+      if (j + 1 < J) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        k_slice_dma_2<NN>(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), lds, t, T2);
+      }
+      static_for<0, 2>([&](auto s) {
+        const int p = t + s * T2, kp = p / NN;
+        fft<NN, false>(fr[s], fi[s]);
+        mode_multiply<NN, float>(fr[s], fi[s], p, [&](auto ky) {       // Phi_j / n^3
+          constexpr int fy = ky <= N ? ky : NN - ky;
+          const int q = fx * fx + fy * fy;
+          return float2{tab[q + kp * kp], tab[q + N * N]};
+        });
+        static_for<0, NN>([&](auto k) {
+          Lr[s][k] += fr[s][k];
+          Li[s][k] += fi[s][k];
+        });
+      });
+    }
+    // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
+    static_for<0, 2>([&](auto s) {
+      const int p = t + s * T2;
+      fft<NN, true>(Lr[s], Li[s]);
+      transpose_plane<NN, float>(Lr[s], Li[s], lds, p);
+      fft<NN, true>(Lr[s], Li[s]);
+    });
+    x_to_z_2<NN, float>(Lr, Li, lds, t, T2);
+    static_for<0, 2>([&](auto s) {
+      const int zx = (t + s * T2) / N, col1 = zx * NN + zyp;
+      float zr[NN], zi[NN];
+      z_inverse<NN, float>(Lr[s], Li[s], zr, zi);
+      float* o1 = out + ((size_t)cell * NP + col1) * NN;
+      float* o2 = o1 + (size_t)N * NN;
+      static_for<0, NN>([&](auto z) {
+        o1[z] = o1[z] + zr[z];
+        o2[z] = o2[z] + zi[z];
+      });
+    });
+  }
+}
+
 bool fused_supported(int n, int dtype) { return dtype == 1 && (n == 16 || n == 32); }
 
-size_t fused_scratch_bytes(int n, int nslots) {
-  // per slot: R (complex double) and the L+ accumulator (complex float)
-  return (size_t)nslots * (n / 2) * n * n * (sizeof(double2) + sizeof(float2));
+size_t fused_scratch_bytes(int n, int nslots, int ppt) {
+  // per slot: R (complex double) and, with one pencil per thread, the L+
+  // accumulator (complex float); with two it stays in registers
+  return (size_t)nslots * (n / 2) * n * n * (sizeof(double2) + (ppt == 2 ? 0 : sizeof(float2)));
 }
 
 // Workgroups resident per compute unit: n = 32 needs all of a CU's LDS, the
@@ -543,14 +885,23 @@ hipError_t fused_apply(const ApplyCtx& c) {
   const float* Phi = static_cast<const float*>(c.Phi);
   const float* Om = static_cast<const float*>(c.Om);
   double2* scr = static_cast<double2*>(c.R);
+  const bool two = c.fused_ppt == 2;
   switch (c.n) {
     case 16:
-      k_fused<16><<<slots, Cfg<16>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
-                                                       Phi, Om, scr, c.J, c.gate);
+      if (two)
+        k_fused2<16><<<slots, Cfg<16>::T / 2, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh,
+                                                              nu, Phi, Om, scr, c.J, c.gate);
+      else
+        k_fused<16><<<slots, Cfg<16>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
+                                                         Phi, Om, scr, c.J, c.gate);
       break;
     case 32:
-      k_fused<32><<<slots, Cfg<32>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
-                                                       Phi, Om, scr, c.J, c.gate);
+      if (two)
+        k_fused2<32><<<slots, Cfg<32>::T / 2, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh,
+                                                              nu, Phi, Om, scr, c.J, c.gate);
+      else
+        k_fused<32><<<slots, Cfg<32>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
+                                                         Phi, Om, scr, c.J, c.gate);
       break;
     default:
       return hipErrorInvalidValue;

@@ -195,3 +195,21 @@ def test_autotune_cache_by_key():
     p3.set_maxwellians(dev(params[:3], torch.float64))
     p3.autotune(dev(h[:3], torch.float64), reps=1)      # batch bucket 4, not 8
     assert p3.info("tune_cached") == 0
+
+
+@pytest.mark.parametrize("n,batch", [(16, 21), (32, 37)])
+def test_fused_two_pencils_per_thread(n, batch):
+    """The fused kernel with two pencils per thread (one wave per SIMD, the
+    L+^ accumulator in registers) against the one-pencil kernel on the same
+    inputs (the same arithmetic in the same order) and against the oracle."""
+    L, om = 8.0, 0.74
+    h, params = mixed_inputs(n, L, batch, seed=3200 + n)
+    hin = h.astype(np.float32).astype(np.float64)
+    one = eager_result(n, L, om, "f32", "fused", hin, params, fused_ppt=1).double().numpy()
+    two = eager_result(n, L, om, "f32", "fused", hin, params, fused_ppt=2).double().numpy()
+    d = np.max(np.abs(two - one)) / np.max(np.abs(one))
+    print(f"n={n}: max |two - one| / max |one| = {d:.3e}")
+    assert d <= 1e-6, d
+    sample = [0, batch // 2, batch - 1]
+    orc = alg1.apply_batch(fd.make_plan(n, L, om), hin[sample], params[sample])
+    check_cells(two, orc, 1e-5, cells=sample)
