@@ -506,6 +506,8 @@ def main():
     ap.add_argument("--graph", type=int, default=None, help="force graph replay off (0) or on (1)")
     ap.add_argument("--fused-ppt", type=int, default=None, choices=[1, 2],
                     help="fused path: force one or two pencils per thread (skips the tuner)")
+    ap.add_argument("--fused-keep", type=int, default=None, choices=[0, 4, 8, 16],
+                    help="fused path: force the accumulator chunks kept in registers (skips the tuner)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (reference kernel for counter runs)")
     a = ap.parse_args()
@@ -561,6 +563,9 @@ def main():
         if a.fused_ppt is not None:
             plan.set_option("fused_ppt", a.fused_ppt)
             a.no_tune = True
+        if a.fused_keep is not None:
+            plan.set_option("fused_keep", a.fused_keep)
+            a.no_tune = True
         if not a.no_tune and a.path == "auto":
             tuned_ms = plan.autotune(ht, out, reps=3)   # untimed; picks path, workgroups/CU, graph replay
         if a.graph is not None:
@@ -569,9 +574,12 @@ def main():
         launch = {"path": path, "graph": int(plan.info("graph")), "tuned_ms": tuned_ms,
                   "fused_per_cu": int(plan.info("fused_per_cu")) if path == "fused" else None,
                   "fused_pencils_per_thread": int(plan.info("fused_ppt")) if path == "fused" else None,
+                  "fused_accumulator_chunks_in_registers": int(plan.info("fused_keep"))
+                  if path == "fused" and plan.info("fused_ppt") == 1 else None,
                   "staged_zblock": int(plan.info("zblock")) if path == "staged" else None,
                   "staged_plane_tile": int(plan.info("plane_tile")) if path == "staged" else None,
-                  "tuner": "lincoll_autotune over path x workgroups/CU x staged tiles x graph"}
+                  "tuner": "lincoll_autotune over path x workgroups/CU x fused pencils per thread x fused "
+                           "accumulator split x staged tiles x graph"}
         for _ in range(a.warmup):
             plan.apply(ht, out)
         stream.synchronize()

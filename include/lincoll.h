@@ -159,6 +159,7 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_PLANE_TILE 16   /* staged path: in-plane tile (0: 64 threads, 1: 32 threads per block) */
 #define LINCOLL_INFO_TUNE_CACHED 17  /* 1 if the last lincoll_autotune took its result from the cache */
 #define LINCOLL_INFO_FUSED_PPT 18    /* fused path: pencils per thread (LINCOLL_OPT_FUSED_PPT) */
+#define LINCOLL_INFO_FUSED_KEEP 19   /* fused path: accumulator chunks kept in registers, in effect */
 /* Reads one plan property into *val.  With plan == NULL only
  * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
  * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */
@@ -193,9 +194,16 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
                                          threads per block, i.e. 64/n or 32/n planes per block */
 #define LINCOLL_OPT_TUNE_CACHE 9      /* 1 (default): lincoll_autotune reuses a cached result; 0: always times */
 #define LINCOLL_OPT_FUSED_PPT 10      /* fused path: pencils per thread, 1 (default: two waves per SIMD, the L+^
-                                         accumulator streamed through the workgroup's scratch slot every node) or
-                                         2 (one wave per SIMD with the whole register file per lane; the
-                                         accumulator stays in registers).  Same arithmetic, bitwise equal results */
+                                         accumulator partly streamed through the workgroup's scratch slot every
+                                         node, see LINCOLL_OPT_FUSED_KEEP) or 2 (one wave per SIMD with the whole
+                                         register file per lane; the accumulator stays in registers).  The same
+                                         arithmetic; results agree to float rounding (the two kernels are
+                                         compiled separately and may contract differently) */
+#define LINCOLL_OPT_FUSED_KEEP 11     /* fused path, one pencil per thread: how many chunks (of two complex
+                                         values) of each thread's L+^ accumulator stay in registers across the
+                                         quadrature nodes instead of making a round trip through the scratch slot:
+                                         0, 4, 8 (of 8 at n = 16; of 16 at n = 32), 16 (n = 32), or -1 for the
+                                         default (8).  Results are bitwise the same for every value */
 #define LINCOLL_OPT_QUAD_FIX 6        /* quadcoll: mass fix of Sec. 2.3 -- 0 none (default); 1 Q^_0 = 0 (eq. (15)),
                                          the per-cell mean of Q removed; 2 the sinc of the loss term replaced by
                                          its estimate on the hemisphere rule (eq. (16)), a [n]^3 FP64 table the

@@ -59,6 +59,7 @@ struct lincoll_plan_s {
   // options (lincoll_set_option)
   int opt_graph = 0, opt_per_cu = 0;
   int opt_zblk = 128, opt_tile = 0, opt_tune_cache = 1, opt_ppt = 1;
+  int opt_keep = -1;   // fused accumulator chunks kept in registers (-1: the default for n)
   double tuned_ms = 0.0;
   int tuned_cached = 0;
   std::string arch;           // gcnArchName of the plan's device (key of the tuner's cache)
@@ -167,6 +168,13 @@ lincoll_params_t resolved(const lincoll_params_t* in) {
   if (p.R <= 0.0) p.R = 4.0 * p.L / (3.0 + std::sqrt(2.0));
   if (p.J <= 0) p.J = p.n / 2 + 1;
   return p;
+}
+
+// Accumulator chunks the fused kernel keeps in registers: the plan's option,
+// else the default for n (the fastest measured on MI355X).
+int fused_keep(const lincoll_plan_s* pl) {
+  if (pl->opt_keep >= 0) return pl->opt_keep;
+  return 8;
 }
 
 bool use_fused(const lincoll_plan_s* pl) {
@@ -481,6 +489,7 @@ ApplyCtx apply_ctx(lincoll_plan_t pl, const void* hin, void* out, int batch, hip
   c.per_cu = pl->opt_per_cu;
   c.zblk = pl->opt_zblk;
   c.fused_ppt = pl->opt_ppt;
+  c.fused_keep = fused_keep(pl);
   c.plane_tile = pl->opt_tile;
   c.dtype = pl->p.dtype;
   c.stream = stream;
@@ -640,6 +649,10 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       if (value != 1 && value != 2) return LINCOLL_EINVAL;
       pl->opt_ppt = value;
       break;
+    case LINCOLL_OPT_FUSED_KEEP:
+      if (value != -1 && !fused_keep_valid(pl->p.n, value)) return LINCOLL_EINVAL;
+      pl->opt_keep = value;
+      break;
     case LINCOLL_OPT_TUNE_CACHE:
       if (value != 0 && value != 1) return LINCOLL_EINVAL;
       pl->opt_tune_cache = value;
@@ -662,7 +675,7 @@ namespace {
 // A launch configuration of the apply: path, fused workgroups per CU,
 // staged tile (z-pass block size, in-plane tile) and graph replay.
 struct Tuned {
-  int path, per_cu, zblk, tile, graph, ppt;
+  int path, per_cu, zblk, tile, graph, ppt, keep;
   double ms;
 };
 
@@ -686,6 +699,7 @@ void apply_tuned(lincoll_plan_t pl, const Tuned& t) {
   pl->opt_tile = t.tile;
   pl->opt_graph = t.graph;
   pl->opt_ppt = t.ppt;
+  pl->opt_keep = t.keep;
   pl->tuned_ms = t.ms;
   drop_graph(pl);
 }
@@ -712,13 +726,17 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
     if (staged_supported(n, dt))
       for (int zb : {64, 128, 256})
         for (int tile = 0; tile <= (n <= 32 ? 1 : 0); ++tile)
-          cands.push_back({LINCOLL_PATH_STAGED, 0, zb, tile, g, 1, 0.0});
+          cands.push_back({LINCOLL_PATH_STAGED, 0, zb, tile, g, 1, -1, 0.0});
     if (fused_supported(n, dt))
-      for (int ppt = 1; ppt <= 2; ++ppt)
-        for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, ppt, 0.0});
+      for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) {
+        for (int keep : {0, 4, 8, 16})
+          if (fused_keep_valid(n, keep)) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 1, keep, 0.0});
+        cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 2, -1, 0.0});
+      }
   }
   if (cands.empty()) return LINCOLL_EINVAL;
-  const Tuned saved{pl->p.path, pl->opt_per_cu, pl->opt_zblk, pl->opt_tile, pl->opt_graph, pl->opt_ppt, pl->tuned_ms};
+  const Tuned saved{pl->p.path, pl->opt_per_cu, pl->opt_zblk, pl->opt_tile, pl->opt_graph, pl->opt_ppt, pl->opt_keep,
+                    pl->tuned_ms};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e;
   if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
@@ -1013,6 +1031,7 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_PLANE_TILE: *val = pl->opt_tile; break;
     case LINCOLL_INFO_TUNE_CACHED: *val = pl->tuned_cached; break;
     case LINCOLL_INFO_FUSED_PPT: *val = pl->opt_ppt; break;
+    case LINCOLL_INFO_FUSED_KEEP: *val = fused_keep(pl); break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;

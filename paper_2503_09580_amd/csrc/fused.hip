@@ -291,9 +291,55 @@ __device__ __forceinline__ void mode_multiply(T (&vr)[NN], T (&vi)[NN], int t, G
   }
 }
 
+// Doubles of wave 0's copy of K_j in its LDS region: its PW planes and the
+// Nyquist plane kz = N.
+template <int NN>
+constexpr int kslice_doubles() { return (64 / NN + 1) * (NN / 2 + 1) * (NN / 2 + 1); }
+
+// The same product for the FP64 pencils of the K_j step, written so that no
+// branch produces a second copy of the pencil (a divergent or wave-level
+// branch whose two sides both rewrite all 2 NN doubles made the compiler keep
+// both, which spilled the whole gain loop).  Every lane multiplies by its own
+// plane's factor; on the packed plane that factor is s = (m0 + mN)/2, which
+// wave 0 writes over m0 in its LDS copy (and d = (m0 - mN)/2 over mN), and
+// the packed lanes then add d conj(v(-k)) in place, one component at a time:
+// the real part of v' = s v + d conj(v(-k)) needs only real parts, the
+// imaginary part only imaginary parts.  The partner values come from a free
+// part of wave 0's own region, after the K_j copy.
+template <int NN, typename G>
+__device__ __forceinline__ void mode_multiply_d(double (&vr)[NN], double (&vi)[NN], int t, double* region, G&& getm) {
+  constexpr int P = NN / 2 + 1, PP = P * P, PW = 64 / NN;
+  constexpr int OFF = (kslice_doubles<NN>() + 63) / 64 * 64;
+  static_assert(OFF + NN * NN <= PW * NN * (NN + 1), "partner buffer exceeds the wave's LDS region");
+  const bool packed = t < NN;                       // plane 0, wave 0
+  const int lane = t % NN, partner = (NN - lane) % NN;
+  double* buf = region + OFF;
+  if (__builtin_amdgcn_readfirstlane(t) < 64)       // wave 0 (a wave-uniform branch)
+    for (int q = t; q < PP; q += 64) {
+      const double m0 = region[q], mN = region[PW * PP + q];
+      region[q] = 0.5 * (m0 + mN);
+      region[PW * PP + q] = 0.5 * (m0 - mN);
+    }
+  auto one = [&](double(&w)[NN], double sign) {
+    if (packed) static_for<0, NN>([&](auto j) { buf[j * NN + lane] = w[j]; });
+    wave_lds_sync();
+    static_for<0, NN>([&](auto j) { w[j] *= getm(j).x; });
+    if (packed)
+      static_for<0, NN>([&](auto j) {
+        constexpr int jm = (NN - j) % NN;
+        w[j] = fma(sign * getm(j).y, buf[jm * NN + partner], w[j]);
+      });
+    wave_lds_sync();
+  };
+  one(vr, 1.0);
+  one(vi, -1.0);
+}
+
 }  // namespace
 
-template <int NN>
+// KA: chunks (of two complex values) of each thread's L+^ accumulator that
+// stay in registers across the nodes; the others stream through the slot.
+template <int NN, int KA>
 __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     const float* __restrict__ h, float* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
     const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
@@ -403,10 +449,13 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     k_slice_dma<NN>(Kh + (size_t)cc * J * kh_stride(NN), lds, t);   // K_0 into this wave's region
 
     // ---------------- gain loop ---------------------------------------------------
-    // The running sum of Phi_j Q_j lives in the scratch slot between nodes (it
-    // is loaded back only during the float part of a node, where registers are
-    // free); after the last node it stays in registers.
+    // The running sum of Phi_j Q_j: its first KA chunks stay in registers, the
+    // others live in the scratch slot between nodes (loaded back only during
+    // the float part of a node, where registers are free); after the last
+    // node all of it is in registers.
     float Lr[NN], Li[NN];
+    float4 keep[KA > 0 ? KA : 1];
+    static_for<0, KA>([&](auto c) { keep[c] = float4{0.f, 0.f, 0.f, 0.f}; });
     for (int j = 0; j < J; ++j) {
       asm volatile("" : "+v"(t));
       float fr[NN], fi[NN];
@@ -418,9 +467,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
           vi[ky] = v.y;
         });
         __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copy of K_j has landed
-        const double* Kw = reinterpret_cast<const double*>(lds + (t / 64) * PW * NN * LD);
+        double* Kw = reinterpret_cast<double*>(lds + (t / 64) * PW * NN * LD);
         const int kw = kp - (t / 64) * PW;
-        mode_multiply<NN, double>(vr, vi, t, [&](auto ky) {     // K_j / n^3
+        mode_multiply_d<NN>(vr, vi, t, Kw, [&](auto ky) {     // K_j / n^3
           constexpr int fy = ky <= N ? ky : NN - ky;
           return double2{Kw[(kw * P + fy) * P + fx], Kw[(PW * P + fy) * P + fx]};
         });
@@ -448,7 +497,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
       z_to_x<NN, float>(fr, fi, lds, t);
       float4 acc[NN / 2];
-      static_for<0, NN / 2>([&](auto c) { acc[c] = j > 0 ? Ac[c * C::T + t] : float4{0.f, 0.f, 0.f, 0.f}; });
+      static_for<KA, NN / 2>([&](auto c) { acc[c] = j > 0 ? Ac[c * C::T + t] : float4{0.f, 0.f, 0.f, 0.f}; });
       fft<NN, false>(fr, fi);
       transpose_plane<NN, float>(fr, fi, lds, t);
       // This wave is done with its region until the next node's K_j product;
@@ -464,14 +513,17 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         return float2{tab[q + kp * kp], tab[q + N * N]};
       });
       static_for<0, NN / 2>([&](auto c) {
-        Lr[2 * c] = acc[c].x + fr[2 * c];
-        Li[2 * c] = acc[c].y + fi[2 * c];
-        Lr[2 * c + 1] = acc[c].z + fr[2 * c + 1];
-        Li[2 * c + 1] = acc[c].w + fi[2 * c + 1];
+        float4 a;
+        if constexpr (c < KA) a = keep[c]; else a = acc[c];
+        Lr[2 * c] = a.x + fr[2 * c];
+        Li[2 * c] = a.y + fi[2 * c];
+        Lr[2 * c + 1] = a.z + fr[2 * c + 1];
+        Li[2 * c + 1] = a.w + fi[2 * c + 1];
       });
       if (j + 1 < J)
         static_for<0, NN / 2>([&](auto c) {
-          Ac[c * C::T + t] = float4{Lr[2 * c], Li[2 * c], Lr[2 * c + 1], Li[2 * c + 1]};
+          const float4 v{Lr[2 * c], Li[2 * c], Lr[2 * c + 1], Li[2 * c + 1]};
+          if constexpr (c < KA) keep[c] = v; else Ac[c * C::T + t] = v;
         });
     }
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
@@ -875,6 +927,10 @@ hipError_t fused_noalloc_scratch(int device, void** ptr, size_t* bytes) {
   return hipSuccess;
 }
 
+bool fused_keep_valid(int n, int keep) {
+  return keep == 0 || keep == 4 || keep == 8 || (n == 32 && keep == 16);
+}
+
 hipError_t fused_apply(const ApplyCtx& c) {
   int slots = fused_slots(c.n, c.batch, c.per_cu, c.cus);
   if (c.max_slots > 0 && slots > c.max_slots) slots = c.max_slots;   // the kernel is persistent over cells
@@ -885,23 +941,25 @@ hipError_t fused_apply(const ApplyCtx& c) {
   const float* Phi = static_cast<const float*>(c.Phi);
   const float* Om = static_cast<const float*>(c.Om);
   double2* scr = static_cast<double2*>(c.R);
+  if (!fused_keep_valid(c.n, c.fused_keep)) return hipErrorInvalidValue;
+  auto one = [&](auto kernel, int threads) {
+    kernel<<<slots, threads, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu, Phi, Om, scr,
+                                            c.J, c.gate);
+  };
   const bool two = c.fused_ppt == 2;
   switch (c.n) {
     case 16:
-      if (two)
-        k_fused2<16><<<slots, Cfg<16>::T / 2, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh,
-                                                              nu, Phi, Om, scr, c.J, c.gate);
-      else
-        k_fused<16><<<slots, Cfg<16>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
-                                                         Phi, Om, scr, c.J, c.gate);
+      if (two) one(k_fused2<16>, Cfg<16>::T / 2);
+      else if (c.fused_keep == 0) one(k_fused<16, 0>, Cfg<16>::T);
+      else if (c.fused_keep == 4) one(k_fused<16, 4>, Cfg<16>::T);
+      else one(k_fused<16, 8>, Cfg<16>::T);
       break;
     case 32:
-      if (two)
-        k_fused2<32><<<slots, Cfg<32>::T / 2, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh,
-                                                              nu, Phi, Om, scr, c.J, c.gate);
-      else
-        k_fused<32><<<slots, Cfg<32>::T, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu,
-                                                         Phi, Om, scr, c.J, c.gate);
+      if (two) one(k_fused2<32>, Cfg<32>::T / 2);
+      else if (c.fused_keep == 0) one(k_fused<32, 0>, Cfg<32>::T);
+      else if (c.fused_keep == 4) one(k_fused<32, 4>, Cfg<32>::T);
+      else if (c.fused_keep == 8) one(k_fused<32, 8>, Cfg<32>::T);
+      else one(k_fused<32, 16>, Cfg<32>::T);
       break;
     default:
       return hipErrorInvalidValue;

@@ -112,12 +112,38 @@ def test_fused_workgroups_per_cu_do_not_change_results(per_cu):
     assert torch.equal(got, ref)
 
 
+@pytest.mark.parametrize("n,batch", [(16, 23), (32, 19)])
+def test_fused_kept_accumulator_is_bitwise_identical(n, batch):
+    """Every split of the L+^ accumulator between registers and the scratch
+    slot (LINCOLL_OPT_FUSED_KEEP) adds the same float values in the same
+    order, so the results are bitwise equal; one of them is checked against
+    the oracle, including the packed plane's partner correction of the K_j
+    product (cells with drift, so that plane is not symmetric)."""
+    L, om = 8.0, 0.74
+    h, params = mixed_inputs(n, L, batch, seed=1300 + n)
+    hin = h.astype(np.float32).astype(np.float64)
+    keeps = [0, 4, 8] + ([16] if n == 32 else [])
+    outs = [eager_result(n, L, om, "f32", "fused", hin, params, fused_keep=k) for k in keeps]
+    for k, o in zip(keeps[1:], outs[1:]):
+        assert torch.equal(o, outs[0]), k
+    sample = [0, batch // 2, batch - 1]
+    orc = alg1.apply_batch(fd.make_plan(n, L, om), hin[sample], params[sample])
+    check_cells(outs[-1].double().numpy(), orc, 1e-5, cells=sample)
+
+
 def test_option_errors():
     lib = lc.library()
     plan = lc.Plan(32, 8.0, 0.74, "f32")
     assert lib.lincoll_set_option(plan._h, lc.OPTIONS["fused_per_cu"], 2) == lc.EINVAL   # n = 32 fits one
     assert lib.lincoll_set_option(plan._h, lc.OPTIONS["graph"], 2) == lc.EINVAL
     assert lib.lincoll_set_option(plan._h, 99, 0) == lc.EINVAL
+    for bad in (-2, 2, 12, 32):
+        assert lib.lincoll_set_option(plan._h, lc.OPTIONS["fused_keep"], bad) == lc.EINVAL
+    assert lib.lincoll_set_option(plan._h, lc.OPTIONS["fused_keep"], 16) == lc.OK
+    assert plan.info("fused_keep") == 16
+    assert lib.lincoll_set_option(plan._h, lc.OPTIONS["fused_keep"], -1) == lc.OK
+    p16 = lc.Plan(16, 8.0, 0.74, "f32")
+    assert lib.lincoll_set_option(p16._h, lc.OPTIONS["fused_keep"], 16) == lc.EINVAL   # 8 chunks at n = 16
     p64 = lc.Plan(32, 8.0, 0.74, "f64")
     assert lib.lincoll_set_option(p64._h, lc.OPTIONS["path"], lc.PATHS["fused"]) == lc.EINVAL
     x = torch.zeros((2, 32, 32, 32), dtype=torch.float32, device=DEV)
