@@ -24,8 +24,9 @@
 // that size over the box and cost up to 1.8e-5 of max |L| element-wise.
 // After the product with M^h everything runs in float.
 //
-// LDS: one float2 volume for the exchanges, the radial table of the node
-// and the 1-D Maxwellian factors.  The kernel modes K_j of a node are needed
+// LDS: one float2 volume for the exchanges, the radial table of the node,
+// the 1-D Maxwellian factors and (n = 32) two chunks of each thread's L+^
+// accumulator.  The kernel modes K_j of a node are needed
 // only in the Y role, where each wave handles its own planes: each wave
 // copies its planes of K_j (and, wave 0, the Nyquist plane kz = N) into its
 // own region of the exchange volume, which no other wave touches between the
@@ -351,6 +352,10 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
   __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
   __shared__ double fs[9 * NN + 3];
   __shared__ float tab[Q];
+  // Accumulator chunks KA .. KA + KL - 1 live in LDS, each thread's own (the
+  // 16 KB left over at n = 32 beside the exchange volume and the tables).
+  constexpr int KL = (NN == 32 && KA < NN / 2) ? (NN / 2 - KA < 2 ? NN / 2 - KA : 2) : 0;
+  __shared__ float4 accl[KL > 0 ? KL : 1][KL > 0 ? C::T : 1];
   const int t0 = threadIdx.x;
   // Scratch slot of this workgroup: R (KP*NP complex double) then the L+
   // accumulator (KP*NP complex float).  Both are interleaved by thread
@@ -450,9 +455,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
 
     // ---------------- gain loop ---------------------------------------------------
     // The running sum of Phi_j Q_j: its first KA chunks stay in registers, the
-    // others live in the scratch slot between nodes (loaded back only during
-    // the float part of a node, where registers are free); after the last
-    // node all of it is in registers.
+    // next KL in LDS, the others in the scratch slot between nodes (loaded back
+    // only during the float part of a node, where registers are free); after
+    // the last node all of it is in registers.
     float Lr[NN], Li[NN];
     float4 keep[KA > 0 ? KA : 1];
     static_for<0, KA>([&](auto c) { keep[c] = float4{0.f, 0.f, 0.f, 0.f}; });
@@ -497,7 +502,10 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
       z_to_x<NN, float>(fr, fi, lds, t);
       float4 acc[NN / 2];
-      static_for<KA, NN / 2>([&](auto c) { acc[c] = j > 0 ? Ac[c * C::T + t] : float4{0.f, 0.f, 0.f, 0.f}; });
+      static_for<KA, NN / 2>([&](auto c) {
+        if constexpr (c < KA + KL) acc[c] = j > 0 ? accl[c - KA][t] : float4{0.f, 0.f, 0.f, 0.f};
+        else acc[c] = j > 0 ? Ac[c * C::T + t] : float4{0.f, 0.f, 0.f, 0.f};
+      });
       fft<NN, false>(fr, fi);
       transpose_plane<NN, float>(fr, fi, lds, t);
       // This wave is done with its region until the next node's K_j product;
@@ -523,7 +531,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       if (j + 1 < J)
         static_for<0, NN / 2>([&](auto c) {
           const float4 v{Lr[2 * c], Li[2 * c], Lr[2 * c + 1], Li[2 * c + 1]};
-          if constexpr (c < KA) keep[c] = v; else Ac[c * C::T + t] = v;
+          if constexpr (c < KA) keep[c] = v;
+          else if constexpr (c < KA + KL) accl[c - KA][t] = v;
+          else Ac[c * C::T + t] = v;
         });
     }
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
