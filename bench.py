@@ -52,7 +52,9 @@ KERNEL_SOURCES = {
     "fused": ["paper_2503_09580_amd/csrc/fused.hip", "paper_2503_09580_amd/csrc/fft.h",
               "paper_2503_09580_amd/csrc/twiddles.h", "paper_2503_09580_amd/csrc/internal.h"],
 }
-KERNEL_NAMES = {("fused", 32): "k_fused<32>", ("fused", 16): "k_fused<16>"}
+def fused_kernel_name(n, ppt, keep):
+    """Name of the fused kernel instance a plan launches (as in the profiles)."""
+    return f"k_fused2<{n}>" if ppt == 2 else f"k_fused<{n}, {keep}>"
 
 
 def kernel_source_hash(path):
@@ -627,7 +629,8 @@ def main():
     fl = alg_flops_per_cell(n, J) * B
     by = alg_bytes_per_cell(n, elem) * B
     achieved = fl / (ms_per_step / 1e3) / 1e12
-    kname = KERNEL_NAMES.get((path, n), "lincoll_apply (all launches of one step)")
+    kname = (fused_kernel_name(n, int(plan.info("fused_ppt")), int(plan.info("fused_keep"))) if path == "fused"
+             else "lincoll_apply (all launches of one step)")
     tr = traffic_record(kname, a.config, a.dtype, path) if path == "fused" else None
     rec["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / PEAK_VALU_TFLOPS,
