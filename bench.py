@@ -674,8 +674,19 @@ def main():
                 return e0.elapsed_time(e1) / reps
 
             with torch.cuda.stream(stream):
-                ms64 = timed(ref_plan, h64, torch.empty_like(h64))
-                others["f64"] = {"ms_per_step": ms64, "applies_per_s": B / (ms64 / 1e3), "path": "staged"}
+                # the paper's precision on the path an F64 plan takes by default
+                # (the fused kernel at n <= 32), and on the staged kernels
+                p64 = lincoll.Plan(n, L, om, "f64")
+                p64.set_maxwellians(pt)
+                o64 = torch.empty_like(h64)
+                ms64 = timed(p64, h64, o64)
+                path64 = "fused" if p64.info("path") == 2 else "staged"
+                ms64s = timed(ref_plan, h64, torch.empty_like(h64)) if path64 == "fused" else ms64
+                d64 = errs(o64)
+                others["f64"] = {"ms_per_step": ms64, "applies_per_s": B / (ms64 / 1e3), "path": path64,
+                                 "staged_ms_per_step": ms64s, "staged_applies_per_s": B / (ms64s / 1e3),
+                                 "max_rel_diff_vs_staged": max(d64["max"], d64["elementwise_max"])}
+                del p64, o64
                 if a.dtype != "bf16x3":
                     bp = lincoll.Plan(n, L, om, "bf16x3")
                     bp.set_maxwellians(pt)

@@ -55,7 +55,7 @@ typedef enum {
 typedef enum {
   LINCOLL_PATH_AUTO = 0,    /* fused kernel where it exists, otherwise the staged kernels */
   LINCOLL_PATH_STAGED = 1,  /* batched per-stage kernels (every n and dtype) */
-  LINCOLL_PATH_FUSED = 2    /* one persistent workgroup per cell (F32 at n = 16, 32) */
+  LINCOLL_PATH_FUSED = 2    /* one persistent workgroup per cell (F32 and F64 at n = 16, 32) */
 } lincoll_path_t;
 
 typedef struct {
@@ -109,13 +109,14 @@ int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
  * never records a graph: the fused kernel's per-workgroup scratch (the
  * spectrum of r and the L+ accumulator) lives in a fixed 96 MiB device array
  * of the library, one per GPU, held until the process ends, which limits
- * the persistent workgroups to 256 at n = 32 and 1024 at n = 16 (any batch
- * is processed; the workgroups loop over cells).  Nothing in that array needs
+ * the persistent workgroups to 256 at n = 32 and 1024 at n = 16 for F32
+ * plans, 192 and 1536 for F64 (whose accumulator is double); any batch is
+ * processed, the workgroups loop over cells.  Nothing in that array needs
  * to start at zero.  All calls on one GPU share it: calls that overlap in
  * time on one GPU (other streams, other plans, other threads) race and give
  * wrong results; serialise them.  Requirements beyond lincoll_apply's: the
- * plan's apply takes the fused path (LINCOLL_F32, n = 16 or 32, path AUTO or
- * FUSED), project = 0, the Maxwellians already set (lincoll_set_maxwellians
+ * plan's apply takes the fused path (LINCOLL_F32 or LINCOLL_F64, n = 16 or
+ * 32, path AUTO or FUSED), project = 0, the Maxwellians already set (lincoll_set_maxwellians
  * allocates), and the plan's device current; otherwise LINCOLL_EINVAL. */
 int lincoll_apply_noalloc(lincoll_plan_t plan, const void* h, void* out, int batch);
 
@@ -198,12 +199,17 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
                                          node, see LINCOLL_OPT_FUSED_KEEP) or 2 (one wave per SIMD with the whole
                                          register file per lane; the accumulator stays in registers).  The same
                                          arithmetic; results agree to float rounding (the two kernels are
-                                         compiled separately and may contract differently) */
-#define LINCOLL_OPT_FUSED_KEEP 11     /* fused path, one pencil per thread: how many chunks (of two complex
-                                         values) of each thread's L+^ accumulator stay in registers across the
-                                         quadrature nodes instead of making a round trip through the scratch slot:
-                                         0, 4, 8 (of 8 at n = 16; of 16 at n = 32), 16 (n = 32), or -1 for the
-                                         default (8).  Results are bitwise the same for every value */
+                                         compiled separately and may contract differently).  F32 plans only */
+#define LINCOLL_OPT_FUSED_KEEP 11     /* fused path, one pencil per thread: how many chunks of each thread's
+                                         L+^ accumulator stay in registers across the quadrature nodes instead of
+                                         making a round trip through LDS or the scratch slot.  F32 (chunks of two
+                                         complex floats): 0, 4, 8 (all at n = 16), 16 (n = 32, all); default 8.
+                                         F64 (chunks of one complex double): n = 16: 0, 8, 16 (all), default 16;
+                                         n = 32: 0, 4, 8, default 0.  -1 restores the default.  The same
+                                         additions in the same order for every value: F32 results are bitwise
+                                         equal; F64 results agree to a few units in the last place (the compiler
+                                         may contract the M^h product into the next addition differently in
+                                         each compiled instance) */
 #define LINCOLL_OPT_QUAD_FIX 6        /* quadcoll: mass fix of Sec. 2.3 -- 0 none (default); 1 Q^_0 = 0 (eq. (15)),
                                          the per-cell mean of Q removed; 2 the sinc of the loss term replaced by
                                          its estimate on the hemisphere rule (eq. (16)), a [n]^3 FP64 table the

@@ -174,7 +174,7 @@ lincoll_params_t resolved(const lincoll_params_t* in) {
 // else the default for n (the fastest measured on MI355X).
 int fused_keep(const lincoll_plan_s* pl) {
   if (pl->opt_keep >= 0) return pl->opt_keep;
-  return 8;
+  return fused_default_keep(pl->p.n, pl->p.dtype);
 }
 
 bool use_fused(const lincoll_plan_s* pl) {
@@ -232,7 +232,7 @@ int ensure_work(lincoll_plan_t pl, int B) {
     pl->cap_pin = B;
   }
   if (use_fused(pl)) {
-    const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus), pl->opt_ppt);
+    const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus), pl->opt_ppt, pl->p.dtype);
     if (need > pl->R_bytes || !pl->d_R) {
       pl->cap_work = 0;
       if ((e = dalloc(pl, &pl->d_R, need))) {
@@ -600,7 +600,7 @@ int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch
   void* scr = nullptr;
   size_t bytes = 0;
   if ((e = fused_noalloc_scratch(dev, &scr, &bytes))) return hip_fail(pl, e);
-  const size_t slot = fused_scratch_bytes(pl->p.n, 1, pl->opt_ppt);
+  const size_t slot = fused_scratch_bytes(pl->p.n, 1, pl->opt_ppt, pl->p.dtype);
   if (slot == 0 || slot > bytes) return LINCOLL_EINVAL;
   ApplyCtx c = apply_ctx(pl, h, out, batch, pl->stream);
   c.R = scr;
@@ -647,10 +647,11 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       break;
     case LINCOLL_OPT_FUSED_PPT:
       if (value != 1 && value != 2) return LINCOLL_EINVAL;
+      if (value == 2 && pl->p.dtype != LINCOLL_F32) return LINCOLL_EINVAL;
       pl->opt_ppt = value;
       break;
     case LINCOLL_OPT_FUSED_KEEP:
-      if (value != -1 && !fused_keep_valid(pl->p.n, value)) return LINCOLL_EINVAL;
+      if (value != -1 && !fused_keep_valid(pl->p.n, pl->p.dtype, value)) return LINCOLL_EINVAL;
       pl->opt_keep = value;
       break;
     case LINCOLL_OPT_TUNE_CACHE:
@@ -730,8 +731,8 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
     if (fused_supported(n, dt))
       for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) {
         for (int keep : {0, 4, 8, 16})
-          if (fused_keep_valid(n, keep)) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 1, keep, 0.0});
-        cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 2, -1, 0.0});
+          if (fused_keep_valid(n, dt, keep)) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 1, keep, 0.0});
+        if (dt == LINCOLL_F32) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 2, -1, 0.0});
       }
   }
   if (cands.empty()) return LINCOLL_EINVAL;

@@ -22,11 +22,13 @@
 // is large where M is small (Sec. 3.3): a float rounding anywhere on that
 // path (of K_j, or of partially transformed values between passes) spreads
 // that size over the box and cost up to 1.8e-5 of max |L| element-wise.
-// After the product with M^h everything runs in float.
+// After the product with M^h everything runs in float.  F64 plans run the
+// same kernel with that second half (and h, L, nu and the radial tables) in
+// double.
 //
-// LDS: one float2 volume for the exchanges, the radial table of the node,
-// the 1-D Maxwellian factors and (n = 32) two chunks of each thread's L+^
-// accumulator.  The kernel modes K_j of a node are needed
+// LDS: one float2 volume for the exchanges (double data in two rounds), the
+// radial table of the node, the 1-D Maxwellian factors and (n = 32) two
+// chunks of each thread's L+^ accumulator.  The kernel modes K_j of a node are needed
 // only in the Y role, where each wave handles its own planes: each wave
 // copies its planes of K_j (and, wave 0, the Nyquist plane kz = N) into its
 // own region of the exchange volume, which no other wave touches between the
@@ -43,7 +45,8 @@ namespace lincoll {
 // spectrum of r and the L+ accumulator) in a file-scope device array instead
 // of plan memory, so that the entry point allocates nothing.  Each device the
 // library runs on holds its own copy until the process ends.  96 MiB holds
-// 256 slots at n = 32 (one per compute unit of an MI355X) or 1024 at n = 16.
+// 256 F32 slots at n = 32 (one per compute unit of an MI355X) or 1024 at
+// n = 16; 192 and 1536 F64 slots.
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(96) << 20;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
@@ -336,33 +339,125 @@ __device__ __forceinline__ void mode_multiply_d(double (&vr)[NN], double (&vi)[N
   one(vi, -1.0);
 }
 
+// The FP64 form of mode_multiply for a radial table (the loss's Omega and the
+// gain's Phi_j in an FP64 apply), without a branch that copies the pencil:
+// every lane multiplies by its own plane's factor m0, and wave 0's packed
+// lanes then overwrite that product with s v + d conj(v(-k)), s and d as
+// above, one component at a time, from the original values parked in the same
+// free part of wave 0's LDS region that mode_multiply_d uses (so no
+// difference of the two products is formed).
+template <int NN, typename G>
+__device__ __forceinline__ void mode_multiply_tab_d(double (&vr)[NN], double (&vi)[NN], int t, double* region,
+                                                    G&& getm) {
+  constexpr int PW = 64 / NN;
+  constexpr int OFF = (kslice_doubles<NN>() + 63) / 64 * 64;
+  static_assert(OFF + NN * NN <= PW * NN * (NN + 1), "partner buffer exceeds the wave's LDS region");
+  const bool packed = t < NN;
+  const int lane = t % NN, partner = (NN - lane) % NN;
+  double* buf = region + OFF;
+  auto one = [&](double(&w)[NN], double sign) {
+    if (packed) static_for<0, NN>([&](auto j) { buf[j * NN + lane] = w[j]; });
+    wave_lds_sync();
+    static_for<0, NN>([&](auto j) { w[j] *= getm(j).x; });
+    if (packed)
+      static_for<0, NN>([&](auto j) {
+        constexpr int jm = (NN - j) % NN;
+        const auto m = getm(j);
+        w[j] = fma(0.5 * (m.x - m.y), sign * buf[jm * NN + partner], 0.5 * (m.x + m.y) * buf[j * NN + lane]);
+      });
+    wave_lds_sync();
+  };
+  one(vr, 1.0);
+  one(vi, -1.0);
+}
+
+// The pieces of the fused kernel that depend on the arithmetic type TL of
+// everything after the product with M^h (float for F32 plans, double for F64):
+// the exchanges through LDS, the radial-table product and the accumulator's
+// chunks (two complex floats or one complex double).
+template <int NN, typename TL>
+__device__ __forceinline__ void exch_z_to_x(TL (&vr)[NN], TL (&vi)[NN], float2* lds, int t) {
+  if constexpr (std::is_same<TL, float>::value) z_to_x<NN, float>(vr, vi, lds, t);
+  else z_to_x_d<NN>(vr, vi, lds, t);
+}
+template <int NN, typename TL>
+__device__ __forceinline__ void exch_x_to_z(TL (&vr)[NN], TL (&vi)[NN], float2* lds, int t) {
+  if constexpr (std::is_same<TL, float>::value) x_to_z<NN, float>(vr, vi, lds, t);
+  else x_to_z_d<NN>(vr, vi, lds, t);
+}
+template <int NN, typename TL>
+__device__ __forceinline__ void exch_transpose(TL (&vr)[NN], TL (&vi)[NN], float2* lds, int t) {
+  if constexpr (std::is_same<TL, float>::value) transpose_plane<NN, float>(vr, vi, lds, t);
+  else transpose_plane_d<NN>(vr, vi, lds, t);
+}
+template <int NN, typename TL, typename G>
+__device__ __forceinline__ void radial_multiply(TL (&vr)[NN], TL (&vi)[NN], int t, float2* lds, G&& getm) {
+  if constexpr (std::is_same<TL, float>::value) {
+    mode_multiply<NN, float>(vr, vi, t, getm);
+  } else {
+    constexpr int PW = 64 / NN, LD = NN + 1;
+    mode_multiply_tab_d<NN>(vr, vi, t, reinterpret_cast<double*>(lds + (t / 64) * PW * NN * LD), getm);
+  }
+}
+
+template <typename TL>
+struct AccChunk;
+template <>
+struct AccChunk<float> {   // two complex values
+  using V = float4;
+  static constexpr int PER = 2;
+  __device__ static float re(const V& a, int p) { return p ? a.z : a.x; }
+  __device__ static float im(const V& a, int p) { return p ? a.w : a.y; }
+  template <int NN>
+  __device__ static V make(const float (&r)[NN], const float (&i)[NN], int c) {
+    return V{r[2 * c], i[2 * c], r[2 * c + 1], i[2 * c + 1]};
+  }
+};
+template <>
+struct AccChunk<double> {   // one complex value
+  using V = double2;
+  static constexpr int PER = 1;
+  __device__ static double re(const V& a, int) { return a.x; }
+  __device__ static double im(const V& a, int) { return a.y; }
+  template <int NN>
+  __device__ static V make(const double (&r)[NN], const double (&i)[NN], int c) {
+    return V{r[c], i[c]};
+  }
+};
+
 }  // namespace
 
-// KA: chunks (of two complex values) of each thread's L+^ accumulator that
-// stay in registers across the nodes; the others stream through the slot.
-template <int NN, int KA>
+// TL: the type of everything after the product with M^h and of h and L at
+// the boundary (float: F32 plans; double: F64 plans).
+// KA: chunks (two complex floats, or one complex double) of each thread's L+^
+// accumulator that stay in registers across the nodes; the next KL live in
+// LDS, the others stream through the slot.
+template <int NN, int KA, typename TL>
 __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
-    const float* __restrict__ h, float* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
+    const TL* __restrict__ h, TL* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
     const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
-    const float* __restrict__ nu, const float* __restrict__ Phi, const float* __restrict__ Om,
+    const TL* __restrict__ nu, const TL* __restrict__ Phi, const TL* __restrict__ Om,
     double2* __restrict__ slots, int J, const int* __restrict__ gate) {
   using C = Cfg<NN>;
+  using A = AccChunk<TL>;
+  using V = typename A::V;
   if (gate && *gate == 0) return;   // a gated-off step of the device-resident GMRES
   constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, PW = 64 / NN, LD = C::LD;
+  constexpr int NCH = NN / A::PER;   // accumulator chunks per thread
   __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
   __shared__ double fs[9 * NN + 3];
-  __shared__ float tab[Q];
+  __shared__ __align__(16) TL tab[Q];
   // Accumulator chunks KA .. KA + KL - 1 live in LDS, each thread's own (the
   // 16 KB left over at n = 32 beside the exchange volume and the tables).
-  constexpr int KL = (NN == 32 && KA < NN / 2) ? (NN / 2 - KA < 2 ? NN / 2 - KA : 2) : 0;
-  __shared__ float4 accl[KL > 0 ? KL : 1][KL > 0 ? C::T : 1];
+  constexpr int KL = (NN == 32 && KA < NCH) ? (NCH - KA < 2 ? NCH - KA : 2) : 0;
+  __shared__ V accl[KL > 0 ? KL : 1][KL > 0 ? C::T : 1];
   const int t0 = threadIdx.x;
   // Scratch slot of this workgroup: R (KP*NP complex double) then the L+
-  // accumulator (KP*NP complex float).  Both are interleaved by thread
+  // accumulator (KP*NP complex TL).  Both are interleaved by thread
   // (element i of thread t at i*T + t) so that each load or store
   // instruction of a wave covers one contiguous segment.
-  double2* Rs = slots + (size_t)blockIdx.x * (KP * NP + KP * NP / 2);
-  float4* Ac = reinterpret_cast<float4*>(Rs + KP * NP);
+  double2* Rs = slots + (size_t)blockIdx.x * (KP * NP + KP * NP * sizeof(TL) / 8);
+  V* Ac = reinterpret_cast<V*>(Rs + KP * NP);
 
   for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
     const int cc = Bc > 1 ? cell : 0;
@@ -379,50 +474,54 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     if (t < 2) fs[6 * NN + t] = pref64[2 * cc + t];
     for (int q = t; q < Q; q += C::T) tab[q] = Om[q];
     __syncthreads();
-    // reciprocal factors of M for r = chi h / M (infinite where a factor
-    // underflows; such points are outside the cutoff and never selected)
-    for (int i = t; i < 3 * NN; i += C::T) fs[6 * NN + 2 + i] = 1.0 / fs[i];
-    if (t == 0) fs[9 * NN + 2] = 1.0 / fs[6 * NN];
-    __syncthreads();
+    if constexpr (std::is_same<TL, float>::value) {
+      // reciprocal factors of M for r = chi h / M (infinite where a factor
+      // underflows; such points are outside the cutoff and never selected)
+      for (int i = t; i < 3 * NN; i += C::T) fs[6 * NN + 2 + i] = 1.0 / fs[i];
+      if (t == 0) fs[9 * NN + 2] = 1.0 / fs[6 * NN];
+      __syncthreads();
+    }
     const double* ex = fs;
     const double* eh = fs + 3 * NN;
     const double prefM = fs[6 * NN], prefH = fs[6 * NN + 1];
     const int col1 = zx * NN + zyp;
-    const float* h1 = h + ((size_t)cell * NP + col1) * NN;
-    const float* h2 = h1 + (size_t)N * NN;
+    const TL* h1 = h + ((size_t)cell * NP + col1) * NN;
+    const TL* h2 = h1 + (size_t)N * NN;
     const double mxy1 = prefM * ex[zx] * ex[NN + zyp], mxy2 = prefM * ex[zx] * ex[NN + zyp + N];
+    auto radial = [&](auto ky) {   // a radial table at (kx, ky) of this pencil's plane and of kz = N
+      constexpr int fy = ky <= N ? ky : NN - ky;
+      const int q = fx * fx + fy * fy;
+      if constexpr (std::is_same<TL, float>::value) return float2{tab[q + kp * kp], tab[q + N * N]};
+      else return double2{tab[q + kp * kp], tab[q + N * N]};
+    };
 
-    // ---------------- loss: U = iDFT[Omega DFT[h]] in float -------------------------
+    // ---------------- loss: U = iDFT[Omega DFT[h]] in TL ---------------------------
     {
-      float fr[NN], fi[NN];
+      TL fr[NN], fi[NN];
       {
-        float zr[NN], zi[NN];
+        TL zr[NN], zi[NN];
         static_for<0, NN>([&](auto z) { zr[z] = h1[z]; zi[z] = h2[z]; });
-        z_forward<NN, float>(zr, zi, fr, fi);
+        z_forward<NN, TL>(zr, zi, fr, fi);
       }
-      z_to_x<NN, float>(fr, fi, lds, t);
+      exch_z_to_x<NN, TL>(fr, fi, lds, t);
       fft<NN, false>(fr, fi);
-      transpose_plane<NN, float>(fr, fi, lds, t);
+      exch_transpose<NN, TL>(fr, fi, lds, t);
       fft<NN, false>(fr, fi);
-      mode_multiply<NN, float>(fr, fi, t, [&](auto ky) {   // Omega(|k|^2) / n^3
-        constexpr int fy = ky <= N ? ky : NN - ky;
-        const int q = fx * fx + fy * fy;
-        return float2{tab[q + kp * kp], tab[q + N * N]};
-      });
+      radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Omega(|k|^2) / n^3
       fft<NN, true>(fr, fi);
-      transpose_plane<NN, float>(fr, fi, lds, t);
+      exch_transpose<NN, TL>(fr, fi, lds, t);
       fft<NN, true>(fr, fi);
-      x_to_z<NN, float>(fr, fi, lds, t);
-      float zr[NN], zi[NN];
-      z_inverse<NN, float>(fr, fi, zr, zi);
-      const float* n1 = nu + ((size_t)cc * NP + col1) * NN;
-      const float* n2 = n1 + (size_t)N * NN;
-      float* o1 = out + ((size_t)cell * NP + col1) * NN;
-      float* o2 = o1 + (size_t)N * NN;
+      exch_x_to_z<NN, TL>(fr, fi, lds, t);
+      TL zr[NN], zi[NN];
+      z_inverse<NN, TL>(fr, fi, zr, zi);
+      const TL* n1 = nu + ((size_t)cc * NP + col1) * NN;
+      const TL* n2 = n1 + (size_t)N * NN;
+      TL* o1 = out + ((size_t)cell * NP + col1) * NN;
+      TL* o2 = o1 + (size_t)N * NN;
       static_for<0, NN>([&](auto z) {
         const double ez = ex[2 * NN + z];
-        o1[z] = float(-(mxy1 * ez) * double(zr[z]) - double(n1[z]) * double(h1[z]));
-        o2[z] = float(-(mxy2 * ez) * double(zi[z]) - double(n2[z]) * double(h2[z]));
+        o1[z] = TL(-(mxy1 * ez) * double(zr[z]) - double(n1[z]) * double(h1[z]));
+        o2[z] = TL(-(mxy2 * ez) * double(zi[z]) - double(n2[z]) * double(h2[z]));
       });
     }
     // ---------------- R = DFT[chi h / M]: double arithmetic, double result --------
@@ -433,16 +532,29 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         const uint32_t* mk2 = mk1 + (size_t)N * MW;
         uint32_t b1[MW], b2[MW];
         static_for<0, MW>([&](auto w) { b1[w] = mk1[w]; b2[w] = mk2[w]; });
-        const double* rx = fs + 6 * NN + 2;
-        const double rxy = fs[9 * NN + 2] * rx[zx];
-        const double r1 = rxy * rx[NN + zyp], r2 = rxy * rx[NN + zyp + N];
+        // r = h / M.  F32 plans multiply by the product of the reciprocal
+        // factors; F64 plans divide by M (the product of its factors), which
+        // rounds fewer times: r is large where M is small, and the few ulps
+        // saved there are visible at FP64 precision (not at FP32).
         double zr[NN], zi[NN];
-        static_for<0, NN>([&](auto z) {
-          const double rz = rx[2 * NN + z];
-          const double q1 = double(h1[z]) * (r1 * rz), q2 = double(h2[z]) * (r2 * rz);
-          zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? q1 : 0.0;
-          zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? q2 : 0.0;
-        });
+        if constexpr (std::is_same<TL, float>::value) {
+          const double* rx = fs + 6 * NN + 2;
+          const double rxy = fs[9 * NN + 2] * rx[zx];
+          const double r1 = rxy * rx[NN + zyp], r2 = rxy * rx[NN + zyp + N];
+          static_for<0, NN>([&](auto z) {
+            const double rz = rx[2 * NN + z];
+            const double q1 = double(h1[z]) * (r1 * rz), q2 = double(h2[z]) * (r2 * rz);
+            zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? q1 : 0.0;
+            zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? q2 : 0.0;
+          });
+        } else {
+          static_for<0, NN>([&](auto z) {
+            const double ez = ex[2 * NN + z];
+            const double q1 = double(h1[z]) / (mxy1 * ez), q2 = double(h2[z]) / (mxy2 * ez);
+            zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? q1 : 0.0;
+            zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? q2 : 0.0;
+          });
+        }
         z_forward<NN, double>(zr, zi, vr, vi);
       }
       z_to_x_d<NN>(vr, vi, lds, t);
@@ -456,14 +568,14 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     // ---------------- gain loop ---------------------------------------------------
     // The running sum of Phi_j Q_j: its first KA chunks stay in registers, the
     // next KL in LDS, the others in the scratch slot between nodes (loaded back
-    // only during the float part of a node, where registers are free); after
+    // only during the TL part of a node, where registers are free); after
     // the last node all of it is in registers.
-    float Lr[NN], Li[NN];
-    float4 keep[KA > 0 ? KA : 1];
-    static_for<0, KA>([&](auto c) { keep[c] = float4{0.f, 0.f, 0.f, 0.f}; });
+    TL Lr[NN], Li[NN];
+    V keep[KA > 0 ? KA : 1];
+    static_for<0, KA>([&](auto c) { keep[c] = V{}; });
     for (int j = 0; j < J; ++j) {
       asm volatile("" : "+v"(t));
-      float fr[NN], fi[NN];
+      TL fr[NN], fi[NN];
       {
         double vr[NN], vi[NN];
         static_for<0, NN>([&](auto ky) {
@@ -485,29 +597,33 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
         // the z stage runs.  It is complete and visible after the wait and
         // first barrier of the next X <- Z exchange.
-        lds_dma(Phi + (size_t)j * phi_stride(NN), tab, Q, t, C::T);
-        // psi on the two columns, times M^h; float from here on
+        lds_dma(reinterpret_cast<const float*>(Phi + (size_t)j * phi_stride(NN)), reinterpret_cast<float*>(tab),
+                Q * int(sizeof(TL) / 4), t, C::T);
+        // psi on the two columns, times M^h; TL from here on
         double zr[NN], zi[NN];
         z_inverse<NN, double>(vr, vi, zr, zi);
         const double hx = prefH * eh[zx];
         const double g1 = hx * eh[NN + zyp], g2 = hx * eh[NN + zyp + N];
-        float qr[NN], qi[NN];
+        TL qr[NN], qi[NN];
         static_for<0, NN>([&](auto z) {
           const double ez = eh[2 * NN + z];
-          qr[z] = float(zr[z] * (g1 * ez));
-          qi[z] = float(zi[z] * (g2 * ez));
+          qr[z] = TL(zr[z] * (g1 * ez));
+          qi[z] = TL(zi[z] * (g2 * ez));
         });
-        z_forward<NN, float>(qr, qi, fr, fi);
+        z_forward<NN, TL>(qr, qi, fr, fi);
       }
       __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
-      z_to_x<NN, float>(fr, fi, lds, t);
-      float4 acc[NN / 2];
-      static_for<KA, NN / 2>([&](auto c) {
-        if constexpr (c < KA + KL) acc[c] = j > 0 ? accl[c - KA][t] : float4{0.f, 0.f, 0.f, 0.f};
-        else acc[c] = j > 0 ? Ac[c * C::T + t] : float4{0.f, 0.f, 0.f, 0.f};
-      });
+      exch_z_to_x<NN, TL>(fr, fi, lds, t);
+      // Float chunks are loaded here, well ahead of their use (they fit beside
+      // the pencil); double chunks are loaded one at a time where they are added.
+      V acc[NCH];
+      if constexpr (std::is_same<TL, float>::value)
+        static_for<KA, NCH>([&](auto c) {
+          if constexpr (c < KA + KL) acc[c] = j > 0 ? accl[c - KA][t] : V{};
+          else acc[c] = j > 0 ? Ac[c * C::T + t] : V{};
+        });
       fft<NN, false>(fr, fi);
-      transpose_plane<NN, float>(fr, fi, lds, t);
+      exch_transpose<NN, TL>(fr, fi, lds, t);
       // This wave is done with its region until the next node's K_j product;
       // its transpose reads complete (lgkmcnt(0)) before the copy may land.
       if (j + 1 < J) {
@@ -515,37 +631,36 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         k_slice_dma<NN>(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), lds, t);
       }
       fft<NN, false>(fr, fi);
-      mode_multiply<NN, float>(fr, fi, t, [&](auto ky) {       // Phi_j / n^3
-        constexpr int fy = ky <= N ? ky : NN - ky;
-        const int q = fx * fx + fy * fy;
-        return float2{tab[q + kp * kp], tab[q + N * N]};
-      });
-      static_for<0, NN / 2>([&](auto c) {
-        float4 a;
-        if constexpr (c < KA) a = keep[c]; else a = acc[c];
-        Lr[2 * c] = a.x + fr[2 * c];
-        Li[2 * c] = a.y + fi[2 * c];
-        Lr[2 * c + 1] = a.z + fr[2 * c + 1];
-        Li[2 * c + 1] = a.w + fi[2 * c + 1];
-      });
-      if (j + 1 < J)
-        static_for<0, NN / 2>([&](auto c) {
-          const float4 v{Lr[2 * c], Li[2 * c], Lr[2 * c + 1], Li[2 * c + 1]};
+      radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Phi_j / n^3
+      static_for<0, NCH>([&](auto c) {
+        V a;
+        if constexpr (c < KA) a = keep[c];
+        else if constexpr (std::is_same<TL, float>::value) a = acc[c];
+        else if constexpr (c < KA + KL) a = j > 0 ? accl[c - KA][t] : V{};
+        else a = j > 0 ? Ac[c * C::T + t] : V{};
+        static_for<0, A::PER>([&](auto q) {
+          constexpr int e = A::PER * c + q;
+          Lr[e] = A::re(a, q) + fr[e];
+          Li[e] = A::im(a, q) + fi[e];
+        });
+        if (j + 1 < J) {
+          const V v = A::template make<NN>(Lr, Li, c);
           if constexpr (c < KA) keep[c] = v;
           else if constexpr (c < KA + KL) accl[c - KA][t] = v;
           else Ac[c * C::T + t] = v;
-        });
+        }
+      });
     }
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
     fft<NN, true>(Lr, Li);
-    transpose_plane<NN, float>(Lr, Li, lds, t);
+    exch_transpose<NN, TL>(Lr, Li, lds, t);
     fft<NN, true>(Lr, Li);
-    x_to_z<NN, float>(Lr, Li, lds, t);
+    exch_x_to_z<NN, TL>(Lr, Li, lds, t);
     {
-      float zr[NN], zi[NN];
-      z_inverse<NN, float>(Lr, Li, zr, zi);
-      float* o1 = out + ((size_t)cell * NP + col1) * NN;
-      float* o2 = o1 + (size_t)N * NN;
+      TL zr[NN], zi[NN];
+      z_inverse<NN, TL>(Lr, Li, zr, zi);
+      TL* o1 = out + ((size_t)cell * NP + col1) * NN;
+      TL* o2 = o1 + (size_t)N * NN;
       static_for<0, NN>([&](auto z) {
         o1[z] = o1[z] + zr[z];
         o2[z] = o2[z] + zi[z];
@@ -895,12 +1010,15 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
   }
 }
 
-bool fused_supported(int n, int dtype) { return dtype == 1 && (n == 16 || n == 32); }
+// F32 and F64 plans at n = 16 and 32 (dtype: 0 = F64, 1 = F32).
+bool fused_supported(int n, int dtype) { return (dtype == 0 || dtype == 1) && (n == 16 || n == 32); }
 
-size_t fused_scratch_bytes(int n, int nslots, int ppt) {
+size_t fused_scratch_bytes(int n, int nslots, int ppt, int dtype) {
   // per slot: R (complex double) and, with one pencil per thread, the L+
-  // accumulator (complex float); with two it stays in registers
-  return (size_t)nslots * (n / 2) * n * n * (sizeof(double2) + (ppt == 2 ? 0 : sizeof(float2)));
+  // accumulator (complex float, or complex double for F64); with two pencils
+  // (F32 only) it stays in registers
+  const size_t acc = ppt == 2 ? 0 : dtype == 0 ? sizeof(double2) : sizeof(float2);
+  return (size_t)nslots * (n / 2) * n * n * (sizeof(double2) + acc);
 }
 
 // Workgroups resident per compute unit: n = 32 needs all of a CU's LDS, the
@@ -937,42 +1055,68 @@ hipError_t fused_noalloc_scratch(int device, void** ptr, size_t* bytes) {
   return hipSuccess;
 }
 
-bool fused_keep_valid(int n, int keep) {
-  return keep == 0 || keep == 4 || keep == 8 || (n == 32 && keep == 16);
+// Accumulator splits compiled for each plan type (chunks of two complex
+// floats for F32, of one complex double for F64).
+bool fused_keep_valid(int n, int dtype, int keep) {
+  if (dtype == 1) return keep == 0 || keep == 4 || keep == 8 || (n == 32 && keep == 16);
+  if (dtype == 0) return keep == 0 || (n == 32 && keep == 4) || keep == 8 || (n == 16 && keep == 16);
+  return false;
 }
+
+int fused_default_keep(int n, int dtype) {
+  if (dtype == 0) return n == 16 ? 16 : 0;
+  return 8;
+}
+
+namespace {
+
+template <int NN, int KA, typename TL>
+void launch_fused(const ApplyCtx& c, int slots) {
+  k_fused<NN, KA, TL><<<slots, Cfg<NN>::T, 0, c.stream>>>(
+      static_cast<const TL*>(c.h), static_cast<TL*>(c.out), c.batch, c.Bc, c.fac64, c.pref64, c.mask,
+      static_cast<const double*>(c.Kh), static_cast<const TL*>(c.nu), static_cast<const TL*>(c.Phi),
+      static_cast<const TL*>(c.Om), static_cast<double2*>(c.R), c.J, c.gate);
+}
+
+template <int NN>
+void launch_fused2(const ApplyCtx& c, int slots) {
+  k_fused2<NN><<<slots, Cfg<NN>::T / 2, 0, c.stream>>>(
+      static_cast<const float*>(c.h), static_cast<float*>(c.out), c.batch, c.Bc, c.fac64, c.pref64, c.mask,
+      static_cast<const double*>(c.Kh), static_cast<const float*>(c.nu), static_cast<const float*>(c.Phi),
+      static_cast<const float*>(c.Om), static_cast<double2*>(c.R), c.J, c.gate);
+}
+
+}  // namespace
 
 hipError_t fused_apply(const ApplyCtx& c) {
   int slots = fused_slots(c.n, c.batch, c.per_cu, c.cus);
   if (c.max_slots > 0 && slots > c.max_slots) slots = c.max_slots;   // the kernel is persistent over cells
-  const float* h = static_cast<const float*>(c.h);
-  float* out = static_cast<float*>(c.out);
-  const double* Kh = static_cast<const double*>(c.Kh);
-  const float* nu = static_cast<const float*>(c.nu);
-  const float* Phi = static_cast<const float*>(c.Phi);
-  const float* Om = static_cast<const float*>(c.Om);
-  double2* scr = static_cast<double2*>(c.R);
-  if (!fused_keep_valid(c.n, c.fused_keep)) return hipErrorInvalidValue;
-  auto one = [&](auto kernel, int threads) {
-    kernel<<<slots, threads, 0, c.stream>>>(h, out, c.batch, c.Bc, c.fac64, c.pref64, c.mask, Kh, nu, Phi, Om, scr,
-                                            c.J, c.gate);
-  };
-  const bool two = c.fused_ppt == 2;
-  switch (c.n) {
-    case 16:
-      if (two) one(k_fused2<16>, Cfg<16>::T / 2);
-      else if (c.fused_keep == 0) one(k_fused<16, 0>, Cfg<16>::T);
-      else if (c.fused_keep == 4) one(k_fused<16, 4>, Cfg<16>::T);
-      else one(k_fused<16, 8>, Cfg<16>::T);
-      break;
-    case 32:
-      if (two) one(k_fused2<32>, Cfg<32>::T / 2);
-      else if (c.fused_keep == 0) one(k_fused<32, 0>, Cfg<32>::T);
-      else if (c.fused_keep == 4) one(k_fused<32, 4>, Cfg<32>::T);
-      else if (c.fused_keep == 8) one(k_fused<32, 8>, Cfg<32>::T);
-      else one(k_fused<32, 16>, Cfg<32>::T);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  if (!fused_supported(c.n, c.dtype) || !fused_keep_valid(c.n, c.dtype, c.fused_keep)) return hipErrorInvalidValue;
+  if (c.fused_ppt == 2 && c.dtype != 1) return hipErrorInvalidValue;
+  const int k = c.fused_keep;
+  if (c.dtype == 1) {
+    if (c.n == 16) {
+      if (c.fused_ppt == 2) launch_fused2<16>(c, slots);
+      else if (k == 0) launch_fused<16, 0, float>(c, slots);
+      else if (k == 4) launch_fused<16, 4, float>(c, slots);
+      else launch_fused<16, 8, float>(c, slots);
+    } else {
+      if (c.fused_ppt == 2) launch_fused2<32>(c, slots);
+      else if (k == 0) launch_fused<32, 0, float>(c, slots);
+      else if (k == 4) launch_fused<32, 4, float>(c, slots);
+      else if (k == 8) launch_fused<32, 8, float>(c, slots);
+      else launch_fused<32, 16, float>(c, slots);
+    }
+  } else {
+    if (c.n == 16) {
+      if (k == 0) launch_fused<16, 0, double>(c, slots);
+      else if (k == 8) launch_fused<16, 8, double>(c, slots);
+      else launch_fused<16, 16, double>(c, slots);
+    } else {
+      if (k == 0) launch_fused<32, 0, double>(c, slots);
+      else if (k == 4) launch_fused<32, 4, double>(c, slots);
+      else launch_fused<32, 8, double>(c, slots);
+    }
   }
   return hipGetLastError();
 }

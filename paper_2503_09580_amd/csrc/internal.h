@@ -47,7 +47,7 @@ struct ApplyCtx {
   int per_cu = 0;              // fused path: workgroups per compute unit (0 = default)
   int max_slots = 0;           // fused path: cap on the persistent workgroups (0 = none)
   int fused_ppt = 1;           // fused path: pencils per thread (1: k_fused, 2: k_fused2)
-  int fused_keep = 0;          // k_fused: accumulator chunks kept in registers (0, 4, 8; 16 at n = 32)
+  int fused_keep = 0;          // k_fused: accumulator chunks kept in registers (fused_keep_valid)
   int zblk = 128;              // staged path: threads per block of the z-pass kernels (64, 128, 256)
   int plane_tile = 0;          // staged path: 0 = 64-thread in-plane blocks, 1 = 32-thread (n <= 32)
   const int* gate = nullptr;   // fused path: the kernel does nothing unless *gate != 0 (device flag)
@@ -152,8 +152,9 @@ hipError_t plane_fwd_bf16x3(int n, const float2* in, float2* out, const float* t
 hipError_t rk_stage(int dtype, const void* f, const void* k, void* acc, void* tmp, long count, double a, double b,
                     int first, hipStream_t s);
 hipError_t rk_final(int dtype, void* f, const void* acc, const void* k, long count, double a, hipStream_t s);
-size_t fused_scratch_bytes(int n, int nslots, int ppt);
-bool fused_keep_valid(int n, int keep);
+size_t fused_scratch_bytes(int n, int nslots, int ppt, int dtype);
+bool fused_keep_valid(int n, int dtype, int keep);
+int fused_default_keep(int n, int dtype);
 // The fixed device scratch of lincoll_apply_noalloc on `device` (which must
 // be current): its address and size.
 hipError_t fused_noalloc_scratch(int device, void** ptr, size_t* bytes);

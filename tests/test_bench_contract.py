@@ -63,6 +63,6 @@ def test_bench_line(monkeypatch, capsys, args, steps, warmup):
     check_line(rec, steps, warmup)
     if "--op" not in args:
         # the headline apply line: the fused kernel's roofline, FP32 error against FP64 within the bar
-        assert rec["roofline"]["kernel"] == "k_fused<32>"
+        assert rec["roofline"]["kernel"].startswith("k_fused<32, ")
         assert rec["rel_err_vs_fp64"]["max"] <= 1e-5
         assert rec["vs_baseline"] is None

@@ -70,6 +70,22 @@ def test_fp64_staged_matches_oracle(n, L, omega, batch):
     check_cells(got, ref, 1e-12, tag="f64 staged")
 
 
+@pytest.mark.parametrize("n,L,omega,batch", [(16, 8.0, 0.74, 7), (32, 8.0, 0.74, 5), (16, 8.0, 1.0, 300)])
+def test_fp64_fused_matches_oracle_and_staged(n, L, omega, batch):
+    """The fused kernel on an F64 plan (double after the product with M^h as
+    well) against the oracle, and against the staged FP64 path on every cell;
+    the 300-cell case runs several cells per persistent workgroup."""
+    h, params = mixed_inputs(n, L, batch, seed=1100 + n + batch)
+    plan = lc.Plan(n, L, omega, "f64", path="fused")
+    assert plan.info("path") == 2
+    got = run(plan, h, params, "f64")
+    sample = [0, batch // 2, batch - 1] if batch > 10 else list(range(batch))
+    ref = oracle_cells(n, L, omega, h[sample], params[sample])
+    check_cells(got, ref, 1e-12, cells=sample, tag="f64 fused vs oracle")
+    staged = run(lc.Plan(n, L, omega, "f64", path="staged"), h, params, "f64")
+    check_batch(got, staged, 1e-12, tag="f64 fused vs staged")
+
+
 def test_fp64_matches_direct_sum_oracle():
     """Against O1 (dense DFT + naive convolution) as well, n = 16."""
     n, L, om = 16, 8.0, 0.74
@@ -294,7 +310,7 @@ def test_c3_fp32_fused_every_cell():
     sample = list(range(0, B, B // 64))[:64]
     ref = oracle_cells(n, L, om, hin[sample], params[sample])
     l2o, mxo = check_cells(got, ref, 1e-5, cells=sample, tag="oracle")
-    ref64 = lc.Plan(n, L, om, "f64")
+    ref64 = lc.Plan(n, L, om, "f64", path="staged")
     full = run(ref64, hin, params, "f64")
     ref64.close()
     # the GPU FP64 result is itself the oracle's on the sampled cells
@@ -322,7 +338,8 @@ def test_fp32_without_cutoff(n, path):
 
 
 @pytest.mark.parametrize("n,J,dtype,path", [(8, 2, "f32", "staged"), (16, 3, "f32", "fused"), (32, 4, "f32", "fused"),
-                                            (32, 4, "f32", "staged"), (16, 3, "f64", "staged")])
+                                            (32, 4, "f32", "staged"), (16, 3, "f64", "staged"), (16, 3, "f64", "fused"),
+                                            (32, 4, "f64", "fused")])
 def test_small_quadrature_counts(n, J, dtype, path):
     """Few g-nodes (J P^3 < n^3 with P = n/2 + 1): the per-cell setup scratch
     must still hold the FP64 loss frequency of n^3 values per cell.  Per-cell

@@ -24,17 +24,21 @@ def dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
-@pytest.mark.parametrize("n,big,small", [(32, 300, 37), (16, 1500, 5)])
-def test_noalloc_matches_apply_twice(n, big, small):
+@pytest.mark.parametrize("n,big,small,dtype", [(32, 300, 37, "f32"), (16, 1500, 5, "f32"), (32, 250, 37, "f64"),
+                                               (16, 1700, 5, "f64")])
+def test_noalloc_matches_apply_twice(n, big, small, dtype):
+    """The F64 cases exceed the array's 192 (n = 32) and 1536 (n = 16) F64
+    slots, so the persistent workgroups loop over several cells each."""
     L, om = 8.0, 0.74
     lib = lc.library()
     h, params = mixed_inputs(n, L, big, seed=2900 + n)
-    plan = lc.Plan(n, L, om, "f32")
+    plan = lc.Plan(n, L, om, dtype)
     assert plan.info("path") == 2
+    td = torch.float32 if dtype == "f32" else torch.float64
     for B in (big, small):
-        print(f"noalloc n={n} batch={B}", flush=True)
+        print(f"noalloc n={n} dtype={dtype} batch={B}", flush=True)
         plan.set_maxwellians(dev(params[:B], torch.float64))
-        x = dev(h[:B], torch.float32)
+        x = dev(h[:B], td)
         ref = plan.apply(x)
         out = torch.full_like(x, float("nan"))
         torch.cuda.synchronize()
@@ -61,10 +65,12 @@ def test_noalloc_rejects_unsupported_plans():
     for kw in (dict(path="staged"), dict(project=1)):
         plan = lc.Plan(n, L, om, "f32", **kw)
         assert lib.lincoll_apply_noalloc(plan._h, px, py, 2) == lc.EINVAL
-    p64 = lc.Plan(n, L, om, "f64")
-    x64 = torch.zeros((2, n, n, n), dtype=torch.float64, device=DEV)
-    y64 = torch.zeros_like(x64)
-    assert lib.lincoll_apply_noalloc(p64._h, ctypes.c_void_p(x64.data_ptr()), ctypes.c_void_p(y64.data_ptr()), 2) \
+    p64 = lc.Plan(n, L, om, "f64", path="staged")                     # not on the fused path
+    assert lib.lincoll_apply_noalloc(p64._h, px, py, 2) == lc.EINVAL
+    pbf = lc.Plan(32, L, om, "bf16x3")                                 # staged only
+    x32 = torch.zeros((2, 32, 32, 32), dtype=torch.float32, device=DEV)
+    y32 = torch.zeros_like(x32)
+    assert lib.lincoll_apply_noalloc(pbf._h, ctypes.c_void_p(x32.data_ptr()), ctypes.c_void_p(y32.data_ptr()), 2) \
         == lc.EINVAL
     plan = lc.Plan(n, L, om, "f32")
     assert lib.lincoll_apply_noalloc(plan._h, px, px, 2) == lc.EINVAL       # aliased
