@@ -53,7 +53,9 @@ typedef enum {
 } lincoll_dtype_t;
 
 typedef enum {
-  LINCOLL_PATH_AUTO = 0,    /* fused kernel where it exists, otherwise the staged kernels */
+  LINCOLL_PATH_AUTO = 0,    /* fused kernel where it exists and the batch is large enough for one cell per
+                               compute unit to beat the staged kernels (n = 16: any batch; n = 32: 16 cells
+                               or more for F32, 128 or more for F64); otherwise the staged kernels */
   LINCOLL_PATH_STAGED = 1,  /* batched per-stage kernels (every n and dtype) */
   LINCOLL_PATH_FUSED = 2    /* one persistent workgroup per cell (F32 and F64 at n = 16, 32) */
 } lincoll_path_t;
@@ -115,8 +117,9 @@ int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
  * to start at zero.  All calls on one GPU share it: calls that overlap in
  * time on one GPU (other streams, other plans, other threads) race and give
  * wrong results; serialise them.  Requirements beyond lincoll_apply's: the
- * plan's apply takes the fused path (LINCOLL_F32 or LINCOLL_F64, n = 16 or
- * 32, path AUTO or FUSED), project = 0, the Maxwellians already set (lincoll_set_maxwellians
+ * plan's apply of this batch takes the fused path (LINCOLL_F32 or
+ * LINCOLL_F64, n = 16 or 32, path FUSED, or AUTO with a batch at or above
+ * AUTO's threshold), project = 0, the Maxwellians already set (lincoll_set_maxwellians
  * allocates), and the plan's device current; otherwise LINCOLL_EINVAL. */
 int lincoll_apply_noalloc(lincoll_plan_t plan, const void* h, void* out, int batch);
 
@@ -145,7 +148,8 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_J 1
 #define LINCOLL_INFO_R 2
 #define LINCOLL_INFO_DTYPE 3
-#define LINCOLL_INFO_PATH 4          /* path the next apply uses (lincoll_path_t) */
+#define LINCOLL_INFO_PATH 4          /* path an apply of the Maxwellian batch takes (of a large batch when the
+                                        Maxwellians are broadcast or not yet set), as lincoll_path_t */
 #define LINCOLL_INFO_MAXW_BATCH 5    /* batch of the Maxwellians currently set */
 #define LINCOLL_INFO_DEVICE_BYTES 6  /* device memory held by the plan */
 #define LINCOLL_INFO_HIP_ERROR 7     /* last hipError_t seen (0 if none) */
@@ -161,6 +165,8 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_TUNE_CACHED 17  /* 1 if the last lincoll_autotune took its result from the cache */
 #define LINCOLL_INFO_FUSED_PPT 18    /* fused path: pencils per thread (LINCOLL_OPT_FUSED_PPT) */
 #define LINCOLL_INFO_FUSED_KEEP 19   /* fused path: accumulator chunks kept in registers, in effect */
+#define LINCOLL_INFO_LAST_PATH 20    /* path the most recent apply (of any batch) took; 0 before the first.  Set
+                                        when the launches are enqueued (or recorded into a graph) */
 /* Reads one plan property into *val.  With plan == NULL only
  * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
  * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */

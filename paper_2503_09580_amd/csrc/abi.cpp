@@ -62,6 +62,7 @@ struct lincoll_plan_s {
   int opt_keep = -1;   // fused accumulator chunks kept in registers (-1: the default for n)
   double tuned_ms = 0.0;
   int tuned_cached = 0;
+  int last_path = 0;          // path of the most recent apply (LINCOLL_INFO_LAST_PATH)
   std::string arch;           // gcnArchName of the plan's device (key of the tuner's cache)
   // replayable graph of the last apply (opt_graph)
   unsigned long alloc_gen = 0;
@@ -177,11 +178,25 @@ int fused_keep(const lincoll_plan_s* pl) {
   return fused_default_keep(pl->p.n, pl->p.dtype);
 }
 
-bool use_fused(const lincoll_plan_s* pl) {
+// Path of an apply of `batch` cells.  AUTO takes the fused kernel where it
+// exists and the batch fills enough of the chip for one cell per compute
+// unit to beat the staged kernels, which spread even one cell over many CUs
+// (measured on MI355X: at n = 16 from one cell; at n = 32 from 16 cells in
+// F32 and from 128 in F64).
+int fused_auto_min_batch(int n, int dtype) {
+  if (n == 16) return 1;
+  return dtype == LINCOLL_F64 ? 128 : 16;
+}
+
+bool use_fused(const lincoll_plan_s* pl, int batch) {
   if (pl->p.path == LINCOLL_PATH_STAGED) return false;
   if (pl->p.path == LINCOLL_PATH_FUSED) return true;
-  return fused_supported(pl->p.n, pl->p.dtype);
+  return fused_supported(pl->p.n, pl->p.dtype) && batch >= fused_auto_min_batch(pl->p.n, pl->p.dtype);
 }
+
+// The batch a path query refers to: the Maxwellian batch when it is per
+// cell, otherwise a large batch.
+int info_batch(const lincoll_plan_s* pl) { return pl->Bc > 1 ? pl->Bc : 1 << 30; }
 
 int ensure_cells(lincoll_plan_t pl, int B) {
   if (B <= pl->cap_cells) return LINCOLL_OK;
@@ -231,7 +246,7 @@ int ensure_work(lincoll_plan_t pl, int B) {
     }
     pl->cap_pin = B;
   }
-  if (use_fused(pl)) {
+  if (use_fused(pl, B)) {
     const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus), pl->opt_ppt, pl->p.dtype);
     if (need > pl->R_bytes || !pl->d_R) {
       pl->cap_work = 0;
@@ -524,7 +539,9 @@ hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, 
   }
   ApplyCtx c = apply_ctx(pl, hin, out, batch, stream);
   c.gate = gate;
-  if ((e = use_fused(pl) ? fused_apply(c) : staged_apply(c))) return e;
+  const bool fused = use_fused(pl, batch);
+  pl->last_path = fused ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED;
+  if ((e = fused ? fused_apply(c) : staged_apply(c))) return e;
   if (pl->p.project) return launch_project(pl, out, out, batch, stream, gate);
   return hipSuccess;
 }
@@ -579,7 +596,7 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
     if ((e = launch_apply(pl, h, out, batch, pl->stream))) return hip_fail(pl, e);
     return LINCOLL_OK;
   }
-  const lincoll_plan_s::GraphKey key{h, out, batch, pl->Bc, use_fused(pl) ? 1 : 0, pl->opt_per_cu, pl->p.project,
+  const lincoll_plan_s::GraphKey key{h, out, batch, pl->Bc, use_fused(pl, batch) ? 1 : 0, pl->opt_per_cu, pl->p.project,
                                      pl->alloc_gen};
   const lincoll_plan_s::GraphKey& k = pl->gkey;
   const bool same = pl->gexec && k.h == key.h && k.out == key.out && k.batch == key.batch && k.Bc == key.Bc &&
@@ -592,7 +609,7 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
 int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch) {
   int st = checked_apply_args(pl, h, out, batch);
   if (st) return st;
-  if (!use_fused(pl) || pl->p.project) return LINCOLL_EINVAL;
+  if (!use_fused(pl, batch) || pl->p.project) return LINCOLL_EINVAL;
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e) return hip_fail(pl, e);
@@ -926,7 +943,7 @@ int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
     return LINCOLL_OK;
   }
   // record one step once, replay it `steps` times
-  const lincoll_plan_s::GraphKey key{f, nullptr, batch, pl->Bc, use_fused(pl) ? 1 : 0, pl->opt_per_cu,
+  const lincoll_plan_s::GraphKey key{f, nullptr, batch, pl->Bc, use_fused(pl, batch) ? 1 : 0, pl->opt_per_cu,
                                      pl->p.project, pl->alloc_gen};
   const lincoll_plan_s::GraphKey& k = pl->rk_key;
   const bool same = pl->rk_gexec && k.h == key.h && k.batch == key.batch && k.Bc == key.Bc && k.fused == key.fused &&
@@ -1015,7 +1032,7 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_J: *val = pl->t.J; break;
     case LINCOLL_INFO_R: *val = pl->p.R; break;
     case LINCOLL_INFO_DTYPE: *val = pl->p.dtype; break;
-    case LINCOLL_INFO_PATH: *val = use_fused(pl) ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED; break;
+    case LINCOLL_INFO_PATH: *val = use_fused(pl, info_batch(pl)) ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED; break;
     case LINCOLL_INFO_MAXW_BATCH: *val = pl->Bc; break;
     case LINCOLL_INFO_DEVICE_BYTES: *val = (double)pl->bytes; break;
     case LINCOLL_INFO_HIP_ERROR: *val = pl->last_hip; break;
@@ -1033,6 +1050,7 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_TUNE_CACHED: *val = pl->tuned_cached; break;
     case LINCOLL_INFO_FUSED_PPT: *val = pl->opt_ppt; break;
     case LINCOLL_INFO_FUSED_KEEP: *val = fused_keep(pl); break;
+    case LINCOLL_INFO_LAST_PATH: *val = pl->last_path; break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;

@@ -20,7 +20,7 @@ TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
 INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
         "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11, "L": 12, "project": 13,
         "quad_fix": 14, "zblock": 15, "plane_tile": 16, "tune_cached": 17, "fused_ppt": 18,
-        "fused_keep": 19}
+        "fused_keep": 19, "last_path": 20}
 PRECONDS = {"none": 0, "sweep": 1, "learned": 2}
 INNERS = {"gmres": 0, "source": 1}
 MLP_IN, MLP_HIDDEN, MLP_OUT = 26, 128, 5
