@@ -52,9 +52,10 @@ KERNEL_SOURCES = {
     "fused": ["paper_2503_09580_amd/csrc/fused.hip", "paper_2503_09580_amd/csrc/fft.h",
               "paper_2503_09580_amd/csrc/twiddles.h", "paper_2503_09580_amd/csrc/internal.h"],
 }
-def fused_kernel_name(n, ppt, keep):
+def fused_kernel_name(n, ppt, keep, dtype):
     """Name of the fused kernel instance a plan launches (as in the profiles)."""
-    return f"k_fused2<{n}>" if ppt == 2 else f"k_fused<{n}, {keep}>"
+    tl = "double" if dtype == "f64" else "float"
+    return f"k_fused2<{n}>" if ppt == 2 else f"k_fused<{n}, {keep}, {tl}>"
 
 
 def kernel_source_hash(path):
@@ -631,7 +632,7 @@ def main():
     fl = alg_flops_per_cell(n, J) * B
     by = alg_bytes_per_cell(n, elem) * B
     achieved = fl / (ms_per_step / 1e3) / 1e12
-    kname = (fused_kernel_name(n, int(plan.info("fused_ppt")), int(plan.info("fused_keep"))) if path == "fused"
+    kname = (fused_kernel_name(n, int(plan.info("fused_ppt")), int(plan.info("fused_keep")), a.dtype) if path == "fused"
              else "lincoll_apply (all launches of one step)")
     tr = traffic_record(kname, a.config, a.dtype, path) if path == "fused" else None
     rec["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
