@@ -52,6 +52,34 @@ def test_plan_tables(n, L, omega):
         assert np.max(np.abs(K.imag)) < 1e-14 * np.max(np.abs(K.real))
 
 
+@pytest.mark.parametrize("n,L,omega", [(8, 4.0, 1.0), (8, 5.0, 0.74)])
+def test_phi_is_the_symmetric_sum_of_eq24(n, L, omega):
+    """Pins reading R4 against the passage it reads.  The bracket of eq. (24)
+    sums sinc(pi g_j |m| / (2L)) e^{i pi k.m / N} over m = -N..N in every
+    axis (2N + 1 terms, both ends).  Evaluated here by brute force on that
+    symmetric range, with math.sin rather than the oracle's sinc helper; it
+    must equal n^3 phi_j(k) at every grid point k = -N..N-1.  A plan without
+    the Nyquist doubling (or with the wrong end doubled, or with the sum
+    stopping at N - 1) fails this."""
+    p = fd.make_plan(n, L, omega)
+    N = n // 2
+    m = np.arange(-N, N + 1)
+    M1, M2, M3 = np.meshgrid(m, m, m, indexing="ij")
+    mabs = np.sqrt(M1 ** 2 + M2 ** 2 + M3 ** 2)
+    k = np.arange(-N, N)
+    # e^{i pi k m / N} per axis: [k, m]
+    E = np.exp(1j * math.pi * np.outer(k, m) / N)
+    for j in (0, p.J // 2, p.J - 1):
+        x = math.pi * p.g[j] * mabs / (2.0 * L)
+        sj = np.where(x == 0.0, 1.0, np.sin(np.where(x == 0.0, 1.0, x)) / np.where(x == 0.0, 1.0, x))
+        bracket = np.einsum("am,bn,cp,mnp->abc", E, E, E, sj)
+        assert np.max(np.abs(bracket.imag)) < 1e-10 * np.max(np.abs(bracket.real))
+        np.testing.assert_allclose(bracket.real, n ** 3 * p.phi[j], rtol=0, atol=1e-10 * np.max(np.abs(bracket)))
+        # and the bracket summed over -N..N-1 only (no doubling) differs
+        short = np.einsum("am,bn,cp,mnp->abc", E[:, :-1], E[:, :-1], E[:, :-1], sj[:-1, :-1, :-1])
+        assert np.max(np.abs(short.real - n ** 3 * p.phi[j])) > 1e-6 * np.max(np.abs(bracket))
+
+
 def test_dense_dft_matches_library_fft():
     rng = np.random.default_rng(5)
     x = rng.standard_normal((8, 8, 8)) + 1j * rng.standard_normal((8, 8, 8))
