@@ -42,6 +42,7 @@ extern "C" {
 #define LINCOLL_ENOTREADY -4 /* batch does not match the Maxwellians set (neither 1 nor batch) */
 #define LINCOLL_ENOTIMPL -5  /* operation not provided by this build */
 #define LINCOLL_EDIVERGED -6 /* an iterate left the admissible set (density or temperature <= 0, non-finite values) */
+#define LINCOLL_ENONFINITE -7 /* debug check (LINCOLL_OPT_CHECK_FINITE): the output holds NaN or infinite values */
 
 typedef struct lincoll_plan_s* lincoll_plan_t;
 
@@ -200,6 +201,11 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
 #define LINCOLL_OPT_PLANE_TILE 8      /* staged path: in-plane kernels with 64 (0, default) or 32 (1, n <= 32)
                                          threads per block, i.e. 64/n or 32/n planes per block */
 #define LINCOLL_OPT_TUNE_CACHE 9      /* 1 (default): lincoll_autotune reuses a cached result; 0: always times */
+#define LINCOLL_OPT_CHECK_FINITE 12   /* debug: 1 = after each lincoll_apply, scan the output for NaN or infinite
+                                         values on the plan's stream and read the result back (the call then
+                                         synchronises the stream); returns LINCOLL_ENONFINITE if any, the output
+                                         as computed.  Not for callers that capture lincoll_apply into a graph
+                                         (the read-back cannot be captured).  0 (default): no check */
 #define LINCOLL_OPT_FUSED_PPT 10      /* fused path: pencils per thread, 1 (default: two waves per SIMD, the L+^
                                          accumulator partly streamed through the workgroup's scratch slot every
                                          node, see LINCOLL_OPT_FUSED_KEEP) or 2 (one wave per SIMD with the whole

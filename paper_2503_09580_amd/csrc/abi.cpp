@@ -63,6 +63,8 @@ struct lincoll_plan_s {
   double tuned_ms = 0.0;
   int tuned_cached = 0;
   int last_path = 0;          // path of the most recent apply (LINCOLL_INFO_LAST_PATH)
+  int opt_check_finite = 0;   // LINCOLL_OPT_CHECK_FINITE
+  int* d_flag = nullptr;      // its device flag
   std::string arch;           // gcnArchName of the plan's device (key of the tuner's cache)
   // replayable graph of the last apply (opt_graph)
   unsigned long alloc_gen = 0;
@@ -345,6 +347,7 @@ const char* lincoll_strerror(int s) {
     case LINCOLL_ENOTREADY: return "Maxwellians not set for this batch";
     case LINCOLL_ENOTIMPL: return "not implemented";
     case LINCOLL_EDIVERGED: return "iteration diverged";
+    case LINCOLL_ENONFINITE: return "non-finite values in the output";
   }
   return "unknown status";
 }
@@ -587,6 +590,25 @@ int checked_apply_args(lincoll_plan_t pl, const void* h, void* out, int batch) {
 
 }  // namespace
 
+namespace {
+
+// LINCOLL_OPT_CHECK_FINITE: scan the output on the plan's stream and read the
+// flag back (synchronises the stream).
+int check_output(lincoll_plan_t pl, const void* out, int batch) {
+  if (!pl->opt_check_finite) return LINCOLL_OK;
+  hipError_t e;
+  if (!pl->d_flag && (e = dalloc(pl, &pl->d_flag, sizeof(int)))) return hip_fail(pl, e);
+  const long count = (long)batch * pl->p.n * pl->p.n * pl->p.n;
+  int host = 0;
+  if ((e = nonfinite_check(out, count, pl->p.dtype == LINCOLL_F64, pl->d_flag, pl->stream)) ||
+      (e = hipMemcpyAsync(&host, pl->d_flag, sizeof(int), hipMemcpyDeviceToHost, pl->stream)) ||
+      (e = hipStreamSynchronize(pl->stream)))
+    return hip_fail(pl, e);
+  return host ? LINCOLL_ENONFINITE : LINCOLL_OK;
+}
+
+}  // namespace
+
 int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
   int st = checked_apply_args(pl, h, out, batch);
   if (st) return st;
@@ -594,7 +616,7 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
   hipError_t e;
   if (!pl->opt_graph) {
     if ((e = launch_apply(pl, h, out, batch, pl->stream))) return hip_fail(pl, e);
-    return LINCOLL_OK;
+    return check_output(pl, out, batch);
   }
   const lincoll_plan_s::GraphKey key{h, out, batch, pl->Bc, use_fused(pl, batch) ? 1 : 0, pl->opt_per_cu, pl->p.project,
                                      pl->alloc_gen};
@@ -603,7 +625,7 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
                     k.fused == key.fused && k.per_cu == key.per_cu && k.project == key.project && k.gen == key.gen;
   if (!same && (e = capture_apply(pl, h, out, batch, key))) return hip_fail(pl, e);
   if ((e = hipGraphLaunch(pl->gexec, pl->stream))) return hip_fail(pl, e);
-  return LINCOLL_OK;
+  return check_output(pl, out, batch);
 }
 
 int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch) {
@@ -674,6 +696,10 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
     case LINCOLL_OPT_TUNE_CACHE:
       if (value != 0 && value != 1) return LINCOLL_EINVAL;
       pl->opt_tune_cache = value;
+      break;
+    case LINCOLL_OPT_CHECK_FINITE:
+      if (value != 0 && value != 1) return LINCOLL_EINVAL;
+      pl->opt_check_finite = value;
       break;
     case LINCOLL_OPT_PATH:
       if (value < LINCOLL_PATH_AUTO || value > LINCOLL_PATH_FUSED) return LINCOLL_EINVAL;
@@ -1066,7 +1092,8 @@ void lincoll_destroy(lincoll_plan_t pl) {
                   pl->d_pref64, pl->d_gfac64, pl->d_Ainv, pl->d_facT, pl->d_prefT, pl->d_mask,  pl->d_Kh,
                   pl->d_nu,   pl->d_tmpA,  pl->d_tmpB,  pl->d_planes64, pl->d_R, pl->d_H, pl->d_W, pl->d_Wq, pl->d_Lp, pl->d_pin,
                   pl->d_rk_k, pl->d_rk_tmp, pl->d_rk_acc, pl->d_Ws, pl->d_qV, pl->d_qF, pl->d_qGp,
-                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ, pl->d_qPh, pl->d_qOs, pl->d_qGW, pl->d_qRule, pl->d_steady};
+                  pl->d_qGm, pl->d_qC, pl->d_qS, pl->d_qQ, pl->d_qPh, pl->d_qOs, pl->d_qGW, pl->d_qRule, pl->d_steady,
+                  pl->d_flag};
   for (void* p : ptrs) dfree(p);
   delete pl;
 }

@@ -154,6 +154,9 @@ hipError_t rk_stage(int dtype, const void* f, const void* k, void* acc, void* tm
 hipError_t rk_final(int dtype, void* f, const void* acc, const void* k, long count, double a, hipStream_t s);
 size_t fused_scratch_bytes(int n, int nslots, int ppt, int dtype);
 bool fused_keep_valid(int n, int dtype, int keep);
+// Sets *flag (device int) to 1 if any of x[0 .. count) is NaN or infinite,
+// else 0 (double if dtype_f64, float otherwise); enqueued on s.
+hipError_t nonfinite_check(const void* x, long count, int dtype_f64, int* flag, hipStream_t s);
 int fused_default_keep(int n, int dtype);
 // The fixed device scratch of lincoll_apply_noalloc on `device` (which must
 // be current): its address and size.

@@ -290,4 +290,27 @@ hipError_t project_cells(const ProjectCtx& c) {
   return hipGetLastError();
 }
 
+// ---- non-finite check (LINCOLL_OPT_CHECK_FINITE) -----------------------------
+namespace {
+
+__global__ void k_flag_clear(int* flag) { *flag = 0; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_nonfinite(const T* __restrict__ x, long count, int* __restrict__ flag) {
+  bool bad = false;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) *flag = 1;   // a plain vector store; any writer leaves 1
+}
+
+}  // namespace
+
+hipError_t nonfinite_check(const void* x, long count, int dtype_f64, int* flag, hipStream_t s) {
+  k_flag_clear<<<1, 1, 0, s>>>(flag);
+  const long blocks = count / 256 + 1 < 4096 ? count / 256 + 1 : 4096;
+  if (dtype_f64) k_nonfinite<double><<<(unsigned)blocks, 256, 0, s>>>(static_cast<const double*>(x), count, flag);
+  else k_nonfinite<float><<<(unsigned)blocks, 256, 0, s>>>(static_cast<const float*>(x), count, flag);
+  return hipGetLastError();
+}
+
 }  // namespace lincoll

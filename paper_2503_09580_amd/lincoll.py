@@ -13,7 +13,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "liblincoll.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENOTIMPL, EDIVERGED = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENOTIMPL, EDIVERGED, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 DTYPES = {"f64": 0, "f32": 1, "bf16x3": 2}
 PATHS = {"auto": 0, "staged": 1, "fused": 2}
 TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
@@ -27,7 +27,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT = 26, 128, 5
 MLP_WEIGHTS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2, "sphere_polar": 3, "sphere_azimuth": 4, "project": 5,
            "quad_fix": 6, "zblock": 7, "plane_tile": 8, "tune_cache": 9, "fused_ppt": 10,
-           "fused_keep": 11}
+           "fused_keep": 11, "check_finite": 12}
 SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
            "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
            "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",

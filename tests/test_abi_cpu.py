@@ -38,6 +38,7 @@ def test_strerror():
     assert lib.lincoll_strerror(0) == b"success"
     assert lib.lincoll_strerror(-1) == b"invalid argument"
     assert lib.lincoll_strerror(-5) == b"not implemented"
+    assert lib.lincoll_strerror(-7) == b"non-finite values in the output"
     assert lib.lincoll_strerror(-99) == b"unknown status"
 
 

@@ -31,6 +31,10 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
 def run(plan, h, params, dtype):
     td = torch.float64 if dtype == "f64" else torch.float32
     ht = torch.from_numpy(np.ascontiguousarray(h)).to(DEV, td)
@@ -252,6 +256,37 @@ def test_abi_errors_on_device():
     assert lib.quadcoll_apply(plan._h, p, ctypes.c_void_p(y.data_ptr()), 2) == lc.OK   # binary operator, FP64
     assert plan.info("J") == n // 2 + 1
     assert plan.info("maxw_batch") == 3
+
+
+@pytest.mark.parametrize("dtype,n,path", [("f32", 32, "fused"), ("f64", 16, "fused"), ("f32", 16, "staged")])
+def test_nonfinite_debug_check(dtype, n, path):
+    """LINCOLL_OPT_CHECK_FINITE: a NaN in one cell's input makes that cell's
+    output non-finite and the apply report LINCOLL_ENONFINITE (the output is
+    still written); finite input passes; without the option the same NaN
+    input returns OK.  Eager and graph replay."""
+    L, om, B = 8.0, 0.74, 20
+    h, params = mixed_inputs(n, L, B, seed=2700 + n)
+    td = torch.float32 if dtype == "f32" else torch.float64
+    for graph in (0, 1):
+        plan = lc.Plan(n, L, om, dtype, path=path)
+        plan.set_option("graph", graph)
+        plan.set_maxwellians(dev(params, torch.float64))
+        x = dev(h, td)
+        out = torch.empty_like(x)
+        plan.set_option("check_finite", 1)
+        plan.apply(x, out)                                  # finite: OK
+        assert bool(torch.isfinite(out).all())
+        bad = x.clone()
+        bad[7, 3, 4, 5] = float("nan")
+        with pytest.raises(lc.LincollError) as err:
+            plan.apply(bad, out)
+        assert err.value.status == lc.ENONFINITE
+        assert not bool(torch.isfinite(out[7]).all())
+        assert bool(torch.isfinite(out[6]).all())           # other cells unaffected
+        plan.set_option("check_finite", 0)
+        plan.apply(bad, out)                                # no check: OK
+        torch.cuda.synchronize()
+        plan.close()
 
 
 def test_empty_and_oversized_batches_are_rejected():
