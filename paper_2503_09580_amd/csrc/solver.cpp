@@ -353,6 +353,13 @@ struct Solver {
       a = rb[0] / a11;
     }
     if (!std::isfinite(a) || !std::isfinite(al)) a = al = 0.0;
+    if (al == 0.0) {
+      // the network's term is dropped (also when its output is not finite:
+      // 0 * NaN would still poison the start), leaving the scaled sweep
+      HIPCK(st_axpby(x0, a, x0, 0.0, nullptr, N, s));
+      HIPCK(st_axpby(V, -a, V, 1.0, b, N, s));              // V0 = b - a Az
+      return LINCOLL_OK;
+    }
     HIPCK(st_axpby(x0, a, x0, al, D, N, s));
     HIPCK(st_axpby(V, -a, V, 1.0, b, N, s));                // V0 = b - a Az
     HIPCK(st_axpby(V, 1.0, V, -al, AD, N, s));              //      - alpha A Delta

@@ -200,3 +200,27 @@ def test_learned_start_end_to_end():
     rn = plan.steady_solve(sp, f)
     print("none inner iterations", rn["inner_iters"], "converged", rn["converged"], rn["res_history"])
     assert (not rn["converged"]) or rn["inner_iters"] >= 5 * rl["inner_iters"], (rn, rl["inner_iters"])
+
+
+@pytest.mark.parametrize("fill", [float("nan"), 1e30])
+def test_learned_start_survives_a_garbage_network(fill):
+    """A garbage network (every weight NaN, so its output is not finite; or
+    every weight 1e30, so it is absurdly large) must not harm the solve: the
+    learned start's two-term minimal-residual fit drops the network's term
+    and keeps the scaled sweep start, so the solve converges to the sweep-only
+    solution in the same Newton steps and about the same inner iterations."""
+    n, L, om, nx = 16, 6.0, 0.74, 64
+    plan = lc.Plan(n, L, om, "f32")
+    f = torch.empty((nx, n, n, n), dtype=torch.float64, device=DEV)
+    rs = plan.steady_solve(lc.steady_params(nx, theta_r=1.5, precond="sweep"), f)
+    fs = f.cpu().numpy().copy()
+    net = lc.MLP(seed=1)
+    net.set_weights(np.full(lc.MLP_WEIGHTS, fill, dtype=np.float32))
+    rep = plan.steady_solve(lc.steady_params(nx, theta_r=1.5, precond="learned", mlp=net), f)
+    print(fill, "inner iterations", rep["inner_iters"], "sweep", rs["inner_iters"], rep["res_history"])
+    assert rep["converged"] and rep["residual"] < 1e-5, rep
+    assert rep["newton_iters"] == rs["newton_iters"]
+    assert rep["inner_iters"] <= 1.25 * rs["inner_iters"], (rep["inner_iters"], rs["inner_iters"])
+    fl = f.cpu().numpy()
+    assert np.all(np.isfinite(fl))
+    assert np.max(np.abs(fl - fs)) <= 1e-3 * np.max(np.abs(fs))
