@@ -57,27 +57,61 @@ __device__ __forceinline__ void twiddle(T& re, T& im) {
 
 // Unnormalised DFT of length N in place, natural order in and out:
 //   X[k] = sum_j x[j] exp(-+ 2 pi i j k / N).
-// Radix-2 decimation in frequency; trivial twiddles are free.
+// Decimation in frequency with radix-4 steps: each step is two radix-2 DIF
+// stages (spans S and S/2) done at once, leaving the same in-place layout, so
+// the output is bit-reversed exactly as after radix-2 stages.  For the four
+// values a, b, c, d at k, k + S/4, k + S/2, k + 3S/4 (w = exp(-+2 pi i / S)):
+//   k        <- (a + c) + (b + d)
+//   k +  S/4 <- ((a + c) - (b + d)) w^2k
+//   k +  S/2 <- ((a - c) -+ i (b - d)) w^k
+//   k + 3S/4 <- ((a - c) +- i (b - d)) w^3k
+// which needs three twiddles where the two radix-2 stages need four.  An odd
+// number of stages ends with one radix-2 stage of span 2 (no twiddles).
 template <int N, bool INV, typename T>
 __device__ __forceinline__ void fft(T (&re)[N], T (&im)[N]) {
   static_assert(N >= 2 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
-  static_for<0, ilog2(N)>([&](auto s) {
-    constexpr int span = N >> s;
-    constexpr int half = span / 2;
+  constexpr int LOG = ilog2(N);
+  static_for<0, LOG / 2>([&](auto st) {
+    constexpr int span = N >> (2 * st);
+    constexpr int q = span / 4;
     static_for<0, N / span>([&](auto g) {
-      static_for<0, half>([&](auto k) {
-        constexpr int i0 = g * span + k;
-        constexpr int i1 = i0 + half;
-        const T ar = re[i0], ai = im[i0], br = re[i1], bi = im[i1];
-        re[i0] = ar + br;
-        im[i0] = ai + bi;
-        T dr = ar - br, di = ai - bi;
-        twiddle<span, k, INV>(dr, di);
-        re[i1] = dr;
-        im[i1] = di;
+      static_for<0, q>([&](auto k) {
+        constexpr int i0 = g * span + k, i1 = i0 + q, i2 = i0 + 2 * q, i3 = i0 + 3 * q;
+        const T t0r = re[i0] + re[i2], t0i = im[i0] + im[i2];
+        const T t1r = re[i0] - re[i2], t1i = im[i0] - im[i2];
+        const T t2r = re[i1] + re[i3], t2i = im[i1] + im[i3];
+        const T dr = re[i1] - re[i3], di = im[i1] - im[i3];
+        // t3 = -i (b - d) forward, +i (b - d) inverse
+        const T t3r = INV ? -di : di, t3i = INV ? dr : -dr;
+        re[i0] = t0r + t2r;
+        im[i0] = t0i + t2i;
+        T xr = t0r - t2r, xi = t0i - t2i;
+        twiddle<span, 2 * k, INV>(xr, xi);
+        re[i1] = xr;
+        im[i1] = xi;
+        xr = t1r + t3r;
+        xi = t1i + t3i;
+        twiddle<span, k, INV>(xr, xi);
+        re[i2] = xr;
+        im[i2] = xi;
+        xr = t1r - t3r;
+        xi = t1i - t3i;
+        twiddle<span, 3 * k, INV>(xr, xi);
+        re[i3] = xr;
+        im[i3] = xi;
       });
     });
   });
+  if constexpr (LOG % 2 == 1) {
+    static_for<0, N / 2>([&](auto g) {
+      constexpr int i0 = 2 * g, i1 = i0 + 1;
+      const T ar = re[i0], ai = im[i0], br = re[i1], bi = im[i1];
+      re[i0] = ar + br;
+      im[i0] = ai + bi;
+      re[i1] = ar - br;
+      im[i1] = ai - bi;
+    });
+  }
   T tr[N], ti[N];
   static_for<0, N>([&](auto i) {
     constexpr int r = bitrev(i, N);
