@@ -197,3 +197,25 @@ def test_solve_heat_transfer_profile():
     p = rho * th
     assert np.max(np.abs(p - p.mean())) < 0.02 * p.mean()
     assert 1.0 < th[0] and th[-1] < 1.5
+    # Fluxes through every cell face, walls included (upwind, with the wall
+    # ghosts).  In a steady state each face-to-face difference is the cell's
+    # collision moment: zero for mass (Q's mass fix), close to zero for
+    # momentum and energy (the spectral Q conserves them up to its
+    # discretisation error).  So the mass flux vanishes at every face (the
+    # walls pass none), the momentum flux is the same at every face, and the
+    # heat flux runs from the hot right wall to the cold left one (negative
+    # along x) and is nearly the same at every face.
+    h3 = P.hv ** 3
+    g0, g1 = P.ghosts(f)
+    ext = np.concatenate([g0[None], f, g1[None]], axis=0)
+    v1 = P.V[0]
+    e = sum(P.V[d] ** 2 for d in range(3)) / 2.0
+
+    def face_flux(w):
+        return np.array([h3 * np.sum(w * (P.vp * ext[i] + P.vm * ext[i + 1])) for i in range(P.nx + 1)])
+
+    fm, fp, fe = face_flux(np.ones_like(v1)), face_flux(v1), face_flux(e)
+    assert np.max(np.abs(fm)) < 1e-10, fm
+    assert np.max(np.abs(fp - fp.mean())) < 1e-3 * abs(fp.mean()), fp
+    assert np.all(fe < 0.0), fe
+    assert np.max(np.abs(fe - fe.mean())) < 0.03 * abs(fe.mean()), fe
