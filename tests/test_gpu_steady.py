@@ -185,6 +185,32 @@ def test_c4_solve_converges_like_the_paper():
     scale = np.linalg.norm(P.transport(fj)[1]) + np.linalg.norm(P.q(fj[1:2])[0]) / sp.kn
     assert np.linalg.norm(got - ref) <= 1e-12 * scale, np.linalg.norm(got - ref) / scale
     check(got, ref, 1e-12, scale=np.abs(P.transport(fj)[1]) + np.abs(P.q(fj[1:2])[0]) / sp.kn)
+    # face fluxes of the full converged state (a property at any size): in a
+    # steady state the face-to-face differences are the cells' collision
+    # moments plus their residual, so the mass flux vanishes at every face up
+    # to the Newton tolerance (Q conserves mass exactly, the walls pass none),
+    # the momentum flux is the same at every face, and heat runs from the hot
+    # right wall to the cold left one, nearly the same at every face
+    full = oracle_problem(n, L, om, sp)
+    fa = f.cpu().numpy()
+    g0, g1 = full.ghosts(fa)
+    ext = np.concatenate([g0[None], fa, g1[None]], axis=0)
+    h3 = full.hv ** 3
+    e = sum(full.V[d] ** 2 for d in range(3)) / 2.0
+
+    def face_flux(w):
+        return np.array([h3 * np.sum(w * (full.vp * ext[i] + full.vm * ext[i + 1])) for i in range(nx + 1)])
+
+    fm, fp, fe = face_flux(1.0), face_flux(full.V[0]), face_flux(e)
+    print(f"C4 face fluxes: mass max {np.max(np.abs(fm)):.3e}; momentum {fp.min():.6f}..{fp.max():.6f}; "
+          f"heat {fe.min():.6f}..{fe.max():.6f}")
+    # sum_j dx h3 |sum_k r_jk| <= sqrt(dx h3 n_values) |r|_w bounds the mass flux
+    bound = np.sqrt(full.dx * h3 * fa.size) * rep["residual"]
+    assert np.max(np.abs(fm)) <= bound, (np.max(np.abs(fm)), bound)
+    # measured: mass 3.7e-7, momentum constant to 1.5e-5, heat to 1e-3
+    assert np.max(np.abs(fp - fp.mean())) < 1e-4 * abs(fp.mean()), fp
+    assert np.all(fe < 0.0)
+    assert np.max(np.abs(fe - fe.mean())) < 1e-2 * abs(fe.mean())
 
 
 @pytest.mark.parametrize("kind,kn,par,count", [
