@@ -124,6 +124,41 @@ __device__ __forceinline__ void fft(T (&re)[N], T (&im)[N]) {
   });
 }
 
+// The same transform with radix-2 steps only (four twiddle multiplies per
+// pair of stages instead of three, but two live values per butterfly instead
+// of four): the fused kernel, whose registers are full, runs faster with it.
+template <int N, bool INV, typename T>
+__device__ __forceinline__ void fft_r2(T (&re)[N], T (&im)[N]) {
+  static_assert(N >= 2 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
+  static_for<0, ilog2(N)>([&](auto s) {
+    constexpr int span = N >> s;
+    constexpr int half = span / 2;
+    static_for<0, N / span>([&](auto g) {
+      static_for<0, half>([&](auto k) {
+        constexpr int i0 = g * span + k;
+        constexpr int i1 = i0 + half;
+        const T ar = re[i0], ai = im[i0], br = re[i1], bi = im[i1];
+        re[i0] = ar + br;
+        im[i0] = ai + bi;
+        T dr = ar - br, di = ai - bi;
+        twiddle<span, k, INV>(dr, di);
+        re[i1] = dr;
+        im[i1] = di;
+      });
+    });
+  });
+  T tr[N], ti[N];
+  static_for<0, N>([&](auto i) {
+    constexpr int r = bitrev(i, N);
+    tr[r] = re[i];
+    ti[r] = im[i];
+  });
+  static_for<0, N>([&](auto i) {
+    re[i] = tr[i];
+    im[i] = ti[i];
+  });
+}
+
 // Two real length-N sequences a, b packed as z = a + i b, transformed
 // forward: returns the half spectra A[k], B[k], k = 0..N/2.
 template <int N, typename T>

@@ -36,7 +36,7 @@
 // X -> Z exchange.
 #include <mutex>
 
-#include "fft.h"
+#include "fft.h"   // fft_r2 throughout: see its comment
 #include "internal.h"
 
 namespace lincoll {
@@ -91,7 +91,7 @@ __device__ __forceinline__ void lds_dma(const float* src, float* dst, int count,
 template <int NN, typename T>
 __device__ __forceinline__ void z_forward(T (&zr)[NN], T (&zi)[NN], T (&vr)[NN], T (&vi)[NN]) {
   constexpr int N = NN / 2;
-  fft<NN, false>(zr, zi);
+  fft_r2<NN, false>(zr, zi);
   T Ar[N + 1], Ai[N + 1], Br[N + 1], Bi[N + 1];
   split_real_pair<NN>(zr, zi, Ar, Ai, Br, Bi);
   vr[0] = Ar[0];
@@ -117,7 +117,7 @@ __device__ __forceinline__ void z_inverse(const T (&vr)[NN], const T (&vi)[NN], 
     Br[k] = vr[N + k]; Bi[k] = vi[N + k];
   });
   join_real_pair<NN>(Ar, Ai, Br, Bi, zr, zi);
-  fft<NN, true>(zr, zi);
+  fft_r2<NN, true>(zr, zi);
 }
 
 // Wave-private copy of K_j: wave w's planes kp = w*PW .. w*PW+PW-1 of the
@@ -504,13 +504,13 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         z_forward<NN, TL>(zr, zi, fr, fi);
       }
       exch_z_to_x<NN, TL>(fr, fi, lds, t);
-      fft<NN, false>(fr, fi);
+      fft_r2<NN, false>(fr, fi);
       exch_transpose<NN, TL>(fr, fi, lds, t);
-      fft<NN, false>(fr, fi);
+      fft_r2<NN, false>(fr, fi);
       radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Omega(|k|^2) / n^3
-      fft<NN, true>(fr, fi);
+      fft_r2<NN, true>(fr, fi);
       exch_transpose<NN, TL>(fr, fi, lds, t);
-      fft<NN, true>(fr, fi);
+      fft_r2<NN, true>(fr, fi);
       exch_x_to_z<NN, TL>(fr, fi, lds, t);
       TL zr[NN], zi[NN];
       z_inverse<NN, TL>(fr, fi, zr, zi);
@@ -558,9 +558,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         z_forward<NN, double>(zr, zi, vr, vi);
       }
       z_to_x_d<NN>(vr, vi, lds, t);
-      fft<NN, false>(vr, vi);
+      fft_r2<NN, false>(vr, vi);
       transpose_plane_d<NN>(vr, vi, lds, t);
-      fft<NN, false>(vr, vi);
+      fft_r2<NN, false>(vr, vi);
       static_for<0, NN>([&](auto ky) { Rs[ky * C::T + t] = double2{vr[ky], vi[ky]}; });
     }
     k_slice_dma<NN>(Kh + (size_t)cc * J * kh_stride(NN), lds, t);   // K_0 into this wave's region
@@ -590,9 +590,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
           constexpr int fy = ky <= N ? ky : NN - ky;
           return double2{Kw[(kw * P + fy) * P + fx], Kw[(PW * P + fy) * P + fx]};
         });
-        fft<NN, true>(vr, vi);
+        fft_r2<NN, true>(vr, vi);
         transpose_plane_d<NN>(vr, vi, lds, t);
-        fft<NN, true>(vr, vi);
+        fft_r2<NN, true>(vr, vi);
         x_to_z_d<NN>(vr, vi, lds, t);
         // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
         // the z stage runs.  It is complete and visible after the wait and
@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
           if constexpr (c < KA + KL) acc[c] = j > 0 ? accl[c - KA][t] : V{};
           else acc[c] = j > 0 ? Ac[c * C::T + t] : V{};
         });
-      fft<NN, false>(fr, fi);
+      fft_r2<NN, false>(fr, fi);
       exch_transpose<NN, TL>(fr, fi, lds, t);
       // This wave is done with its region until the next node's K_j product;
       // its transpose reads complete (lgkmcnt(0)) before the copy may land.
@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         __builtin_amdgcn_s_waitcnt(0xc07f);
         k_slice_dma<NN>(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), lds, t);
       }
-      fft<NN, false>(fr, fi);
+      fft_r2<NN, false>(fr, fi);
       radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Phi_j / n^3
       static_for<0, NCH>([&](auto c) {
         V a;
@@ -652,9 +652,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       });
     }
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
-    fft<NN, true>(Lr, Li);
+    fft_r2<NN, true>(Lr, Li);
     exch_transpose<NN, TL>(Lr, Li, lds, t);
-    fft<NN, true>(Lr, Li);
+    fft_r2<NN, true>(Lr, Li);
     exch_x_to_z<NN, TL>(Lr, Li, lds, t);
     {
       TL zr[NN], zi[NN];
@@ -843,17 +843,17 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
       z_to_x_2<NN, float>(fr, fi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2, kp = p / NN;
-        fft<NN, false>(fr[s], fi[s]);
+        fft_r2<NN, false>(fr[s], fi[s]);
         transpose_plane<NN, float>(fr[s], fi[s], lds, p);
-        fft<NN, false>(fr[s], fi[s]);
+        fft_r2<NN, false>(fr[s], fi[s]);
         mode_multiply<NN, float>(fr[s], fi[s], p, [&](auto ky) {   // Omega(|k|^2) / n^3
           constexpr int fy = ky <= N ? ky : NN - ky;
           const int q = fx * fx + fy * fy;
           return float2{tab[q + kp * kp], tab[q + N * N]};
         });
-        fft<NN, true>(fr[s], fi[s]);
+        fft_r2<NN, true>(fr[s], fi[s]);
         transpose_plane<NN, float>(fr[s], fi[s], lds, p);
-        fft<NN, true>(fr[s], fi[s]);
+        fft_r2<NN, true>(fr[s], fi[s]);
       });
       x_to_z_2<NN, float>(fr, fi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
@@ -900,9 +900,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
       z_to_x_2d<NN>(vr, vi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2;
-        fft<NN, false>(vr[s], vi[s]);
+        fft_r2<NN, false>(vr[s], vi[s]);
         transpose_plane_d<NN>(vr[s], vi[s], lds, p);
-        fft<NN, false>(vr[s], vi[s]);
+        fft_r2<NN, false>(vr[s], vi[s]);
         static_for<0, NN>([&](auto ky) { Rs[ky * C::T + p] = double2{vr[s][ky], vi[s][ky]}; });
       });
     }
@@ -937,9 +937,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
         });
         static_for<0, 2>([&](auto s) {
           const int p = t + s * T2;
-          fft<NN, true>(vr[s], vi[s]);
+          fft_r2<NN, true>(vr[s], vi[s]);
           transpose_plane_d<NN>(vr[s], vi[s], lds, p);
-          fft<NN, true>(vr[s], vi[s]);
+          fft_r2<NN, true>(vr[s], vi[s]);
         });
         x_to_z_2d<NN>(vr, vi, lds, t, T2);
         // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
@@ -965,7 +965,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
       z_to_x_2<NN, float>(fr, fi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2;
-        fft<NN, false>(fr[s], fi[s]);
+        fft_r2<NN, false>(fr[s], fi[s]);
         transpose_plane<NN, float>(fr[s], fi[s], lds, p);
       });
       // This wave is done with its regions until the next node's K_j product;
@@ -976,7 +976,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
       }
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2, kp = p / NN;
-        fft<NN, false>(fr[s], fi[s]);
+        fft_r2<NN, false>(fr[s], fi[s]);
         mode_multiply<NN, float>(fr[s], fi[s], p, [&](auto ky) {       // Phi_j / n^3
           constexpr int fy = ky <= N ? ky : NN - ky;
           const int q = fx * fx + fy * fy;
@@ -991,9 +991,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
     static_for<0, 2>([&](auto s) {
       const int p = t + s * T2;
-      fft<NN, true>(Lr[s], Li[s]);
+      fft_r2<NN, true>(Lr[s], Li[s]);
       transpose_plane<NN, float>(Lr[s], Li[s], lds, p);
-      fft<NN, true>(Lr[s], Li[s]);
+      fft_r2<NN, true>(Lr[s], Li[s]);
     });
     x_to_z_2<NN, float>(Lr, Li, lds, t, T2);
     static_for<0, 2>([&](auto s) {
