@@ -625,6 +625,7 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
                     k.fused == key.fused && k.per_cu == key.per_cu && k.project == key.project && k.gen == key.gen;
   if (!same && (e = capture_apply(pl, h, out, batch, key))) return hip_fail(pl, e);
   if ((e = hipGraphLaunch(pl->gexec, pl->stream))) return hip_fail(pl, e);
+  pl->last_path = key.fused ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED;
   return check_output(pl, out, batch);
 }
 
@@ -645,6 +646,7 @@ int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch
   c.R = scr;
   c.max_slots = (int)(bytes / slot);
   if ((e = fused_apply(c))) return hip_fail(pl, e);
+  pl->last_path = LINCOLL_PATH_FUSED;
   return LINCOLL_OK;
 }
 
@@ -994,6 +996,7 @@ int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
   }
   for (int i = 0; i < steps; ++i)
     if ((e = hipGraphLaunch(pl->rk_gexec, pl->stream))) return hip_fail(pl, e);
+  if (steps > 0) pl->last_path = key.fused ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED;
   return LINCOLL_OK;
 }
 

@@ -87,6 +87,41 @@ def test_graph_replay_is_bitwise_eager(n, dtype, path, batch):
     assert torch.equal(out2.cpu(), eager_result(n, L, om, dtype, path, h, params2))
 
 
+def test_last_path_follows_every_entry_point():
+    """LINCOLL_INFO_LAST_PATH names the path of the most recent apply, also
+    when it was a graph replay (of an apply or of RK4 steps) or the
+    no-allocation entry point.  One Maxwellian serves every batch; an AUTO
+    FP32 plan at n = 32 takes the staged kernels for 2 cells and the fused
+    kernel for 16."""
+    n, L, om = 32, 8.0, 0.74
+    staged, fused = lc.PATHS["staged"], lc.PATHS["fused"]
+    plan = lc.Plan(n, L, om, "f32")
+    assert plan.info("last_path") == 0
+    _, params = mixed_inputs(n, L, 1, seed=811)
+    plan.set_maxwellians(dev(params, torch.float64))
+    small = dev(mixed_inputs(n, L, 2, seed=812)[0], torch.float32)
+    big = dev(mixed_inputs(n, L, 16, seed=813)[0], torch.float32)
+    plan.apply(small)
+    assert plan.info("last_path") == staged
+    out = plan.apply(big)
+    assert plan.info("last_path") == fused
+    plan.set_option("graph", 1)
+    plan.apply(big, out)                     # records
+    f = small.clone()
+    plan.rk4(f, 1e-3, 2)                     # records and replays RK4 steps on 2 cells
+    assert plan.info("last_path") == staged
+    plan.apply(big, out)                     # replays the recorded apply
+    assert plan.info("last_path") == fused
+    plan.rk4(f, 1e-3, 1)                     # replays the recorded RK4 step
+    assert plan.info("last_path") == staged
+    out2 = torch.empty_like(big)
+    plan.apply_noalloc(big, out2)
+    assert plan.info("last_path") == fused
+    torch.cuda.synchronize()
+    assert torch.equal(out.cpu(), out2.cpu())
+    assert torch.isfinite(f).all()
+
+
 def test_graph_rerecords_after_reallocation():
     """A larger batch reallocates the plan's buffers; the replay must not use
     the old pointers."""
