@@ -36,7 +36,7 @@
 // X -> Z exchange.
 #include <mutex>
 
-#include "fft.h"   // fft_r2 throughout: see its comment
+#include "fft.h"
 #include "internal.h"
 
 namespace lincoll {
@@ -87,13 +87,15 @@ __device__ __forceinline__ void lds_dma(const float* src, float* dst, int count,
 
 // ---- z stage: two real columns <-> their packed half spectra ------------------
 // forward: a, b real (as zr, zi) -> v[k] (column a) and v[N + k] (column b),
-// k < N; bin 0 holds (A(0), A(N)), bins 1..N-1 the complex A(k).
+// k < N; bin 0 holds (A(0), A(N)), bins 1..N-1 the complex A(k).  The
+// spectra come out scaled by ga and gb.
 template <int NN, typename T>
-__device__ __forceinline__ void z_forward(T (&zr)[NN], T (&zi)[NN], T (&vr)[NN], T (&vi)[NN]) {
+__device__ __forceinline__ void z_forward(T (&zr)[NN], T (&zi)[NN], T (&vr)[NN], T (&vi)[NN], T ga = T(1),
+                                          T gb = T(1)) {
   constexpr int N = NN / 2;
-  fft_r2<NN, false>(zr, zi);
+  fft<NN, false>(zr, zi);
   T Ar[N + 1], Ai[N + 1], Br[N + 1], Bi[N + 1];
-  split_real_pair<NN>(zr, zi, Ar, Ai, Br, Bi);
+  split_real_pair<NN>(zr, zi, Ar, Ai, Br, Bi, T(0.5) * ga, T(0.5) * gb);
   vr[0] = Ar[0];
   vi[0] = Ar[N];
   vr[N] = Br[0];
@@ -117,7 +119,7 @@ __device__ __forceinline__ void z_inverse(const T (&vr)[NN], const T (&vi)[NN], 
     Br[k] = vr[N + k]; Bi[k] = vi[N + k];
   });
   join_real_pair<NN>(Ar, Ai, Br, Bi, zr, zi);
-  fft_r2<NN, true>(zr, zi);
+  fft<NN, true>(zr, zi);
 }
 
 // Wave-private copy of K_j: wave w's planes kp = w*PW .. w*PW+PW-1 of the
@@ -504,13 +506,13 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         z_forward<NN, TL>(zr, zi, fr, fi);
       }
       exch_z_to_x<NN, TL>(fr, fi, lds, t);
-      fft_r2<NN, false>(fr, fi);
+      fft<NN, false>(fr, fi);
       exch_transpose<NN, TL>(fr, fi, lds, t);
-      fft_r2<NN, false>(fr, fi);
+      fft<NN, false>(fr, fi);
       radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Omega(|k|^2) / n^3
-      fft_r2<NN, true>(fr, fi);
+      fft<NN, true>(fr, fi);
       exch_transpose<NN, TL>(fr, fi, lds, t);
-      fft_r2<NN, true>(fr, fi);
+      fft<NN, true>(fr, fi);
       exch_x_to_z<NN, TL>(fr, fi, lds, t);
       TL zr[NN], zi[NN];
       z_inverse<NN, TL>(fr, fi, zr, zi);
@@ -558,9 +560,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         z_forward<NN, double>(zr, zi, vr, vi);
       }
       z_to_x_d<NN>(vr, vi, lds, t);
-      fft_r2<NN, false>(vr, vi);
+      fft<NN, false>(vr, vi);
       transpose_plane_d<NN>(vr, vi, lds, t);
-      fft_r2<NN, false>(vr, vi);
+      fft<NN, false>(vr, vi);
       static_for<0, NN>([&](auto ky) { Rs[ky * C::T + t] = double2{vr[ky], vi[ky]}; });
     }
     k_slice_dma<NN>(Kh + (size_t)cc * J * kh_stride(NN), lds, t);   // K_0 into this wave's region
@@ -590,16 +592,20 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
           constexpr int fy = ky <= N ? ky : NN - ky;
           return double2{Kw[(kw * P + fy) * P + fx], Kw[(PW * P + fy) * P + fx]};
         });
-        fft_r2<NN, true>(vr, vi);
+        fft<NN, true>(vr, vi);
         transpose_plane_d<NN>(vr, vi, lds, t);
-        fft_r2<NN, true>(vr, vi);
+        fft<NN, true>(vr, vi);
         x_to_z_d<NN>(vr, vi, lds, t);
         // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
         // the z stage runs.  It is complete and visible after the wait and
         // first barrier of the next X <- Z exchange.
         lds_dma(reinterpret_cast<const float*>(Phi + (size_t)j * phi_stride(NN)), reinterpret_cast<float*>(tab),
                 Q * int(sizeof(TL) / 4), t, C::T);
-        // psi on the two columns, times M^h; TL from here on
+        // psi on the two columns, times M^h; TL from here on.  M^h is a
+        // product of one factor per axis: the z factor multiplies each
+        // point, the column's constant x-y factor (g1, g2) scales the
+        // column's spectrum inside z_forward, in the multiply by 1/2 that
+        // separating the two real columns needs anyway.
         double zr[NN], zi[NN];
         z_inverse<NN, double>(vr, vi, zr, zi);
         const double hx = prefH * eh[zx];
@@ -607,10 +613,10 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         TL qr[NN], qi[NN];
         static_for<0, NN>([&](auto z) {
           const double ez = eh[2 * NN + z];
-          qr[z] = TL(zr[z] * (g1 * ez));
-          qi[z] = TL(zi[z] * (g2 * ez));
+          qr[z] = TL(zr[z] * ez);
+          qi[z] = TL(zi[z] * ez);
         });
-        z_forward<NN, TL>(qr, qi, fr, fi);
+        z_forward<NN, TL>(qr, qi, fr, fi, TL(g1), TL(g2));
       }
       __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
       exch_z_to_x<NN, TL>(fr, fi, lds, t);
@@ -622,7 +628,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
           if constexpr (c < KA + KL) acc[c] = j > 0 ? accl[c - KA][t] : V{};
           else acc[c] = j > 0 ? Ac[c * C::T + t] : V{};
         });
-      fft_r2<NN, false>(fr, fi);
+      fft<NN, false>(fr, fi);
       exch_transpose<NN, TL>(fr, fi, lds, t);
       // This wave is done with its region until the next node's K_j product;
       // its transpose reads complete (lgkmcnt(0)) before the copy may land.
@@ -630,7 +636,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
         __builtin_amdgcn_s_waitcnt(0xc07f);
         k_slice_dma<NN>(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), lds, t);
       }
-      fft_r2<NN, false>(fr, fi);
+      fft<NN, false>(fr, fi);
       radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Phi_j / n^3
       static_for<0, NCH>([&](auto c) {
         V a;
@@ -652,9 +658,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
       });
     }
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
-    fft_r2<NN, true>(Lr, Li);
+    fft<NN, true>(Lr, Li);
     exch_transpose<NN, TL>(Lr, Li, lds, t);
-    fft_r2<NN, true>(Lr, Li);
+    fft<NN, true>(Lr, Li);
     exch_x_to_z<NN, TL>(Lr, Li, lds, t);
     {
       TL zr[NN], zi[NN];
@@ -843,17 +849,17 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
       z_to_x_2<NN, float>(fr, fi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2, kp = p / NN;
-        fft_r2<NN, false>(fr[s], fi[s]);
+        fft<NN, false>(fr[s], fi[s]);
         transpose_plane<NN, float>(fr[s], fi[s], lds, p);
-        fft_r2<NN, false>(fr[s], fi[s]);
+        fft<NN, false>(fr[s], fi[s]);
         mode_multiply<NN, float>(fr[s], fi[s], p, [&](auto ky) {   // Omega(|k|^2) / n^3
           constexpr int fy = ky <= N ? ky : NN - ky;
           const int q = fx * fx + fy * fy;
           return float2{tab[q + kp * kp], tab[q + N * N]};
         });
-        fft_r2<NN, true>(fr[s], fi[s]);
+        fft<NN, true>(fr[s], fi[s]);
         transpose_plane<NN, float>(fr[s], fi[s], lds, p);
-        fft_r2<NN, true>(fr[s], fi[s]);
+        fft<NN, true>(fr[s], fi[s]);
       });
       x_to_z_2<NN, float>(fr, fi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
@@ -900,9 +906,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
       z_to_x_2d<NN>(vr, vi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2;
-        fft_r2<NN, false>(vr[s], vi[s]);
+        fft<NN, false>(vr[s], vi[s]);
         transpose_plane_d<NN>(vr[s], vi[s], lds, p);
-        fft_r2<NN, false>(vr[s], vi[s]);
+        fft<NN, false>(vr[s], vi[s]);
         static_for<0, NN>([&](auto ky) { Rs[ky * C::T + p] = double2{vr[s][ky], vi[s][ky]}; });
       });
     }
@@ -937,9 +943,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
         });
         static_for<0, 2>([&](auto s) {
           const int p = t + s * T2;
-          fft_r2<NN, true>(vr[s], vi[s]);
+          fft<NN, true>(vr[s], vi[s]);
           transpose_plane_d<NN>(vr[s], vi[s], lds, p);
-          fft_r2<NN, true>(vr[s], vi[s]);
+          fft<NN, true>(vr[s], vi[s]);
         });
         x_to_z_2d<NN>(vr, vi, lds, t, T2);
         // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
@@ -955,17 +961,17 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
           float qr[NN], qi[NN];
           static_for<0, NN>([&](auto z) {
             const double ez = eh[2 * NN + z];
-            qr[z] = float(zr[z] * (g1 * ez));
-            qi[z] = float(zi[z] * (g2 * ez));
+            qr[z] = float(zr[z] * ez);
+            qi[z] = float(zi[z] * ez);
           });
-          z_forward<NN, float>(qr, qi, fr[s], fi[s]);
+          z_forward<NN, float>(qr, qi, fr[s], fi[s], float(g1), float(g2));   // g1, g2 as in k_fused
         });
       }
       __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
       z_to_x_2<NN, float>(fr, fi, lds, t, T2);
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2;
-        fft_r2<NN, false>(fr[s], fi[s]);
+        fft<NN, false>(fr[s], fi[s]);
         transpose_plane<NN, float>(fr[s], fi[s], lds, p);
       });
       // This wave is done with its regions until the next node's K_j product;
@@ -976,7 +982,7 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
       }
       static_for<0, 2>([&](auto s) {
         const int p = t + s * T2, kp = p / NN;
-        fft_r2<NN, false>(fr[s], fi[s]);
+        fft<NN, false>(fr[s], fi[s]);
         mode_multiply<NN, float>(fr[s], fi[s], p, [&](auto ky) {       // Phi_j / n^3
           constexpr int fy = ky <= N ? ky : NN - ky;
           const int q = fx * fx + fy * fy;
@@ -991,9 +997,9 @@ __global__ void __launch_bounds__(Cfg<NN>::T / 2) k_fused2(
     // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
     static_for<0, 2>([&](auto s) {
       const int p = t + s * T2;
-      fft_r2<NN, true>(Lr[s], Li[s]);
+      fft<NN, true>(Lr[s], Li[s]);
       transpose_plane<NN, float>(Lr[s], Li[s], lds, p);
-      fft_r2<NN, true>(Lr[s], Li[s]);
+      fft<NN, true>(Lr[s], Li[s]);
     });
     x_to_z_2<NN, float>(Lr, Li, lds, t, T2);
     static_for<0, 2>([&](auto s) {

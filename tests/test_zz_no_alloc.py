@@ -4,6 +4,7 @@ calls in a row, the second with a smaller input; no allocation attempted
 (an injected allocation failure stays unused, the plan's and torch's device
 memory unchanged); unsupported configurations rejected."""
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -43,17 +44,25 @@ def test_noalloc_matches_apply_twice(n, big, small, dtype):
         ref = plan.apply(x)
         out = torch.full_like(x, float("nan"))
         torch.cuda.synchronize()
-        held = plan.info("device_bytes")
-        torch_held = torch.cuda.memory_allocated(DEV)
-        lib.lincoll_debug_fail_alloc(1)     # any library allocation now fails
+        # tensors of earlier tests freed by the cycle collector would change
+        # torch's count in between: collect first, and not during the call
+        gc.collect()
+        gc.disable()
         try:
-            st = lib.lincoll_apply_noalloc(plan._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), B)
+            held = plan.info("device_bytes")
+            torch_held = torch.cuda.memory_allocated(DEV)
+            lib.lincoll_debug_fail_alloc(1)     # any library allocation now fails
+            try:
+                st = lib.lincoll_apply_noalloc(plan._h, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), B)
+            finally:
+                lib.lincoll_debug_fail_alloc(0)
+            assert st == lc.OK, lc.library().lincoll_strerror(st)
+            torch.cuda.synchronize()
+            assert plan.info("device_bytes") == held
+            assert torch.cuda.memory_allocated(DEV) == torch_held
         finally:
-            lib.lincoll_debug_fail_alloc(0)
-        assert st == lc.OK, lc.library().lincoll_strerror(st)
-        torch.cuda.synchronize()
-        assert plan.info("device_bytes") == held
-        assert torch.cuda.memory_allocated(DEV) == torch_held
+            gc.enable()
         assert torch.equal(out, ref), float((out - ref).abs().max())
 
 
