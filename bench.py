@@ -49,13 +49,19 @@ def alg_bytes_per_cell(n, elem):
 # Sources whose compiled code is the fused kernel; a counter record is only
 # used while their hash matches.
 KERNEL_SOURCES = {
-    "fused": ["paper_2503_09580_amd/csrc/fused.hip", "paper_2503_09580_amd/csrc/fft.h",
+    "fused": ["paper_2503_09580_amd/csrc/fused.hip", "paper_2503_09580_amd/csrc/fused_body.inc",
+              "paper_2503_09580_amd/csrc/fft.h",
               "paper_2503_09580_amd/csrc/twiddles.h", "paper_2503_09580_amd/csrc/internal.h"],
 }
-def fused_kernel_name(n, ppt, keep, dtype):
-    """Name of the fused kernel instance a plan launches (as in the profiles)."""
+def fused_kernel_name(n, ppt, keep, dtype, split=1):
+    """Name of the fused kernel instance a plan launches (as in the profiles);
+    a split apply is two launches."""
     tl = "double" if dtype == "f64" else "float"
-    return f"k_fused2<{n}>" if ppt == 2 else f"k_fused<{n}, {keep}, {tl}>"
+    if ppt == 2:
+        return f"k_fused2<{n}>"
+    if split > 1:
+        return f"k_fused_split<{n}, {keep}, {tl}> + k_fused_finish<{n}, {tl}>"
+    return f"k_fused<{n}, {keep}, {tl}>"
 
 
 def kernel_source_hash(path):
@@ -581,10 +587,11 @@ def main():
                   "fused_pencils_per_thread": int(plan.info("fused_ppt")) if path == "fused" else None,
                   "fused_accumulator_chunks_in_registers": int(plan.info("fused_keep"))
                   if path == "fused" and plan.info("fused_ppt") == 1 else None,
+                  "fused_workgroups_per_cell": int(plan.info("fused_split")) if path == "fused" else None,
                   "staged_zblock": int(plan.info("zblock")) if path == "staged" else None,
                   "staged_plane_tile": int(plan.info("plane_tile")) if path == "staged" else None,
                   "tuner": "lincoll_autotune over path x workgroups/CU x fused pencils per thread x fused "
-                           "accumulator split x staged tiles x graph"}
+                           "accumulator split x fused workgroups per cell x staged tiles x graph"}
         for _ in range(a.warmup):
             plan.apply(ht, out)
         stream.synchronize()
@@ -627,19 +634,21 @@ def main():
                   "what": "lincoll_set_maxwellians for all cells (FP64 per-cell setup), untimed in value"},
     }
     # Roofline of the dominant kernel.  On the fused path a step is exactly one
-    # launch of the fused kernel on `stream`, so the event-timed step is that
-    # kernel's average launch duration; the staged path is reported as a whole.
+    # launch of the fused kernel on `stream` (two for a split apply: the parts,
+    # then the sum and inverse), so the event-timed step is that kernel's
+    # average launch duration; the staged path is reported as a whole.
     fl = alg_flops_per_cell(n, J) * B
     by = alg_bytes_per_cell(n, elem) * B
     achieved = fl / (ms_per_step / 1e3) / 1e12
-    kname = (fused_kernel_name(n, int(plan.info("fused_ppt")), int(plan.info("fused_keep")), a.dtype) if path == "fused"
-             else "lincoll_apply (all launches of one step)")
+    split = int(plan.info("fused_split")) if path == "fused" else 1
+    kname = (fused_kernel_name(n, int(plan.info("fused_ppt")), int(plan.info("fused_keep")), a.dtype, split)
+             if path == "fused" else "lincoll_apply (all launches of one step)")
     tr = traffic_record(kname, a.config, a.dtype, path) if path == "fused" else None
     rec["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / PEAK_VALU_TFLOPS,
                        "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
                        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                       "kernel": kname, "launches_per_step": 1 if path == "fused" else None,
+                       "kernel": kname, "launches_per_step": (2 if split > 1 else 1) if path == "fused" else None,
                        "alg_flops_per_launch": fl, "alg_bytes_per_launch": by,
                        "hbm_GBs_compulsory": by / (ms_per_step / 1e3) / 1e9}
     if tr:

@@ -54,11 +54,15 @@ typedef enum {
 } lincoll_dtype_t;
 
 typedef enum {
-  LINCOLL_PATH_AUTO = 0,    /* fused kernel where it exists and the batch is large enough for one cell per
-                               compute unit to beat the staged kernels (n = 16: any batch; n = 32: 16 cells
-                               or more for F32, 128 or more for F64); otherwise the staged kernels */
+  LINCOLL_PATH_AUTO = 0,    /* the fused kernels where they exist (F32 and F64 at n = 16, 32), for any batch:
+                               batches smaller than the device's compute unit count are split over several
+                               workgroups per cell (LINCOLL_OPT_FUSED_SPLIT).  With splitting switched off
+                               (LINCOLL_OPT_FUSED_SPLIT = 1) or two pencils per thread, n = 32 takes the
+                               staged kernels below 16 cells (F32) or 128 cells (F64).  Otherwise (n = 8,
+                               64, BF16X3) the staged kernels */
   LINCOLL_PATH_STAGED = 1,  /* batched per-stage kernels (every n and dtype) */
-  LINCOLL_PATH_FUSED = 2    /* one persistent workgroup per cell (F32 and F64 at n = 16, 32) */
+  LINCOLL_PATH_FUSED = 2    /* persistent workgroups, one per cell or S per cell (LINCOLL_OPT_FUSED_SPLIT)
+                               (F32 and F64 at n = 16, 32) */
 } lincoll_path_t;
 
 typedef struct {
@@ -108,7 +112,10 @@ int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, results and argument checks as
  * lincoll_apply; the output is bitwise identical to lincoll_apply's on the
- * same plan.  It calls no hipMalloc, hipFree or other allocating routine and
+ * same plan when that apply runs one workgroup per cell (a batch of at
+ * least as many cells as the device has compute units, or
+ * LINCOLL_OPT_FUSED_SPLIT = 1); lincoll_apply splits smaller batches over
+ * several workgroups per cell, which agrees to rounding.  It calls no hipMalloc, hipFree or other allocating routine and
  * never records a graph: the fused kernel's per-workgroup scratch (the
  * spectrum of r and the L+ accumulator) lives in a fixed 96 MiB device array
  * of the library, one per GPU, held until the process ends, which limits
@@ -119,8 +126,8 @@ int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
  * time on one GPU (other streams, other plans, other threads) race and give
  * wrong results; serialise them.  Requirements beyond lincoll_apply's: the
  * plan's apply of this batch takes the fused path (LINCOLL_F32 or
- * LINCOLL_F64, n = 16 or 32, path FUSED, or AUTO with a batch at or above
- * AUTO's threshold), project = 0, the Maxwellians already set (lincoll_set_maxwellians
+ * LINCOLL_F64, n = 16 or 32, path FUSED or AUTO; see LINCOLL_PATH_AUTO),
+ * project = 0, the Maxwellians already set (lincoll_set_maxwellians
  * allocates), and the plan's device current; otherwise LINCOLL_EINVAL. */
 int lincoll_apply_noalloc(lincoll_plan_t plan, const void* h, void* out, int batch);
 
@@ -168,6 +175,8 @@ int quadcoll_apply(lincoll_plan_t plan, const void* f, void* out, int batch);
 #define LINCOLL_INFO_FUSED_KEEP 19   /* fused path: accumulator chunks kept in registers, in effect */
 #define LINCOLL_INFO_LAST_PATH 20    /* path the most recent apply (of any batch) took; 0 before the first.  Set
                                         when the launches are enqueued (or recorded into a graph) */
+#define LINCOLL_INFO_FUSED_SPLIT 21  /* workgroups per cell of the most recent apply: S > 1 when it took the
+                                        fused path split S ways (LINCOLL_OPT_FUSED_SPLIT), else 1 */
 /* Reads one plan property into *val.  With plan == NULL only
  * LINCOLL_INFO_HIP_ERROR is accepted: the last HIP error seen on this thread
  * (for a lincoll_plan/lincoll_plan_ex that failed with LINCOLL_EHIP). */
@@ -222,6 +231,17 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
                                          equal; F64 results agree to a few units in the last place (the compiler
                                          may contract the M^h product into the next addition differently in
                                          each compiled instance) */
+#define LINCOLL_OPT_FUSED_SPLIT 13    /* fused path, one pencil per thread: workgroups per cell.  The gain loop of
+                                         Algorithm 1 is partitioned: part p of a cell takes the nodes j = p, p + S,
+                                         ..., computes its own spectrum of r, and writes its partial sum of
+                                         Phi_j Q_j to the plan's work memory (part 0 also writes the loss term);
+                                         a second kernel adds the S parts in order and applies the final inverse
+                                         transform.  0 (default): by batch -- a batch with fewer cells than the
+                                         device has compute units is split into about (compute units / batch)
+                                         parts, at most J, so that small batches (one cell, a few dozen) use the
+                                         whole chip; 1: never split; S = 2..J: S parts.  Results agree with the
+                                         unsplit kernel to rounding (the gain sum is associated differently).
+                                         lincoll_apply_noalloc always runs unsplit */
 #define LINCOLL_OPT_QUAD_FIX 6        /* quadcoll: mass fix of Sec. 2.3 -- 0 none (default); 1 Q^_0 = 0 (eq. (15)),
                                          the per-cell mean of Q removed; 2 the sinc of the loss term replaced by
                                          its estimate on the hemisphere rule (eq. (16)), a [n]^3 FP64 table the
@@ -230,8 +250,10 @@ int lincoll_set_option(lincoll_plan_t plan, int key, int value);
 
 /* Launch-configuration tuner: times `reps` applies of every supported
  * configuration on the caller's h/out/batch (after one warm-up each): path;
- * on the fused path the workgroups per CU and the pencils per thread
- * (LINCOLL_OPT_FUSED_PPT); on the staged path the z-pass
+ * on the fused path the workgroups per CU, the pencils per thread
+ * (LINCOLL_OPT_FUSED_PPT), the accumulator split (LINCOLL_OPT_FUSED_KEEP)
+ * and, for a batch that AUTO splits, split or not (LINCOLL_OPT_FUSED_SPLIT
+ * 0 or 1); on the staged path the z-pass
  * block size (64, 128, 256) and the in-plane tile (LINCOLL_OPT_ZBLOCK,
  * LINCOLL_OPT_PLANE_TILE); graph replay on and off.  Keeps the fastest as the
  * plan's configuration, records its time (LINCOLL_INFO_TUNED_MS) and stores
@@ -239,7 +261,8 @@ int lincoll_set_option(lincoll_plan_t plan, int key, int value);
  * rounded up to a power of two, projection flag, per-cell or broadcast
  * Maxwellians); a later call with the same key takes the cached result
  * without timing (LINCOLL_INFO_TUNE_CACHED = 1) unless LINCOLL_OPT_TUNE_CACHE
- * is 0.  No configuration changes the arithmetic of a path.  Synchronises the
+ * is 0.  No configuration changes the arithmetic of a path beyond the
+ * association of sums (the split).  Synchronises the
  * plan's stream; out holds L[h] afterwards (after a cache hit it is not
  * written).  Same argument rules as lincoll_apply; reps in [1, 1000]. */
 int lincoll_autotune(lincoll_plan_t plan, const void* h, void* out, int batch, int reps);

@@ -60,6 +60,8 @@ struct lincoll_plan_s {
   int opt_graph = 0, opt_per_cu = 0;
   int opt_zblk = 128, opt_tile = 0, opt_tune_cache = 1, opt_ppt = 1;
   int opt_keep = -1;   // fused accumulator chunks kept in registers (-1: the default for n)
+  int opt_split = 0;   // fused workgroups per cell: 0 = by batch, 1 = never split, S = S parts
+  int last_split = 1;  // parts per cell of the most recent apply (LINCOLL_INFO_FUSED_SPLIT)
   double tuned_ms = 0.0;
   int tuned_cached = 0;
   int last_path = 0;          // path of the most recent apply (LINCOLL_INFO_LAST_PATH)
@@ -180,20 +182,31 @@ int fused_keep(const lincoll_plan_s* pl) {
   return fused_default_keep(pl->p.n, pl->p.dtype);
 }
 
-// Path of an apply of `batch` cells.  AUTO takes the fused kernel where it
-// exists and the batch fills enough of the chip for one cell per compute
-// unit to beat the staged kernels, which spread even one cell over many CUs
-// (measured on MI355X: at n = 16 from one cell; at n = 32 from 16 cells in
-// F32 and from 128 in F64).
-int fused_auto_min_batch(int n, int dtype) {
-  if (n == 16) return 1;
-  return dtype == LINCOLL_F64 ? 128 : 16;
+// Path of an apply of `batch` cells.  AUTO takes the fused kernels where
+// they exist.  Split over several workgroups per cell, they beat the staged
+// kernels from one cell on; with one workgroup per cell (splitting switched
+// off, or two pencils per thread) a small batch leaves most of the chip idle,
+// and the staged kernels, which spread even one cell over many CUs, are
+// faster at n = 32 below 16 cells in F32 and 128 in F64 (measured on MI355X).
+int fused_auto_min_batch(const lincoll_plan_s* pl) {
+  const bool can_split = pl->opt_ppt == 1 && pl->opt_split != 1;
+  if (pl->p.n == 16 || can_split) return 1;
+  return pl->p.dtype == LINCOLL_F64 ? 128 : 16;
 }
 
 bool use_fused(const lincoll_plan_s* pl, int batch) {
   if (pl->p.path == LINCOLL_PATH_STAGED) return false;
   if (pl->p.path == LINCOLL_PATH_FUSED) return true;
-  return fused_supported(pl->p.n, pl->p.dtype) && batch >= fused_auto_min_batch(pl->p.n, pl->p.dtype);
+  return fused_supported(pl->p.n, pl->p.dtype) && batch >= fused_auto_min_batch(pl);
+}
+
+// Workgroups per cell of a fused apply of `batch` cells: the plan's option,
+// else enough parts to spread a small batch over the chip (one workgroup per
+// cell once the batch fills it).  The two-pencil kernel does not split.
+int fused_split(const lincoll_plan_s* pl, int batch) {
+  if (pl->opt_ppt != 1 || pl->opt_split == 1) return 1;
+  if (pl->opt_split > 1) return std::min(pl->opt_split, pl->t.J);
+  return fused_auto_split(pl->t.J, batch, pl->cus);
 }
 
 // The batch a path query refers to: the Maxwellian batch when it is per
@@ -249,7 +262,10 @@ int ensure_work(lincoll_plan_t pl, int B) {
     pl->cap_pin = B;
   }
   if (use_fused(pl, B)) {
-    const size_t need = fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus), pl->opt_ppt, pl->p.dtype);
+    const int S = fused_split(pl, B);
+    const size_t need =
+        S > 1 ? fused_split_scratch_bytes(n, fused_slots(n, B * S, pl->opt_per_cu, pl->cus), B, S, pl->p.dtype)
+              : fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus), pl->opt_ppt, pl->p.dtype);
     if (need > pl->R_bytes || !pl->d_R) {
       pl->cap_work = 0;
       if ((e = dalloc(pl, &pl->d_R, need))) {
@@ -508,6 +524,7 @@ ApplyCtx apply_ctx(lincoll_plan_t pl, const void* hin, void* out, int batch, hip
   c.zblk = pl->opt_zblk;
   c.fused_ppt = pl->opt_ppt;
   c.fused_keep = fused_keep(pl);
+  c.fused_split = use_fused(pl, batch) ? fused_split(pl, batch) : 1;
   c.plane_tile = pl->opt_tile;
   c.dtype = pl->p.dtype;
   c.stream = stream;
@@ -544,6 +561,7 @@ hipError_t launch_apply(lincoll_plan_t pl, const void* h, void* out, int batch, 
   c.gate = gate;
   const bool fused = use_fused(pl, batch);
   pl->last_path = fused ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED;
+  pl->last_split = fused ? c.fused_split : 1;
   if ((e = fused ? fused_apply(c) : staged_apply(c))) return e;
   if (pl->p.project) return launch_project(pl, out, out, batch, stream, gate);
   return hipSuccess;
@@ -645,8 +663,10 @@ int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch
   ApplyCtx c = apply_ctx(pl, h, out, batch, pl->stream);
   c.R = scr;
   c.max_slots = (int)(bytes / slot);
+  c.fused_split = 1;   // one workgroup per cell: the array holds slots only
   if ((e = fused_apply(c))) return hip_fail(pl, e);
   pl->last_path = LINCOLL_PATH_FUSED;
+  pl->last_split = 1;
   return LINCOLL_OK;
 }
 
@@ -695,6 +715,10 @@ int lincoll_set_option(lincoll_plan_t pl, int key, int value) {
       if (value != -1 && !fused_keep_valid(pl->p.n, pl->p.dtype, value)) return LINCOLL_EINVAL;
       pl->opt_keep = value;
       break;
+    case LINCOLL_OPT_FUSED_SPLIT:
+      if (value < 0 || value > pl->t.J) return LINCOLL_EINVAL;
+      pl->opt_split = value;
+      break;
     case LINCOLL_OPT_TUNE_CACHE:
       if (value != 0 && value != 1) return LINCOLL_EINVAL;
       pl->opt_tune_cache = value;
@@ -721,7 +745,7 @@ namespace {
 // A launch configuration of the apply: path, fused workgroups per CU,
 // staged tile (z-pass block size, in-plane tile) and graph replay.
 struct Tuned {
-  int path, per_cu, zblk, tile, graph, ppt, keep;
+  int path, per_cu, zblk, tile, graph, ppt, keep, split;
   double ms;
 };
 
@@ -746,6 +770,7 @@ void apply_tuned(lincoll_plan_t pl, const Tuned& t) {
   pl->opt_graph = t.graph;
   pl->opt_ppt = t.ppt;
   pl->opt_keep = t.keep;
+  pl->opt_split = t.split;
   pl->tuned_ms = t.ms;
   drop_graph(pl);
 }
@@ -768,21 +793,26 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
   }
   std::vector<Tuned> cands;
   const int n = pl->p.n, dt = pl->p.dtype;
+  // workgroups per cell: the split chosen by batch, and (where that splits)
+  // one workgroup per cell
+  std::vector<int> splits{0};
+  if (fused_auto_split(pl->t.J, batch, pl->cus) > 1) splits.push_back(1);
   for (int g = 0; g < 2; ++g) {
     if (staged_supported(n, dt))
       for (int zb : {64, 128, 256})
         for (int tile = 0; tile <= (n <= 32 ? 1 : 0); ++tile)
-          cands.push_back({LINCOLL_PATH_STAGED, 0, zb, tile, g, 1, -1, 0.0});
+          cands.push_back({LINCOLL_PATH_STAGED, 0, zb, tile, g, 1, -1, 0, 0.0});
     if (fused_supported(n, dt))
       for (int pc = 1; pc <= fused_max_per_cu(n); ++pc) {
         for (int keep : {0, 4, 8, 16})
-          if (fused_keep_valid(n, dt, keep)) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 1, keep, 0.0});
-        if (dt == LINCOLL_F32) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 2, -1, 0.0});
+          if (fused_keep_valid(n, dt, keep))
+            for (int sp : splits) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 1, keep, sp, 0.0});
+        if (dt == LINCOLL_F32) cands.push_back({LINCOLL_PATH_FUSED, pc, 128, 0, g, 2, -1, 0, 0.0});
       }
   }
   if (cands.empty()) return LINCOLL_EINVAL;
   const Tuned saved{pl->p.path, pl->opt_per_cu, pl->opt_zblk, pl->opt_tile, pl->opt_graph, pl->opt_ppt, pl->opt_keep,
-                    pl->tuned_ms};
+                    pl->opt_split, pl->tuned_ms};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e;
   if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
@@ -1080,6 +1110,7 @@ int lincoll_get_info(lincoll_plan_t pl, int key, double* val) {
     case LINCOLL_INFO_FUSED_PPT: *val = pl->opt_ppt; break;
     case LINCOLL_INFO_FUSED_KEEP: *val = fused_keep(pl); break;
     case LINCOLL_INFO_LAST_PATH: *val = pl->last_path; break;
+    case LINCOLL_INFO_FUSED_SPLIT: *val = pl->last_split; break;
     default: return LINCOLL_EINVAL;
   }
   return LINCOLL_OK;

@@ -427,251 +427,88 @@ struct AccChunk<double> {   // one complex value
   }
 };
 
+template <typename TL>
+using Cplx = typename std::conditional<std::is_same<TL, float>::value, float2, double2>::type;
+
+// L+ = iDFT[L+^] from the Y-role pencils of one cell, added to out (Alg. 1,
+// the inverse transform of the gain sum and the combination with the loss).
+template <int NN, typename TL>
+__device__ __forceinline__ void gain_inverse_add(TL (&Lr)[NN], TL (&Li)[NN], float2* lds, int t, TL* out, int cell,
+                                                 int col1) {
+  constexpr int N = NN / 2, NP = NN * NN;
+  fft<NN, true>(Lr, Li);
+  exch_transpose<NN, TL>(Lr, Li, lds, t);
+  fft<NN, true>(Lr, Li);
+  exch_x_to_z<NN, TL>(Lr, Li, lds, t);
+  TL zr[NN], zi[NN];
+  z_inverse<NN, TL>(Lr, Li, zr, zi);
+  TL* o1 = out + ((size_t)cell * NP + col1) * NN;
+  TL* o2 = o1 + (size_t)N * NN;
+  static_for<0, NN>([&](auto z) {
+    o1[z] = o1[z] + zr[z];
+    o2[z] = o2[z] + zi[z];
+  });
+}
+
 }  // namespace
 
-// TL: the type of everything after the product with M^h and of h and L at
-// the boundary (float: F32 plans; double: F64 plans).
-// KA: chunks (two complex floats, or one complex double) of each thread's L+^
-// accumulator that stay in registers across the nodes; the next KL live in
-// LDS, the others stream through the slot.
+// The whole apply (Algorithm 1) for each cell of the batch, one workgroup
+// per cell at a time, persistent over cells (the body: fused_body.inc).
 template <int NN, int KA, typename TL>
 __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     const TL* __restrict__ h, TL* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
     const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
     const TL* __restrict__ nu, const TL* __restrict__ Phi, const TL* __restrict__ Om,
     double2* __restrict__ slots, int J, const int* __restrict__ gate) {
-  using C = Cfg<NN>;
-  using A = AccChunk<TL>;
-  using V = typename A::V;
   if (gate && *gate == 0) return;   // a gated-off step of the device-resident GMRES
-  constexpr int N = C::N, KP = C::KP, P = C::P, Q = C::Q, MW = C::MW, NP = NN * NN, PW = 64 / NN, LD = C::LD;
-  constexpr int NCH = NN / A::PER;   // accumulator chunks per thread
+  constexpr bool SPLIT = false;
+  constexpr int S = 1;
+  Cplx<TL>* const partial = nullptr;
+#include "fused_body.inc"
+}
+
+// The apply with each cell's J nodes split over S workgroups (for batches
+// too small to fill the chip one cell per workgroup).  Work item w is cell
+// w / S, part w % S; its partial gain sum goes to partial[w].
+template <int NN, int KA, typename TL>
+__global__ void __launch_bounds__(Cfg<NN>::T) k_fused_split(
+    const TL* __restrict__ h, TL* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
+    const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
+    const TL* __restrict__ nu, const TL* __restrict__ Phi, const TL* __restrict__ Om,
+    double2* __restrict__ slots, int J, int S, Cplx<TL>* __restrict__ partial, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  constexpr bool SPLIT = true;
+#include "fused_body.inc"
+}
+
+// Completes a split apply: the S partial gain sums of a cell, added in part
+// order, then L+ = iDFT[L+^] and out += L+.
+template <int NN, typename TL>
+__global__ void __launch_bounds__(Cfg<NN>::T) k_fused_finish(TL* __restrict__ out, int batch,
+                                                            const Cplx<TL>* __restrict__ partial, int S,
+                                                            const int* __restrict__ gate) {
+  using C = Cfg<NN>;
+  if (gate && *gate == 0) return;
   __shared__ __align__(16) float2 lds[C::LDS_BYTES / 8];
-  __shared__ double fs[9 * NN + 3];
-  __shared__ __align__(16) TL tab[Q];
-  // Accumulator chunks KA .. KA + KL - 1 live in LDS, each thread's own (the
-  // 16 KB left over at n = 32 beside the exchange volume and the tables).
-  constexpr int KL = (NN == 32 && KA < NCH) ? (NCH - KA < 2 ? NCH - KA : 2) : 0;
-  __shared__ V accl[KL > 0 ? KL : 1][KL > 0 ? C::T : 1];
-  const int t0 = threadIdx.x;
-  // Scratch slot of this workgroup: R (KP*NP complex double) then the L+
-  // accumulator (KP*NP complex TL).  Both are interleaved by thread
-  // (element i of thread t at i*T + t) so that each load or store
-  // instruction of a wave covers one contiguous segment.
-  double2* Rs = slots + (size_t)blockIdx.x * (KP * NP + KP * NP * sizeof(TL) / 8);
-  V* Ac = reinterpret_cast<V*>(Rs + KP * NP);
-
   for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
-    const int cc = Bc > 1 ? cell : 0;
-    // Per-thread addresses derive from t; keeping t opaque to the optimiser
-    // here stops it from hoisting dozens of them out of the loop (and
-    // spilling them); they are recomputed with a few integer operations.
-    int t = t0;
-    asm volatile("" : "+v"(t));
-    const int kp = t / NN, ia = t % NN;          // Y / X roles
-    const int zx = t / N, zyp = t % N;           // Z role
-    const int fx = ia <= N ? ia : NN - ia;
-    __syncthreads();
-    for (int i = t; i < 6 * NN; i += C::T) fs[i] = fac64[(size_t)cc * 6 * NN + i];
-    if (t < 2) fs[6 * NN + t] = pref64[2 * cc + t];
-    for (int q = t; q < Q; q += C::T) tab[q] = Om[q];
-    __syncthreads();
-    if constexpr (std::is_same<TL, float>::value) {
-      // reciprocal factors of M for r = chi h / M (infinite where a factor
-      // underflows; such points are outside the cutoff and never selected)
-      for (int i = t; i < 3 * NN; i += C::T) fs[6 * NN + 2 + i] = 1.0 / fs[i];
-      if (t == 0) fs[9 * NN + 2] = 1.0 / fs[6 * NN];
-      __syncthreads();
-    }
-    const double* ex = fs;
-    const double* eh = fs + 3 * NN;
-    const double prefM = fs[6 * NN], prefH = fs[6 * NN + 1];
-    const int col1 = zx * NN + zyp;
-    const TL* h1 = h + ((size_t)cell * NP + col1) * NN;
-    const TL* h2 = h1 + (size_t)N * NN;
-    const double mxy1 = prefM * ex[zx] * ex[NN + zyp], mxy2 = prefM * ex[zx] * ex[NN + zyp + N];
-    auto radial = [&](auto ky) {   // a radial table at (kx, ky) of this pencil's plane and of kz = N
-      constexpr int fy = ky <= N ? ky : NN - ky;
-      const int q = fx * fx + fy * fy;
-      if constexpr (std::is_same<TL, float>::value) return float2{tab[q + kp * kp], tab[q + N * N]};
-      else return double2{tab[q + kp * kp], tab[q + N * N]};
-    };
-
-    // ---------------- loss: U = iDFT[Omega DFT[h]] in TL ---------------------------
-    {
-      TL fr[NN], fi[NN];
-      {
-        TL zr[NN], zi[NN];
-        static_for<0, NN>([&](auto z) { zr[z] = h1[z]; zi[z] = h2[z]; });
-        z_forward<NN, TL>(zr, zi, fr, fi);
-      }
-      exch_z_to_x<NN, TL>(fr, fi, lds, t);
-      fft<NN, false>(fr, fi);
-      exch_transpose<NN, TL>(fr, fi, lds, t);
-      fft<NN, false>(fr, fi);
-      radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Omega(|k|^2) / n^3
-      fft<NN, true>(fr, fi);
-      exch_transpose<NN, TL>(fr, fi, lds, t);
-      fft<NN, true>(fr, fi);
-      exch_x_to_z<NN, TL>(fr, fi, lds, t);
-      TL zr[NN], zi[NN];
-      z_inverse<NN, TL>(fr, fi, zr, zi);
-      const TL* n1 = nu + ((size_t)cc * NP + col1) * NN;
-      const TL* n2 = n1 + (size_t)N * NN;
-      TL* o1 = out + ((size_t)cell * NP + col1) * NN;
-      TL* o2 = o1 + (size_t)N * NN;
-      static_for<0, NN>([&](auto z) {
-        const double ez = ex[2 * NN + z];
-        o1[z] = TL(-(mxy1 * ez) * double(zr[z]) - double(n1[z]) * double(h1[z]));
-        o2[z] = TL(-(mxy2 * ez) * double(zi[z]) - double(n2[z]) * double(h2[z]));
-      });
-    }
-    // ---------------- R = DFT[chi h / M]: double arithmetic, double result --------
-    {
-      double vr[NN], vi[NN];
-      {
-        const uint32_t* mk1 = mask + ((size_t)cc * NP + col1) * MW;
-        const uint32_t* mk2 = mk1 + (size_t)N * MW;
-        uint32_t b1[MW], b2[MW];
-        static_for<0, MW>([&](auto w) { b1[w] = mk1[w]; b2[w] = mk2[w]; });
-        // r = h / M.  F32 plans multiply by the product of the reciprocal
-        // factors; F64 plans divide by M (the product of its factors), which
-        // rounds fewer times: r is large where M is small, and the few ulps
-        // saved there are visible at FP64 precision (not at FP32).
-        double zr[NN], zi[NN];
-        if constexpr (std::is_same<TL, float>::value) {
-          const double* rx = fs + 6 * NN + 2;
-          const double rxy = fs[9 * NN + 2] * rx[zx];
-          const double r1 = rxy * rx[NN + zyp], r2 = rxy * rx[NN + zyp + N];
-          static_for<0, NN>([&](auto z) {
-            const double rz = rx[2 * NN + z];
-            const double q1 = double(h1[z]) * (r1 * rz), q2 = double(h2[z]) * (r2 * rz);
-            zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? q1 : 0.0;
-            zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? q2 : 0.0;
-          });
-        } else {
-          static_for<0, NN>([&](auto z) {
-            const double ez = ex[2 * NN + z];
-            const double q1 = double(h1[z]) / (mxy1 * ez), q2 = double(h2[z]) / (mxy2 * ez);
-            zr[z] = ((b1[z / 32] >> (z % 32)) & 1u) ? q1 : 0.0;
-            zi[z] = ((b2[z / 32] >> (z % 32)) & 1u) ? q2 : 0.0;
-          });
-        }
-        z_forward<NN, double>(zr, zi, vr, vi);
-      }
-      z_to_x_d<NN>(vr, vi, lds, t);
-      fft<NN, false>(vr, vi);
-      transpose_plane_d<NN>(vr, vi, lds, t);
-      fft<NN, false>(vr, vi);
-      static_for<0, NN>([&](auto ky) { Rs[ky * C::T + t] = double2{vr[ky], vi[ky]}; });
-    }
-    k_slice_dma<NN>(Kh + (size_t)cc * J * kh_stride(NN), lds, t);   // K_0 into this wave's region
-
-    // ---------------- gain loop ---------------------------------------------------
-    // The running sum of Phi_j Q_j: its first KA chunks stay in registers, the
-    // next KL in LDS, the others in the scratch slot between nodes (loaded back
-    // only during the TL part of a node, where registers are free); after
-    // the last node all of it is in registers.
+    const int t = threadIdx.x;
+    __syncthreads();   // the previous cell's exchange reads are done
     TL Lr[NN], Li[NN];
-    V keep[KA > 0 ? KA : 1];
-    static_for<0, KA>([&](auto c) { keep[c] = V{}; });
-    for (int j = 0; j < J; ++j) {
-      asm volatile("" : "+v"(t));
-      TL fr[NN], fi[NN];
-      {
-        double vr[NN], vi[NN];
-        static_for<0, NN>([&](auto ky) {
-          const double2 v = Rs[ky * C::T + t];
-          vr[ky] = v.x;
-          vi[ky] = v.y;
-        });
-        __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copy of K_j has landed
-        double* Kw = reinterpret_cast<double*>(lds + (t / 64) * PW * NN * LD);
-        const int kw = kp - (t / 64) * PW;
-        mode_multiply_d<NN>(vr, vi, t, Kw, [&](auto ky) {     // K_j / n^3
-          constexpr int fy = ky <= N ? ky : NN - ky;
-          return double2{Kw[(kw * P + fy) * P + fx], Kw[(PW * P + fy) * P + fx]};
-        });
-        fft<NN, true>(vr, vi);
-        transpose_plane_d<NN>(vr, vi, lds, t);
-        fft<NN, true>(vr, vi);
-        x_to_z_d<NN>(vr, vi, lds, t);
-        // Every wave has used Phi_{j-1} by now: stream Phi_j into LDS while
-        // the z stage runs.  It is complete and visible after the wait and
-        // first barrier of the next X <- Z exchange.
-        lds_dma(reinterpret_cast<const float*>(Phi + (size_t)j * phi_stride(NN)), reinterpret_cast<float*>(tab),
-                Q * int(sizeof(TL) / 4), t, C::T);
-        // psi on the two columns, times M^h; TL from here on.  M^h is a
-        // product of one factor per axis: the z factor multiplies each
-        // point, the column's constant x-y factor (g1, g2) scales the
-        // column's spectrum inside z_forward, in the multiply by 1/2 that
-        // separating the two real columns needs anyway.
-        double zr[NN], zi[NN];
-        z_inverse<NN, double>(vr, vi, zr, zi);
-        const double hx = prefH * eh[zx];
-        const double g1 = hx * eh[NN + zyp], g2 = hx * eh[NN + zyp + N];
-        TL qr[NN], qi[NN];
-        static_for<0, NN>([&](auto z) {
-          const double ez = eh[2 * NN + z];
-          qr[z] = TL(zr[z] * ez);
-          qi[z] = TL(zi[z] * ez);
-        });
-        z_forward<NN, TL>(qr, qi, fr, fi, TL(g1), TL(g2));
-      }
-      __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's table loads have landed
-      exch_z_to_x<NN, TL>(fr, fi, lds, t);
-      // Float chunks are loaded here, well ahead of their use (they fit beside
-      // the pencil); double chunks are loaded one at a time where they are added.
-      V acc[NCH];
-      if constexpr (std::is_same<TL, float>::value)
-        static_for<KA, NCH>([&](auto c) {
-          if constexpr (c < KA + KL) acc[c] = j > 0 ? accl[c - KA][t] : V{};
-          else acc[c] = j > 0 ? Ac[c * C::T + t] : V{};
-        });
-      fft<NN, false>(fr, fi);
-      exch_transpose<NN, TL>(fr, fi, lds, t);
-      // This wave is done with its region until the next node's K_j product;
-      // its transpose reads complete (lgkmcnt(0)) before the copy may land.
-      if (j + 1 < J) {
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        k_slice_dma<NN>(Kh + ((size_t)cc * J + j + 1) * kh_stride(NN), lds, t);
-      }
-      fft<NN, false>(fr, fi);
-      radial_multiply<NN, TL>(fr, fi, t, lds, radial);   // Phi_j / n^3
-      static_for<0, NCH>([&](auto c) {
-        V a;
-        if constexpr (c < KA) a = keep[c];
-        else if constexpr (std::is_same<TL, float>::value) a = acc[c];
-        else if constexpr (c < KA + KL) a = j > 0 ? accl[c - KA][t] : V{};
-        else a = j > 0 ? Ac[c * C::T + t] : V{};
-        static_for<0, A::PER>([&](auto q) {
-          constexpr int e = A::PER * c + q;
-          Lr[e] = A::re(a, q) + fr[e];
-          Li[e] = A::im(a, q) + fi[e];
-        });
-        if (j + 1 < J) {
-          const V v = A::template make<NN>(Lr, Li, c);
-          if constexpr (c < KA) keep[c] = v;
-          else if constexpr (c < KA + KL) accl[c - KA][t] = v;
-          else Ac[c * C::T + t] = v;
-        }
+    const Cplx<TL>* pp = partial + (size_t)cell * S * NN * C::T;
+    static_for<0, NN>([&](auto e) {
+      const Cplx<TL> v = pp[e * C::T + t];
+      Lr[e] = v.x;
+      Li[e] = v.y;
+    });
+    for (int p = 1; p < S; ++p) {
+      pp += (size_t)NN * C::T;
+      static_for<0, NN>([&](auto e) {
+        const Cplx<TL> v = pp[e * C::T + t];
+        Lr[e] += v.x;
+        Li[e] += v.y;
       });
     }
-    // ---------------- L+ = iDFT[L+^], out += L+ -------------------------------------
-    fft<NN, true>(Lr, Li);
-    exch_transpose<NN, TL>(Lr, Li, lds, t);
-    fft<NN, true>(Lr, Li);
-    exch_x_to_z<NN, TL>(Lr, Li, lds, t);
-    {
-      TL zr[NN], zi[NN];
-      z_inverse<NN, TL>(Lr, Li, zr, zi);
-      TL* o1 = out + ((size_t)cell * NP + col1) * NN;
-      TL* o2 = o1 + (size_t)N * NN;
-      static_for<0, NN>([&](auto z) {
-        o1[z] = o1[z] + zr[z];
-        o2[z] = o2[z] + zi[z];
-      });
-    }
+    gain_inverse_add<NN, TL>(Lr, Li, lds, t, out, cell, (t / (NN / 2)) * NN + t % (NN / 2));
   }
 }
 
@@ -1038,6 +875,26 @@ int fused_slots(int n, int batch, int per_cu, int cus) {
   return batch < slots ? batch : slots;
 }
 
+int fused_auto_split(int J, int batch, int cus) {
+  const int c = cus > 0 ? cus : 256;
+  if (batch <= 0 || batch >= c) return 1;
+  // at least two nodes per part: each part transforms r itself, about one
+  // node's work (measured on MI355X: one cell at n = 32 is fastest with 6 to
+  // 9 parts, not 17)
+  const int smax = (J + 1) / 2;
+  const int s = c / batch;
+  return s < 1 ? 1 : s > smax ? smax : s;
+}
+
+size_t fused_partial_offset(int n, int nslots, int dtype) {
+  return (fused_scratch_bytes(n, nslots, 1, dtype) + 255) / 256 * 256;
+}
+
+size_t fused_split_scratch_bytes(int n, int nslots, int batch, int S, int dtype) {
+  const size_t cplx = dtype == 0 ? sizeof(double2) : sizeof(float2);
+  return fused_partial_offset(n, nslots, dtype) + (size_t)batch * S * (n / 2) * n * n * cplx;
+}
+
 // Device address of `scratch` on `device`, looked up once per device with
 // that device current (the host-side name of a __device__ array is only a
 // stand-in, never a device address).
@@ -1084,6 +941,25 @@ void launch_fused(const ApplyCtx& c, int slots) {
       static_cast<const TL*>(c.Om), static_cast<double2*>(c.R), c.J, c.gate);
 }
 
+template <int NN, int KA, typename TL>
+void launch_fused_split(const ApplyCtx& c, int slots) {
+  const int S = c.fused_split;
+  Cplx<TL>* partial =
+      reinterpret_cast<Cplx<TL>*>(static_cast<char*>(c.R) + fused_partial_offset(NN, slots, c.dtype));
+  k_fused_split<NN, KA, TL><<<slots, Cfg<NN>::T, 0, c.stream>>>(
+      static_cast<const TL*>(c.h), static_cast<TL*>(c.out), c.batch, c.Bc, c.fac64, c.pref64, c.mask,
+      static_cast<const double*>(c.Kh), static_cast<const TL*>(c.nu), static_cast<const TL*>(c.Phi),
+      static_cast<const TL*>(c.Om), static_cast<double2*>(c.R), c.J, S, partial, c.gate);
+  const int cells = c.batch < c.cus * fused_max_per_cu(NN) ? c.batch : c.cus * fused_max_per_cu(NN);
+  k_fused_finish<NN, TL><<<cells, Cfg<NN>::T, 0, c.stream>>>(static_cast<TL*>(c.out), c.batch, partial, S, c.gate);
+}
+
+template <int NN, int KA, typename TL>
+void launch_fused_any(const ApplyCtx& c, int slots) {
+  if (c.fused_split > 1) launch_fused_split<NN, KA, TL>(c, slots);
+  else launch_fused<NN, KA, TL>(c, slots);
+}
+
 template <int NN>
 void launch_fused2(const ApplyCtx& c, int slots) {
   k_fused2<NN><<<slots, Cfg<NN>::T / 2, 0, c.stream>>>(
@@ -1095,33 +971,36 @@ void launch_fused2(const ApplyCtx& c, int slots) {
 }  // namespace
 
 hipError_t fused_apply(const ApplyCtx& c) {
-  int slots = fused_slots(c.n, c.batch, c.per_cu, c.cus);
-  if (c.max_slots > 0 && slots > c.max_slots) slots = c.max_slots;   // the kernel is persistent over cells
+  const int S = c.fused_split;
   if (!fused_supported(c.n, c.dtype) || !fused_keep_valid(c.n, c.dtype, c.fused_keep)) return hipErrorInvalidValue;
   if (c.fused_ppt == 2 && c.dtype != 1) return hipErrorInvalidValue;
+  if (S < 1 || S > c.J || (S > 1 && c.fused_ppt != 1)) return hipErrorInvalidValue;
+  // the kernels are persistent over their work items (cells, or cell parts)
+  int slots = fused_slots(c.n, S > 1 ? c.batch * S : c.batch, c.per_cu, c.cus);
+  if (c.max_slots > 0 && slots > c.max_slots) slots = c.max_slots;
   const int k = c.fused_keep;
   if (c.dtype == 1) {
     if (c.n == 16) {
       if (c.fused_ppt == 2) launch_fused2<16>(c, slots);
-      else if (k == 0) launch_fused<16, 0, float>(c, slots);
-      else if (k == 4) launch_fused<16, 4, float>(c, slots);
-      else launch_fused<16, 8, float>(c, slots);
+      else if (k == 0) launch_fused_any<16, 0, float>(c, slots);
+      else if (k == 4) launch_fused_any<16, 4, float>(c, slots);
+      else launch_fused_any<16, 8, float>(c, slots);
     } else {
       if (c.fused_ppt == 2) launch_fused2<32>(c, slots);
-      else if (k == 0) launch_fused<32, 0, float>(c, slots);
-      else if (k == 4) launch_fused<32, 4, float>(c, slots);
-      else if (k == 8) launch_fused<32, 8, float>(c, slots);
-      else launch_fused<32, 16, float>(c, slots);
+      else if (k == 0) launch_fused_any<32, 0, float>(c, slots);
+      else if (k == 4) launch_fused_any<32, 4, float>(c, slots);
+      else if (k == 8) launch_fused_any<32, 8, float>(c, slots);
+      else launch_fused_any<32, 16, float>(c, slots);
     }
   } else {
     if (c.n == 16) {
-      if (k == 0) launch_fused<16, 0, double>(c, slots);
-      else if (k == 8) launch_fused<16, 8, double>(c, slots);
-      else launch_fused<16, 16, double>(c, slots);
+      if (k == 0) launch_fused_any<16, 0, double>(c, slots);
+      else if (k == 8) launch_fused_any<16, 8, double>(c, slots);
+      else launch_fused_any<16, 16, double>(c, slots);
     } else {
-      if (k == 0) launch_fused<32, 0, double>(c, slots);
-      else if (k == 4) launch_fused<32, 4, double>(c, slots);
-      else launch_fused<32, 8, double>(c, slots);
+      if (k == 0) launch_fused_any<32, 0, double>(c, slots);
+      else if (k == 4) launch_fused_any<32, 4, double>(c, slots);
+      else launch_fused_any<32, 8, double>(c, slots);
     }
   }
   return hipGetLastError();

@@ -48,6 +48,7 @@ struct ApplyCtx {
   int max_slots = 0;           // fused path: cap on the persistent workgroups (0 = none)
   int fused_ppt = 1;           // fused path: pencils per thread (1: k_fused, 2: k_fused2)
   int fused_keep = 0;          // k_fused: accumulator chunks kept in registers (fused_keep_valid)
+  int fused_split = 1;         // fused path: workgroups per cell (1: k_fused; S > 1: k_fused_split, k_fused_finish)
   int zblk = 128;              // staged path: threads per block of the z-pass kernels (64, 128, 256)
   int plane_tile = 0;          // staged path: 0 = 64-thread in-plane blocks, 1 = 32-thread (n <= 32)
   const int* gate = nullptr;   // fused path: the kernel does nothing unless *gate != 0 (device flag)
@@ -163,5 +164,12 @@ int fused_default_keep(int n, int dtype);
 hipError_t fused_noalloc_scratch(int device, void** ptr, size_t* bytes);
 int fused_max_per_cu(int n);
 int fused_slots(int n, int batch, int per_cu, int cus);
+// Parts per cell that spread a batch over the chip (about one work item per
+// compute unit, at most (J + 1) / 2); 1 once the batch alone fills it.
+int fused_auto_split(int J, int batch, int cus);
+// Bytes of R a split apply needs: the slots of its workgroups, then the
+// partial gain sums of batch * S work items (256-byte aligned).
+size_t fused_split_scratch_bytes(int n, int nslots, int batch, int S, int dtype);
+size_t fused_partial_offset(int n, int nslots, int dtype);
 
 }  // namespace lincoll

@@ -20,14 +20,14 @@ TABLES = {"g": 0, "W": 1, "Phi": 2, "Omega": 3, "phi": 4}
 INFO = {"n": 0, "J": 1, "R": 2, "dtype": 3, "path": 4, "maxw_batch": 5, "device_bytes": 6,
         "hip_error": 7, "eps": 8, "graph": 9, "fused_per_cu": 10, "tuned_ms": 11, "L": 12, "project": 13,
         "quad_fix": 14, "zblock": 15, "plane_tile": 16, "tune_cached": 17, "fused_ppt": 18,
-        "fused_keep": 19, "last_path": 20}
+        "fused_keep": 19, "last_path": 20, "fused_split": 21}
 PRECONDS = {"none": 0, "sweep": 1, "learned": 2}
 INNERS = {"gmres": 0, "source": 1}
 MLP_IN, MLP_HIDDEN, MLP_OUT = 26, 128, 5
 MLP_WEIGHTS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 OPTIONS = {"graph": 0, "fused_per_cu": 1, "path": 2, "sphere_polar": 3, "sphere_azimuth": 4, "project": 5,
            "quad_fix": 6, "zblock": 7, "plane_tile": 8, "tune_cache": 9, "fused_ppt": 10,
-           "fused_keep": 11, "check_finite": 12}
+           "fused_keep": 11, "check_finite": 12, "fused_split": 13}
 SYMBOLS = ["lincoll_params_default", "lincoll_plan", "lincoll_plan_ex", "lincoll_set_stream",
            "lincoll_set_maxwellians", "lincoll_apply", "lincoll_project", "quadcoll_apply",
            "lincoll_get_info", "lincoll_destroy", "lincoll_strerror", "lincoll_plan_tables",

@@ -96,6 +96,7 @@ def test_last_path_follows_every_entry_point():
     n, L, om = 32, 8.0, 0.74
     staged, fused = lc.PATHS["staged"], lc.PATHS["fused"]
     plan = lc.Plan(n, L, om, "f32")
+    plan.set_option("fused_split", 1)        # as lincoll_apply_noalloc, so that the two agree bitwise
     assert plan.info("last_path") == 0
     _, params = mixed_inputs(n, L, 1, seed=811)
     plan.set_maxwellians(dev(params, torch.float64))
@@ -164,7 +165,9 @@ def test_fused_kept_accumulator_is_bitwise_identical(n, batch, dtype):
         keeps = [0, 4, 8] + ([16] if n == 32 else [])
     else:
         keeps = [0, 8, 16] if n == 16 else [0, 4, 8]
-    outs = [eager_result(n, L, om, dtype, "fused", hin, params, fused_keep=k) for k in keeps]
+    # one workgroup per cell, so that every accumulator chunk makes its trip
+    # across all J nodes (a split batch gives each part only a few)
+    outs = [eager_result(n, L, om, dtype, "fused", hin, params, fused_keep=k, fused_split=1) for k in keeps]
     for k, o in zip(keeps[1:], outs[1:]):
         if dtype == "f32":
             assert torch.equal(o, outs[0]), k

@@ -1,0 +1,145 @@
+"""The fused path with each cell's quadrature nodes split over several
+workgroups (LINCOLL_OPT_FUSED_SPLIT), through the C ABI.
+
+Part p of a cell takes the nodes j = p, p + S, ... of the gain loop of
+Algorithm 1; a second kernel adds the parts' partial sums of Phi_j Q_j in part
+order and applies the final inverse transform.  Checked here: every split
+against the oracle (FP64 at 1e-12, FP32 at 1e-5, both bars, including S = J
+with one node per part and a ragged last part), against the unsplit kernel
+(the same sum associated differently: agreement to rounding), the automatic
+choice by batch, a batch whose work items outnumber the persistent
+workgroups, graph replay (bitwise equal to the eager apply on every replay)
+and the option's argument checks."""
+import numpy as np
+import pytest
+
+from oracle import alg1, fast_direct as fd
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+lc = pytest.importorskip("paper_2503_09580_amd.lincoll")
+from test_gpu_parity import mixed_inputs  # noqa: E402
+from parity_util import check, check_batch  # noqa: E402
+
+DEV = torch.device("cuda:0")
+L, OM = 8.0, 0.74
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def tdtype(dtype):
+    return torch.float64 if dtype == "f64" else torch.float32
+
+
+def apply(n, dtype, h, params, split, **opts):
+    plan = lc.Plan(n, L, OM, dtype, path="fused")
+    plan.set_option("fused_split", split)
+    for k, v in opts.items():
+        plan.set_option(k, v)
+    plan.set_maxwellians(dev(params, torch.float64))
+    out = plan.apply(dev(h, tdtype(dtype)))
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy(), plan
+
+
+@pytest.mark.parametrize("n,dtype,batch,split", [(16, "f64", 1, 9), (16, "f64", 3, 2), (32, "f64", 1, 17),
+                                                 (32, "f64", 2, 5), (32, "f32", 1, 17), (32, "f32", 3, 4),
+                                                 (16, "f32", 5, 3)])
+def test_split_matches_oracle(n, dtype, batch, split):
+    """S = J: one node per part; J = 9 or 17 with S = 2, 4, 5: parts of
+    unequal length."""
+    h, params = mixed_inputs(n, L, batch, seed=3100 + 7 * n + batch + split)
+    if dtype == "f32":
+        h = h.astype(np.float32).astype(np.float64)
+    got, plan = apply(n, dtype, h, params, split)
+    assert plan.info("last_path") == lc.PATHS["fused"] and plan.info("fused_split") == split
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    cells = sorted({0, batch - 1})
+    ref = alg1.apply_batch(fd.make_plan(n, L, OM), h[cells], params[cells])
+    for i, b in enumerate(cells):
+        check(got[b], ref[i], tol, tag=(n, dtype, batch, split, b))
+
+
+@pytest.mark.parametrize("n,dtype", [(32, "f64"), (32, "f32"), (16, "f64"), (16, "f32")])
+def test_split_agrees_with_unsplit(n, dtype):
+    """The same gain sum, associated per part: FP64 to 1e-13, FP32 to 5e-6
+    of each cell's largest value (and l2)."""
+    J = n // 2 + 1
+    h, params = mixed_inputs(n, L, 6, seed=3200 + n)
+    ref, _ = apply(n, dtype, h, params, 1)
+    tol = 1e-13 if dtype == "f64" else 5e-6
+    for split in (2, 3, J - 1, J):
+        got, plan = apply(n, dtype, h, params, split)
+        assert plan.info("fused_split") == split
+        check_batch(got, ref, tol, tag=(n, dtype, split))
+
+
+def test_more_work_items_than_workgroups():
+    """150 cells split 2 ways at n = 32 are 300 work items for at most one
+    workgroup per compute unit: the persistent workgroups loop over items."""
+    n, dtype, B = 32, "f32", 150
+    h, params = mixed_inputs(n, L, B, seed=3300)
+    ref, _ = apply(n, dtype, h, params, 1)
+    got, plan = apply(n, dtype, h, params, 2)
+    assert plan.info("fused_split") == 2
+    check_batch(got, ref, 5e-6, tag="items > workgroups")
+    cells = [0, 77, B - 1]
+    oref = alg1.apply_batch(fd.make_plan(n, L, OM), h.astype(np.float32).astype(np.float64)[cells], params[cells])
+    for i, b in enumerate(cells):
+        check(got[b], oref[i], 1e-5, tag=b)
+
+
+def test_automatic_split_by_batch():
+    """Default option 0: about (compute units / batch) parts, at most
+    (J + 1) / 2 (two nodes per part), and none once the batch reaches the
+    compute unit count.  AUTO takes the fused path from one cell on."""
+    cus = torch.cuda.get_device_properties(DEV).multi_processor_count
+    n, J = 32, 17
+    plan = lc.Plan(n, L, OM, "f32")
+    _, params = mixed_inputs(n, L, 1, seed=3400)
+    plan.set_maxwellians(dev(params, torch.float64))   # one Maxwellian for every batch
+    for B in (1, 2, cus // 8, cus - 1, cus, cus + 5):
+        x = torch.zeros((B, n, n, n), dtype=torch.float32, device=DEV)
+        plan.apply(x)
+        want = 1 if B >= cus else max(1, min((J + 1) // 2, cus // B))
+        assert plan.info("last_path") == lc.PATHS["fused"], B
+        assert plan.info("fused_split") == want, (B, want)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,dtype,batch", [(32, "f32", 3), (16, "f64", 2)])
+def test_split_graph_replay_is_bitwise_eager(n, dtype, batch):
+    h, params = mixed_inputs(n, L, batch, seed=3500 + n)
+    ref, _ = apply(n, dtype, h, params, 0)
+    plan = lc.Plan(n, L, OM, dtype, path="fused")
+    plan.set_option("graph", 1)
+    plan.set_maxwellians(dev(params, torch.float64))
+    ht = dev(h, tdtype(dtype))
+    out = torch.empty_like(ht)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        plan.apply(ht, out)
+        torch.cuda.synchronize()
+        assert plan.info("fused_split") > 1
+        assert np.array_equal(out.double().cpu().numpy(), ref), rep
+        y = torch.randn(256, 256, device=DEV)
+        (y @ y).sum().item()     # unrelated eager work between replays
+
+
+def test_split_option_checks():
+    lib = lc.library()
+    plan = lc.Plan(32, L, OM, "f32")
+    key = lc.OPTIONS["fused_split"]
+    for bad in (-1, 18, 1000):
+        assert lib.lincoll_set_option(plan._h, key, bad) == lc.EINVAL
+    for good in (0, 1, 2, 17):
+        assert lib.lincoll_set_option(plan._h, key, good) == lc.OK
+    p16 = lc.Plan(16, L, OM, "f64")
+    assert lib.lincoll_set_option(p16._h, key, 10) == lc.EINVAL   # J = 9 at n = 16
+    assert lib.lincoll_set_option(p16._h, key, 9) == lc.OK

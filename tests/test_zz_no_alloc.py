@@ -35,6 +35,7 @@ def test_noalloc_matches_apply_twice(n, big, small, dtype):
     h, params = mixed_inputs(n, L, big, seed=2900 + n)
     # F64 at n = 32 takes the fused path under AUTO only from 128 cells on
     plan = lc.Plan(n, L, om, dtype, path="fused" if (dtype, n) == ("f64", 32) else "auto")
+    plan.set_option("fused_split", 1)   # lincoll_apply_noalloc runs one workgroup per cell
     assert plan.info("path") == 2
     td = torch.float32 if dtype == "f32" else torch.float64
     for B in (big, small):
@@ -77,7 +78,8 @@ def test_noalloc_rejects_unsupported_plans():
         assert lib.lincoll_apply_noalloc(plan._h, px, py, 2) == lc.EINVAL
     p64 = lc.Plan(n, L, om, "f64", path="staged")                     # not on the fused path
     assert lib.lincoll_apply_noalloc(p64._h, px, py, 2) == lc.EINVAL
-    p32 = lc.Plan(32, L, om, "f32")                                    # AUTO: two cells take the staged path
+    p32 = lc.Plan(32, L, om, "f32")                                    # AUTO without splitting: two cells
+    p32.set_option("fused_split", 1)                                   # take the staged path
     p32.set_maxwellians(torch.tensor([[1, 0, 0, 0, 1.0]] * 2, dtype=torch.float64, device=DEV))
     a32 = torch.zeros((2, 32, 32, 32), dtype=torch.float32, device=DEV)
     b32 = torch.zeros_like(a32)
