@@ -55,12 +55,12 @@ KERNEL_SOURCES = {
 }
 def fused_kernel_name(n, ppt, keep, dtype, split=1):
     """Name of the fused kernel instance a plan launches (as in the profiles);
-    a split apply is two launches."""
+    a split apply is three launches."""
     tl = "double" if dtype == "f64" else "float"
     if ppt == 2:
         return f"k_fused2<{n}>"
     if split > 1:
-        return f"k_fused_split<{n}, {keep}, {tl}> + k_fused_finish<{n}, {tl}>"
+        return f"k_fused_split<{n}, {keep}, {tl}> + k_fused_sum + k_fused_finish<{n}, {tl}>"
     return f"k_fused<{n}, {keep}, {tl}>"
 
 
@@ -634,8 +634,8 @@ def main():
                   "what": "lincoll_set_maxwellians for all cells (FP64 per-cell setup), untimed in value"},
     }
     # Roofline of the dominant kernel.  On the fused path a step is exactly one
-    # launch of the fused kernel on `stream` (two for a split apply: the parts,
-    # then the sum and inverse), so the event-timed step is that kernel's
+    # launch of the fused kernel on `stream` (three for a split apply: the
+    # parts, their sum, the inverse), so the event-timed step is that kernel's
     # average launch duration; the staged path is reported as a whole.
     fl = alg_flops_per_cell(n, J) * B
     by = alg_bytes_per_cell(n, elem) * B
@@ -648,7 +648,7 @@ def main():
                        "frac": achieved / PEAK_VALU_TFLOPS,
                        "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
                        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                       "kernel": kname, "launches_per_step": (2 if split > 1 else 1) if path == "fused" else None,
+                       "kernel": kname, "launches_per_step": (3 if split > 1 else 1) if path == "fused" else None,
                        "alg_flops_per_launch": fl, "alg_bytes_per_launch": by,
                        "hbm_GBs_compulsory": by / (ms_per_step / 1e3) / 1e9}
     if tr:

@@ -481,8 +481,30 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused_split(
 #include "fused_body.inc"
 }
 
-// Completes a split apply: the S partial gain sums of a cell, added in part
-// order, then L+ = iDFT[L+^] and out += L+.
+// Adds the S partial gain sums of each cell of a split apply, in part order,
+// into its part 0 (in place: element e of a cell is read and written by one
+// thread).  Spread over many workgroups, so that the sum reads the parts at
+// the chip's bandwidth rather than one workgroup's.
+template <typename T2>
+__global__ void __launch_bounds__(256) k_fused_sum(T2* __restrict__ partial, long per_item, int batch, int S,
+                                                   const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const long total = (long)batch * per_item;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long cell = i / per_item;
+    T2* base = partial + cell * S * per_item + (i - cell * per_item);
+    T2 acc = base[0];
+    for (int p = 1; p < S; ++p) {
+      const T2 v = base[p * per_item];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    base[0] = acc;
+  }
+}
+
+// Completes a split apply: from each cell's summed gain spectrum (its part 0
+// after k_fused_sum), L+ = iDFT[L+^] and out += L+.
 template <int NN, typename TL>
 __global__ void __launch_bounds__(Cfg<NN>::T) k_fused_finish(TL* __restrict__ out, int batch,
                                                             const Cplx<TL>* __restrict__ partial, int S,
@@ -500,14 +522,6 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused_finish(TL* __restrict__ ou
       Lr[e] = v.x;
       Li[e] = v.y;
     });
-    for (int p = 1; p < S; ++p) {
-      pp += (size_t)NN * C::T;
-      static_for<0, NN>([&](auto e) {
-        const Cplx<TL> v = pp[e * C::T + t];
-        Lr[e] += v.x;
-        Li[e] += v.y;
-      });
-    }
     gain_inverse_add<NN, TL>(Lr, Li, lds, t, out, cell, (t / (NN / 2)) * NN + t % (NN / 2));
   }
 }
@@ -878,12 +892,14 @@ int fused_slots(int n, int batch, int per_cu, int cus) {
 int fused_auto_split(int J, int batch, int cus) {
   const int c = cus > 0 ? cus : 256;
   if (batch <= 0 || batch >= c) return 1;
-  // at least two nodes per part: each part transforms r itself, about one
-  // node's work (measured on MI355X: one cell at n = 32 is fastest with 6 to
-  // 9 parts, not 17)
-  const int smax = (J + 1) / 2;
-  const int s = c / batch;
-  return s < 1 ? 1 : s > smax ? smax : s;
+  // The apply takes as long as its longest part, ceil(J / S) nodes: with at
+  // most c / batch parts per cell (one work item per compute unit), take the
+  // fewest parts that reach the shortest longest part (measured on MI355X:
+  // 16 cells at n = 32 run faster in 9 parts of at most 2 nodes than in 16).
+  const int smax = c / batch < J ? c / batch : J;
+  if (smax <= 1) return 1;
+  const int per = (J + smax - 1) / smax;
+  return (J + per - 1) / per;
 }
 
 size_t fused_partial_offset(int n, int nslots, int dtype) {
@@ -950,6 +966,10 @@ void launch_fused_split(const ApplyCtx& c, int slots) {
       static_cast<const TL*>(c.h), static_cast<TL*>(c.out), c.batch, c.Bc, c.fac64, c.pref64, c.mask,
       static_cast<const double*>(c.Kh), static_cast<const TL*>(c.nu), static_cast<const TL*>(c.Phi),
       static_cast<const TL*>(c.Om), static_cast<double2*>(c.R), c.J, S, partial, c.gate);
+  const long per_item = (long)NN * Cfg<NN>::T;
+  const long blocks = ((long)c.batch * per_item + 255) / 256;
+  const int sum_grid = (int)(blocks < 8L * c.cus ? blocks : 8L * c.cus);
+  k_fused_sum<Cplx<TL>><<<sum_grid, 256, 0, c.stream>>>(partial, per_item, c.batch, S, c.gate);
   const int cells = c.batch < c.cus * fused_max_per_cu(NN) ? c.batch : c.cus * fused_max_per_cu(NN);
   k_fused_finish<NN, TL><<<cells, Cfg<NN>::T, 0, c.stream>>>(static_cast<TL*>(c.out), c.batch, partial, S, c.gate);
 }

@@ -96,9 +96,9 @@ def test_more_work_items_than_workgroups():
 
 
 def test_automatic_split_by_batch():
-    """Default option 0: about (compute units / batch) parts, at most
-    (J + 1) / 2 (two nodes per part), and none once the batch reaches the
-    compute unit count.  AUTO takes the fused path from one cell on."""
+    """Default option 0: at most (compute units / batch) and J parts, the
+    fewest with the shortest longest part, and none once the batch reaches
+    the compute unit count.  AUTO takes the fused path from one cell on."""
     cus = torch.cuda.get_device_properties(DEV).multi_processor_count
     n, J = 32, 17
     plan = lc.Plan(n, L, OM, "f32")
@@ -107,7 +107,9 @@ def test_automatic_split_by_batch():
     for B in (1, 2, cus // 8, cus - 1, cus, cus + 5):
         x = torch.zeros((B, n, n, n), dtype=torch.float32, device=DEV)
         plan.apply(x)
-        want = 1 if B >= cus else max(1, min((J + 1) // 2, cus // B))
+        smax = min(J, cus // B)
+        per = -(-J // smax) if smax > 1 else J
+        want = 1 if B >= cus or smax <= 1 else -(-J // per)
         assert plan.info("last_path") == lc.PATHS["fused"], B
         assert plan.info("fused_split") == want, (B, want)
     torch.cuda.synchronize()
