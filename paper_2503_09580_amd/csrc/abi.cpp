@@ -264,7 +264,9 @@ int ensure_work(lincoll_plan_t pl, int B) {
   if (use_fused(pl, B)) {
     const int S = fused_split(pl, B);
     const size_t need =
-        S > 1 ? fused_split_scratch_bytes(n, fused_slots(n, B * S, pl->opt_per_cu, pl->cus), B, S, pl->p.dtype)
+        S > 1 ? fused_split_scratch_bytes(n, fused_slots(n, B * (S + fused_loss_item(n, B, S, pl->cus)), pl->opt_per_cu,
+                                                      pl->cus),
+                                          B, S, pl->p.dtype)
               : fused_scratch_bytes(n, fused_slots(n, B, pl->opt_per_cu, pl->cus), pl->opt_ppt, pl->p.dtype);
     if (need > pl->R_bytes || !pl->d_R) {
       pl->cap_work = 0;

@@ -462,20 +462,22 @@ __global__ void __launch_bounds__(Cfg<NN>::T) k_fused(
     double2* __restrict__ slots, int J, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;   // a gated-off step of the device-resident GMRES
   constexpr bool SPLIT = false;
-  constexpr int S = 1;
+  constexpr int S = 1, LI = 0;
   Cplx<TL>* const partial = nullptr;
 #include "fused_body.inc"
 }
 
 // The apply with each cell's J nodes split over S workgroups (for batches
-// too small to fill the chip one cell per workgroup).  Work item w is cell
-// w / S, part w % S; its partial gain sum goes to partial[w].
+// too small to fill the chip one cell per workgroup).  Work item w is part
+// w % (S + LI) of cell w / (S + LI); part p < S writes its partial gain sum to
+// partial[cell S + p]; with LI = 1, part S computes the loss term alone.
 template <int NN, int KA, typename TL>
 __global__ void __launch_bounds__(Cfg<NN>::T) k_fused_split(
     const TL* __restrict__ h, TL* __restrict__ out, int batch, int Bc, const double* __restrict__ fac64,
     const double* __restrict__ pref64, const uint32_t* __restrict__ mask, const double* __restrict__ Kh,
     const TL* __restrict__ nu, const TL* __restrict__ Phi, const TL* __restrict__ Om,
-    double2* __restrict__ slots, int J, int S, Cplx<TL>* __restrict__ partial, const int* __restrict__ gate) {
+    double2* __restrict__ slots, int J, int S, int LI, Cplx<TL>* __restrict__ partial,
+    const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   constexpr bool SPLIT = true;
 #include "fused_body.inc"
@@ -892,14 +894,22 @@ int fused_slots(int n, int batch, int per_cu, int cus) {
 int fused_auto_split(int J, int batch, int cus) {
   const int c = cus > 0 ? cus : 256;
   if (batch <= 0 || batch >= c) return 1;
-  // The apply takes as long as its longest part, ceil(J / S) nodes: with at
-  // most c / batch parts per cell (one work item per compute unit), take the
-  // fewest parts that reach the shortest longest part (measured on MI355X:
-  // 16 cells at n = 32 run faster in 9 parts of at most 2 nodes than in 16).
-  const int smax = c / batch < J ? c / batch : J;
+  // At most one work item per compute unit: c / batch per cell, one of them
+  // kept for the loss term where that leaves two parts or more (the loss then
+  // runs beside the gain parts instead of before part 0's).  The apply takes
+  // as long as its longest part, ceil(J / S) nodes: take the fewest parts
+  // that reach the shortest longest part (measured on MI355X: 16 cells at
+  // n = 32 run faster in 9 parts of at most 2 nodes than in 15; 64 cells in
+  // 3 parts and the loss than in 4 parts without).
+  int smax = c / batch - 1 >= 2 ? c / batch - 1 : c / batch;
+  if (smax > J) smax = J;
   if (smax <= 1) return 1;
   const int per = (J + smax - 1) / smax;
   return (J + per - 1) / per;
+}
+
+int fused_loss_item(int n, int batch, int S, int cus) {
+  return S > 1 && (long)batch * (S + 1) <= (long)(cus > 0 ? cus : 256) * fused_max_per_cu(n) ? 1 : 0;
 }
 
 size_t fused_partial_offset(int n, int nslots, int dtype) {
@@ -965,7 +975,8 @@ void launch_fused_split(const ApplyCtx& c, int slots) {
   k_fused_split<NN, KA, TL><<<slots, Cfg<NN>::T, 0, c.stream>>>(
       static_cast<const TL*>(c.h), static_cast<TL*>(c.out), c.batch, c.Bc, c.fac64, c.pref64, c.mask,
       static_cast<const double*>(c.Kh), static_cast<const TL*>(c.nu), static_cast<const TL*>(c.Phi),
-      static_cast<const TL*>(c.Om), static_cast<double2*>(c.R), c.J, S, partial, c.gate);
+      static_cast<const TL*>(c.Om), static_cast<double2*>(c.R), c.J, S, fused_loss_item(NN, c.batch, S, c.cus),
+      partial, c.gate);
   const long per_item = (long)NN * Cfg<NN>::T;
   const long blocks = ((long)c.batch * per_item + 255) / 256;
   const int sum_grid = (int)(blocks < 8L * c.cus ? blocks : 8L * c.cus);
@@ -996,7 +1007,8 @@ hipError_t fused_apply(const ApplyCtx& c) {
   if (c.fused_ppt == 2 && c.dtype != 1) return hipErrorInvalidValue;
   if (S < 1 || S > c.J || (S > 1 && c.fused_ppt != 1)) return hipErrorInvalidValue;
   // the kernels are persistent over their work items (cells, or cell parts)
-  int slots = fused_slots(c.n, S > 1 ? c.batch * S : c.batch, c.per_cu, c.cus);
+  int slots = fused_slots(c.n, S > 1 ? c.batch * (S + fused_loss_item(c.n, c.batch, S, c.cus)) : c.batch, c.per_cu,
+                          c.cus);
   if (c.max_slots > 0 && slots > c.max_slots) slots = c.max_slots;
   const int k = c.fused_keep;
   if (c.dtype == 1) {

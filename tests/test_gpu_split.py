@@ -96,9 +96,10 @@ def test_more_work_items_than_workgroups():
 
 
 def test_automatic_split_by_batch():
-    """Default option 0: at most (compute units / batch) and J parts, the
-    fewest with the shortest longest part, and none once the batch reaches
-    the compute unit count.  AUTO takes the fused path from one cell on."""
+    """Default option 0: at most J parts and (compute units / batch) work
+    items per cell, one kept for the loss where two parts remain; the fewest
+    parts with the shortest longest part; none once the batch reaches the
+    compute unit count.  AUTO takes the fused path from one cell on."""
     cus = torch.cuda.get_device_properties(DEV).multi_processor_count
     n, J = 32, 17
     plan = lc.Plan(n, L, OM, "f32")
@@ -107,7 +108,7 @@ def test_automatic_split_by_batch():
     for B in (1, 2, cus // 8, cus - 1, cus, cus + 5):
         x = torch.zeros((B, n, n, n), dtype=torch.float32, device=DEV)
         plan.apply(x)
-        smax = min(J, cus // B)
+        smax = min(J, cus // B - 1 if cus // B - 1 >= 2 else cus // B)
         per = -(-J // smax) if smax > 1 else J
         want = 1 if B >= cus or smax <= 1 else -(-J // per)
         assert plan.info("last_path") == lc.PATHS["fused"], B
