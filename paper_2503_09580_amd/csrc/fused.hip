@@ -1,6 +1,10 @@
 // Fused persistent kernel: one workgroup per cell (looping over cells) runs
 // all of Algorithm 1 on chip; only the FP64 spectrum of r streams from a
-// per-workgroup scratch slot, once per quadrature node.
+// per-workgroup scratch slot, once per quadrature node.  For batches too
+// small to fill the chip, k_fused_split runs the same body with each cell's
+// quadrature nodes partitioned over several workgroups (and the loss term in
+// a work item of its own where the chip has room); k_fused_sum adds the
+// partial gain sums and k_fused_finish applies the last inverse transform.
 //
 // Grid-of-pencils layout for n = NN points per axis (N = NN/2, KP = N packed
 // z-planes, NN*N threads).  The real transform along z packs the real bins
