@@ -274,7 +274,10 @@ class Plan:
         return y
 
     def set_option(self, key, value):
-        """key: "graph" (0|1), "fused_per_cu" (0 = default), "path" ("auto"|"staged"|"fused")."""
+        """lincoll_set_option: key is a name in OPTIONS (the LINCOLL_OPT_* of
+        include/lincoll.h, e.g. "graph" 0|1, "fused_per_cu", "fused_keep",
+        "fused_split" 0 = by batch | 1 = never | S parts); "path" takes
+        "auto" | "staged" | "fused"."""
         v = PATHS[value] if key == "path" else int(value)
         _check(_lib.lincoll_set_option(self._h, OPTIONS[key], v), "lincoll_set_option")
 
@@ -377,6 +380,8 @@ class Plan:
         return out
 
     def info(self, key):
+        """lincoll_get_info: key is a name in INFO (the LINCOLL_INFO_* of
+        include/lincoll.h, e.g. "path", "last_path", "fused_split")."""
         v = ctypes.c_double()
         _check(_lib.lincoll_get_info(self._h, INFO[key], ctypes.byref(v)), "lincoll_get_info")
         return v.value
