@@ -238,13 +238,14 @@ int lincoll_get_info(lincoll_plan_t plan, int key, double* val);
                                          two more kernels add the S parts in order and apply the final inverse
                                          transform.  Where the chip holds S + 1 work items per cell at once,
                                          the loss term gets an item of its own and runs beside the gain parts.
-                                         0 (default): by batch -- a batch with fewer cells than the device has
-                                         compute units is split into at most J parts and at most (compute units /
-                                         batch) work items per cell, one kept for the loss where that leaves two
-                                         parts: the fewest parts whose longest part has the fewest nodes (one
-                                         cell at n = 32: 17 parts; 16 cells: 9 parts of at most 2 nodes; 64
-                                         cells: 3 parts), so that small batches use the whole chip; 1: never
-                                         split; S = 2..J: S parts.  Results agree with the
+                                         0 (default): by batch -- a batch with fewer cells than the device holds
+                                         workgroups at once (one per compute unit at n = 32, four at n = 16) is
+                                         split into at most J parts and at most (resident workgroups / batch)
+                                         work items per cell, one kept for the loss where that leaves two parts:
+                                         the fewest parts whose longest part has the fewest nodes (one cell at
+                                         n = 32: 17 parts; 16 cells: 9 parts of at most 2 nodes; 64 cells: 3
+                                         parts), so that small batches use the whole chip; 1: never split;
+                                         S = 2..J: S parts.  Results agree with the
                                          unsplit kernel to rounding (the gain sum is associated differently).
                                          lincoll_apply_noalloc always runs unsplit */
 #define LINCOLL_OPT_QUAD_FIX 6        /* quadcoll: mass fix of Sec. 2.3 -- 0 none (default); 1 Q^_0 = 0 (eq. (15)),

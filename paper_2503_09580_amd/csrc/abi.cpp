@@ -206,7 +206,7 @@ bool use_fused(const lincoll_plan_s* pl, int batch) {
 int fused_split(const lincoll_plan_s* pl, int batch) {
   if (pl->opt_ppt != 1 || pl->opt_split == 1) return 1;
   if (pl->opt_split > 1) return std::min(pl->opt_split, pl->t.J);
-  return fused_auto_split(pl->t.J, batch, pl->cus);
+  return fused_auto_split(pl->p.n, pl->t.J, batch, pl->cus);
 }
 
 // The batch a path query refers to: the Maxwellian batch when it is per
@@ -798,7 +798,7 @@ int lincoll_autotune(lincoll_plan_t pl, const void* h, void* out, int batch, int
   // workgroups per cell: the split chosen by batch, and (where that splits)
   // one workgroup per cell
   std::vector<int> splits{0};
-  if (fused_auto_split(pl->t.J, batch, pl->cus) > 1) splits.push_back(1);
+  if (fused_auto_split(n, pl->t.J, batch, pl->cus) > 1) splits.push_back(1);
   for (int g = 0; g < 2; ++g) {
     if (staged_supported(n, dt))
       for (int zb : {64, 128, 256})

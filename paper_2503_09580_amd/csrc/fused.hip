@@ -895,17 +895,21 @@ int fused_slots(int n, int batch, int per_cu, int cus) {
   return batch < slots ? batch : slots;
 }
 
-int fused_auto_split(int J, int batch, int cus) {
-  const int c = cus > 0 ? cus : 256;
+int fused_auto_split(int n, int J, int batch, int cus) {
+  const int cu = cus > 0 ? cus : 256;
+  const int c = cu * fused_max_per_cu(n);   // workgroups resident at once
   if (batch <= 0 || batch >= c) return 1;
-  // At most one work item per compute unit: c / batch per cell, one of them
-  // kept for the loss term where that leaves two parts or more (the loss then
-  // runs beside the gain parts instead of before part 0's).  The apply takes
-  // as long as its longest part, ceil(J / S) nodes: take the fewest parts
-  // that reach the shortest longest part (measured on MI355X: 16 cells at
-  // n = 32 run faster in 9 parts of at most 2 nodes than in 15; 64 cells in
-  // 3 parts and the loss than in 4 parts without).
-  int smax = c / batch - 1 >= 2 ? c / batch - 1 : c / batch;
+  // At most one work item per resident workgroup: c / batch per cell, one of
+  // them kept for the loss term where that leaves two parts or more (the
+  // loss then runs beside the gain parts instead of before part 0's); two
+  // parts without it only while that is still one item per compute unit.
+  // The apply takes as long as its longest part, ceil(J / S) nodes: take the
+  // fewest parts that reach the shortest longest part (measured on MI355X:
+  // 16 cells at n = 32 run faster in 9 parts of at most 2 nodes than in 15;
+  // 64 cells in 3 parts and the loss than in 4 parts without; 512 cells at
+  // n = 16 unsplit).
+  int smax = c / batch - 1;
+  if (smax < 2) smax = 2 * batch <= cu ? 2 : 1;
   if (smax > J) smax = J;
   if (smax <= 1) return 1;
   const int per = (J + smax - 1) / smax;

@@ -164,11 +164,11 @@ int fused_default_keep(int n, int dtype);
 hipError_t fused_noalloc_scratch(int device, void** ptr, size_t* bytes);
 int fused_max_per_cu(int n);
 int fused_slots(int n, int batch, int per_cu, int cus);
-// Parts per cell that spread a batch over the chip (at most one work item per
-// compute unit, one of a cell's kept for its loss term where possible, and J
-// parts; the fewest parts with the shortest longest part); 1 once the batch
-// alone fills it.
-int fused_auto_split(int J, int batch, int cus);
+// Parts per cell that spread a batch of n-point cells over the chip (at most
+// one work item per resident workgroup, one of a cell's kept for its loss
+// term where possible, and J parts; the fewest parts with the shortest
+// longest part); 1 once the batch alone fills it.
+int fused_auto_split(int n, int J, int batch, int cus);
 // Bytes of R a split apply needs: the slots of its workgroups, then the
 // partial gain sums of batch * S work items (256-byte aligned).
 size_t fused_split_scratch_bytes(int n, int nslots, int batch, int S, int dtype);

@@ -95,22 +95,29 @@ def test_more_work_items_than_workgroups():
         check(got[b], oref[i], 1e-5, tag=b)
 
 
-def test_automatic_split_by_batch():
-    """Default option 0: at most J parts and (compute units / batch) work
-    items per cell, one kept for the loss where two parts remain; the fewest
-    parts with the shortest longest part; none once the batch reaches the
-    compute unit count.  AUTO takes the fused path from one cell on."""
+@pytest.mark.parametrize("n", [32, 16])
+def test_automatic_split_by_batch(n):
+    """Default option 0: at most J parts and (resident workgroups / batch)
+    work items per cell (one workgroup per CU at n = 32, four at n = 16), one
+    kept for the loss where two parts remain, else two parts while that is
+    one item per CU; the fewest parts with the shortest longest part; none
+    once the batch reaches the resident workgroup count.  AUTO takes the
+    fused path from one cell on."""
     cus = torch.cuda.get_device_properties(DEV).multi_processor_count
-    n, J = 32, 17
+    J = n // 2 + 1
+    c = cus * (4 if n == 16 else 1)
     plan = lc.Plan(n, L, OM, "f32")
     _, params = mixed_inputs(n, L, 1, seed=3400)
     plan.set_maxwellians(dev(params, torch.float64))   # one Maxwellian for every batch
-    for B in (1, 2, cus // 8, cus - 1, cus, cus + 5):
+    batches = (1, 2, cus // 8, cus - 1, cus, cus + 5) if n == 32 else (1, 64, 128, 256, 512, c)
+    for B in batches:
         x = torch.zeros((B, n, n, n), dtype=torch.float32, device=DEV)
         plan.apply(x)
-        smax = min(J, cus // B - 1 if cus // B - 1 >= 2 else cus // B)
-        per = -(-J // smax) if smax > 1 else J
-        want = 1 if B >= cus or smax <= 1 else -(-J // per)
+        smax = c // B - 1
+        if smax < 2:
+            smax = 2 if 2 * B <= cus else 1
+        smax = min(J, smax)
+        want = 1 if B >= c or smax <= 1 else -(-J // -(-J // smax))
         assert plan.info("last_path") == lc.PATHS["fused"], B
         assert plan.info("fused_split") == want, (B, want)
     torch.cuda.synchronize()
