@@ -646,6 +646,7 @@ int lincoll_apply(lincoll_plan_t pl, const void* h, void* out, int batch) {
   if (!same && (e = capture_apply(pl, h, out, batch, key))) return hip_fail(pl, e);
   if ((e = hipGraphLaunch(pl->gexec, pl->stream))) return hip_fail(pl, e);
   pl->last_path = key.fused ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED;
+  pl->last_split = key.fused ? fused_split(pl, batch) : 1;
   return check_output(pl, out, batch);
 }
 
@@ -1028,7 +1029,10 @@ int lincoll_rk4(lincoll_plan_t pl, void* f, int batch, double dt, int steps) {
   }
   for (int i = 0; i < steps; ++i)
     if ((e = hipGraphLaunch(pl->rk_gexec, pl->stream))) return hip_fail(pl, e);
-  if (steps > 0) pl->last_path = key.fused ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED;
+  if (steps > 0) {
+    pl->last_path = key.fused ? LINCOLL_PATH_FUSED : LINCOLL_PATH_STAGED;
+    pl->last_split = key.fused ? fused_split(pl, batch) : 1;
+  }
   return LINCOLL_OK;
 }
 

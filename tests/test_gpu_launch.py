@@ -121,6 +121,16 @@ def test_last_path_follows_every_entry_point():
     torch.cuda.synchronize()
     assert torch.equal(out.cpu(), out2.cpu())
     assert torch.isfinite(f).all()
+    # the split: a replay reports the split of its own batch
+    plan.set_option("fused_split", 0)        # by batch again (drops the recorded graphs)
+    plan.apply(big, out)                     # records: 16 cells split
+    split16 = plan.info("fused_split")
+    assert split16 > 1
+    plan.apply_noalloc(big, out2)            # one workgroup per cell
+    assert plan.info("fused_split") == 1
+    plan.apply(big, out)                     # replays
+    assert plan.info("fused_split") == split16
+    torch.cuda.synchronize()
 
 
 def test_graph_rerecords_after_reallocation():
