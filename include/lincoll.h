@@ -111,17 +111,19 @@ int lincoll_apply(lincoll_plan_t plan, const void* h, void* out, int batch);
 /* lincoll_apply without any allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, results and argument checks as
- * lincoll_apply; the output is bitwise identical to lincoll_apply's on the
- * same plan when that apply runs one workgroup per cell (a batch of at
- * least as many cells as the device has compute units, or
- * LINCOLL_OPT_FUSED_SPLIT = 1); lincoll_apply splits smaller batches over
- * several workgroups per cell, which agrees to rounding.  It calls no hipMalloc, hipFree or other allocating routine and
- * never records a graph: the fused kernel's per-workgroup scratch (the
- * spectrum of r and the L+ accumulator) lives in a fixed 96 MiB device array
- * of the library, one per GPU, held until the process ends, which limits
- * the persistent workgroups to 256 at n = 32 and 1024 at n = 16 for F32
- * plans, 192 and 1536 for F64 (whose accumulator is double); any batch is
- * processed, the workgroups loop over cells.  Nothing in that array needs
+ * lincoll_apply.  A batch that the plan splits over several workgroups per
+ * cell (LINCOLL_OPT_FUSED_SPLIT) is split the same way when its slots and
+ * partial sums fit the array (one cell at n = 32 needs about 10 MiB); the
+ * output is then bitwise identical to lincoll_apply's on the same plan, as
+ * it is for an unsplit batch.  A split batch that does not fit runs one
+ * workgroup per cell and agrees with lincoll_apply to rounding.  It calls no
+ * hipMalloc, hipFree or other allocating routine and never records a
+ * graph: the fused kernels' per-workgroup scratch (the spectrum of r and the
+ * L+ accumulator) and a split's partial sums live in a fixed 96 MiB device
+ * array of the library, one per GPU, held until the process ends, which
+ * limits the persistent workgroups to 256 at n = 32 and 1024 at n = 16 for
+ * F32 plans, 192 and 1536 for F64 (whose accumulator is double); any batch
+ * is processed, the workgroups loop over cells.  Nothing in that array needs
  * to start at zero.  All calls on one GPU share it: calls that overlap in
  * time on one GPU (other streams, other plans, other threads) race and give
  * wrong results; serialise them.  Requirements beyond lincoll_apply's: the

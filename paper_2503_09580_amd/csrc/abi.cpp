@@ -665,11 +665,24 @@ int lincoll_apply_noalloc(lincoll_plan_t pl, const void* h, void* out, int batch
   if (slot == 0 || slot > bytes) return LINCOLL_EINVAL;
   ApplyCtx c = apply_ctx(pl, h, out, batch, pl->stream);
   c.R = scr;
-  c.max_slots = (int)(bytes / slot);
-  c.fused_split = 1;   // one workgroup per cell: the array holds slots only
+  // The plan's split of this batch (as lincoll_apply takes it) where its
+  // slots and partial sums fit the array; else one workgroup per cell, the
+  // persistent workgroups capped to the slots the array holds.
+  const int n = pl->p.n, S = c.fused_split;
+  const size_t need =
+      S > 1 ? fused_split_scratch_bytes(
+                  n, fused_slots(n, batch * (S + fused_loss_item(n, batch, S, pl->cus)), pl->opt_per_cu, pl->cus),
+                  batch, S, pl->p.dtype)
+            : 0;
+  if (S > 1 && need <= bytes) {
+    c.max_slots = 0;
+  } else {
+    c.fused_split = 1;
+    c.max_slots = (int)(bytes / slot);
+  }
   if ((e = fused_apply(c))) return hip_fail(pl, e);
   pl->last_path = LINCOLL_PATH_FUSED;
-  pl->last_split = 1;
+  pl->last_split = c.fused_split;
   return LINCOLL_OK;
 }
 

@@ -126,11 +126,14 @@ def test_last_path_follows_every_entry_point():
     plan.apply(big, out)                     # records: 16 cells split
     split16 = plan.info("fused_split")
     assert split16 > 1
-    plan.apply_noalloc(big, out2)            # one workgroup per cell
-    assert plan.info("fused_split") == 1
-    plan.apply(big, out)                     # replays
+    plan.rk4(f, 1e-3, 1)                     # records an RK4 step on 2 cells: split further
+    assert plan.info("fused_split") > split16
+    plan.apply(big, out)                     # replays the recorded apply
+    assert plan.info("fused_split") == split16
+    plan.apply_noalloc(big, out2)            # the same split in the fixed array
     assert plan.info("fused_split") == split16
     torch.cuda.synchronize()
+    assert torch.equal(out.cpu(), out2.cpu())
 
 
 def test_graph_rerecords_after_reallocation():

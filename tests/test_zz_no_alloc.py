@@ -96,3 +96,64 @@ def test_noalloc_rejects_unsupported_plans():
     assert lib.lincoll_apply_noalloc(plan._h, px, py, 0) == lc.EINVAL       # empty
     plan.set_maxwellians(torch.tensor([[1, 0, 0, 0, 1.0]] * 3, dtype=torch.float64, device=DEV))
     assert lib.lincoll_apply_noalloc(plan._h, px, py, 2) == lc.ENOTREADY
+
+
+@pytest.mark.parametrize("n,big,small,dtype", [(32, 3, 1, "f32"), (32, 2, 1, "f64"), (16, 40, 5, "f64")])
+def test_noalloc_splits_small_batches_like_apply(n, big, small, dtype):
+    """Batches the plan splits over several workgroups per cell run split in
+    the array too (slots and partial sums fit): bitwise equal to
+    lincoll_apply, no allocation, on two calls in a row, the second
+    smaller."""
+    L, om = 8.0, 0.74
+    lib = lc.library()
+    h, params = mixed_inputs(n, L, big, seed=3600 + n)
+    plan = lc.Plan(n, L, om, dtype)
+    td = torch.float32 if dtype == "f32" else torch.float64
+    for B in (big, small):
+        print(f"noalloc split n={n} dtype={dtype} batch={B}", flush=True)
+        plan.set_maxwellians(dev(params[:B], torch.float64))
+        x = dev(h[:B], td)
+        ref = plan.apply(x)
+        split = plan.info("fused_split")
+        assert split > 1
+        out = torch.full_like(x, float("nan"))
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
+        try:
+            held = plan.info("device_bytes")
+            torch_held = torch.cuda.memory_allocated(DEV)
+            lib.lincoll_debug_fail_alloc(1)
+            try:
+                st = lib.lincoll_apply_noalloc(plan._h, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), B)
+            finally:
+                lib.lincoll_debug_fail_alloc(0)
+            assert st == lc.OK, lc.library().lincoll_strerror(st)
+            torch.cuda.synchronize()
+            assert plan.info("device_bytes") == held
+            assert torch.cuda.memory_allocated(DEV) == torch_held
+        finally:
+            gc.enable()
+        assert plan.info("fused_split") == split
+        assert torch.equal(out, ref), float((out - ref).abs().max())
+
+
+def test_noalloc_split_that_does_not_fit_runs_unsplit():
+    """64 cells at n = 32 split 3 ways with the loss item need 256 slots and
+    their partial sums, more than the array holds: one workgroup per cell,
+    agreeing with the split lincoll_apply to rounding."""
+    n, L, om, B = 32, 8.0, 0.74, 64
+    h, params = mixed_inputs(n, L, B, seed=3700)
+    plan = lc.Plan(n, L, om, "f32")
+    plan.set_maxwellians(dev(params, torch.float64))
+    x = dev(h, torch.float32)
+    ref = plan.apply(x)
+    assert plan.info("fused_split") > 1
+    out = torch.full_like(x, float("nan"))
+    plan.apply_noalloc(x, out)
+    torch.cuda.synchronize()
+    assert plan.info("fused_split") == 1
+    d = (out.double() - ref.double()).reshape(B, -1).abs().amax(dim=1)
+    r = ref.double().reshape(B, -1).abs().amax(dim=1)
+    assert float((d / r).max()) <= 5e-6
